@@ -1,0 +1,86 @@
+"""Seeded synthetic inputs for the kiFMM evaluate (shared by tests, smoke and bench).
+
+This module draws random numbers and nothing else: it holds none of the
+method's arithmetic.  The paper measures on two synthetic point distributions,
+uniform in a volume and uniform on the surface of the unit sphere (Section 5);
+the generators below produce those, at the sizes of the workloads this package
+is measured on.
+
+Points are drawn in float64 with numpy's PCG64 generator and rounded once to
+float32; the GPU path receives the float32 values and the FP64 reference
+receives their exact float64 promotion.
+"""
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    n: int                 # number of points (sources = targets)
+    distribution: str      # "cube" (uniform in [0,1)^3) or "sphere" (uniform on the unit sphere)
+    charges: str           # "uniform01", "uniform11" or "normal"
+    p: int                 # expansion order; n_surface = 6 (p-1)^2 + 2
+    depth: int             # uniform octree depth
+    nrhs: int
+    gradient: bool
+    seed: int              # points use seed, charges seed + 1000, weights seed + 2000
+
+    @property
+    def cube(self):
+        """Enclosing cube (centre, half-width) passed explicitly to the tree build."""
+        if self.distribution == "cube":
+            return (0.5, 0.5, 0.5), 0.5
+        return (0.0, 0.0, 0.0), 1.0
+
+
+WORKLOADS = {
+    "cube20k_p6_d3": Workload("cube20k_p6_d3", 20_000, "cube", "uniform01", 6, 3, 1, False, 1001),
+    "cube1m_p6_d5": Workload("cube1m_p6_d5", 1_000_000, "cube", "uniform01", 6, 5, 1, True, 1002),
+    "cube8m_p8_d6": Workload("cube8m_p8_d6", 8_000_000, "cube", "normal", 8, 6, 1, False, 1003),
+    "sphere4m_p6_d7_r32": Workload("sphere4m_p6_d7_r32", 4_000_000, "sphere", "normal", 6, 7, 32, False, 1004),
+    "cube2m_p7_d6": Workload("cube2m_p7_d6", 2_000_000, "cube", "uniform11", 7, 6, 1, True, 1005),
+}
+
+
+def points(distribution, n, seed):
+    """[n, 3] float32 points."""
+    rng = np.random.default_rng(seed)
+    if distribution == "cube":
+        x = rng.random((n, 3))
+    elif distribution == "sphere":
+        g = rng.standard_normal((n, 3))
+        x = g / np.linalg.norm(g, axis=1, keepdims=True)
+    else:
+        raise ValueError(f"unknown distribution {distribution!r}")
+    return x.astype(np.float32)
+
+
+def charges(kind, n, seed, nrhs=1):
+    """[n] (nrhs == 1) or [n, nrhs] float32 densities."""
+    rng = np.random.default_rng(seed)
+    shape = (n,) if nrhs == 1 else (n, nrhs)
+    if kind == "uniform01":
+        s = rng.random(shape)
+    elif kind == "uniform11":
+        s = rng.uniform(-1.0, 1.0, shape)
+    elif kind == "normal":
+        s = rng.standard_normal(shape)
+    else:
+        raise ValueError(f"unknown charge kind {kind!r}")
+    return s.astype(np.float32)
+
+
+def make(workload, n=None):
+    """(points [n,3] f32, charges [n] or [n,nrhs] f32) for a workload; `n` overrides its size."""
+    w = WORKLOADS[workload] if isinstance(workload, str) else workload
+    m = w.n if n is None else int(n)
+    return points(w.distribution, m, w.seed), charges(w.charges, m, w.seed + 1000, w.nrhs)
+
+
+def sample_indices(n, count, seed):
+    """Sorted distinct indices in [0, n) for sampled checks."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n, size=min(count, n), replace=False))
