@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Throughput of one kiFMM evaluate (3D Laplace) on one MI355X.
+
+A step is one full evaluate through the C ABI: permute, S2U (P2M), U2U, M2L
+compression and VLI, post + D2D, fused D2T + ULI (L2P + P2P) writing potentials
+and gradients in input order.  Inputs are resident in HBM before timing; tree
+build and operator precompute are setup and are not timed.
+
+Prints one JSON line: metric/value (Mpoints/s = N / time per evaluate), the
+roofline of the dominant kernel (M2L, FP32 matrix cores) measured with HIP
+events on the evaluate stream, the P2P kernel's FLOP rate, and the FP64 oracle
+timed on a bounded sample on the host CPU.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import tempfile
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 (vector and matrix), dense
+P2P_FLOPS_PER_PAIR = 20    # potential + gradient: 3 sub, 5 for r^2, 1 rsqrt, 2 potential, 1 + 8 gradient
+METRIC = "Mpoints/s per kiFMM evaluate at rel-L2<=1e-5; P2P/M2L % roofline"
+
+
+def kernel_source_hash():
+    with open(os.path.join(ROOT, "paper_2604_19243_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(workload, kernel):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, or None if stale/missing."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            entry = json.load(f)[kernel][workload]
+    except (OSError, KeyError, ValueError):
+        return None
+    if entry.get("kernels_hip_sha256_16") != kernel_source_hash():
+        return None
+    return float(entry["hbm_bytes_per_launch"])
+
+
+def cpu_baseline_worker(args):
+    """Runs in a child process with single-threaded BLAS: times the FP64 oracle on a sample."""
+    import numpy as np
+
+    from oracle import direct, fmm, operators, tree
+    from paper_2604_19243_amd import workloads
+
+    w = workloads.WORKLOADS[args.workload]
+    x32, s32 = workloads.make(w)
+    x, s = x32.astype(np.float64), s32.astype(np.float64)
+    c, r = w.cube
+    t = tree.Tree(x, w.depth, c, r)
+    ops = operators.Operators(w.p, eps_pinv=1e-7, m2l="compressed", eps_svd=1e-6)
+    L = w.depth
+    for l in range(2, L + 1):
+        ops.compression(t.radius(l))          # operator setup, not timed (as on the GPU)
+    s2 = s[:, None]
+    rng = np.random.default_rng(4000 + args.sample_seed)
+    all_leaves = list(t.leaf_points)
+    pick = rng.choice(len(all_leaves), size=min(args.sample_leaves, len(all_leaves)), replace=False)
+    leaves = [all_leaves[i] for i in pick]
+    needed = [set() for _ in range(L + 1)]
+    for b in leaves:
+        for l in range(L + 1):
+            needed[l].add((b[0] >> (L - l), b[1] >> (L - l), b[2] >> (L - l)))
+    needed = [sorted(v) for v in needed]
+
+    t0 = time.perf_counter()
+    u = fmm.upward_pass(t, ops, s2)
+    t1 = time.perf_counter()
+    d = fmm.downward_pass(t, ops, u, needed)
+    t2 = time.perf_counter()
+    phi, _ = fmm.leaf_pass(t, ops, s2, d, leaves, w.gradient)
+    t3 = time.perf_counter()
+    boxes_all = sum(len(t.boxes[l]) for l in range(2, L + 1))
+    boxes_sampled = sum(len(needed[l]) for l in range(2, L + 1))
+    t_full = (t1 - t0) + (t2 - t1) * boxes_all / boxes_sampled + (t3 - t2) * len(all_leaves) / len(leaves)
+
+    # accuracy of the GPU run: oracle direct sum at sampled targets
+    gpu = np.load(args.gpu_sample)
+    idx, gphi = gpu["idx"], gpu["phi"]
+    ref = direct.potential(x[idx], x, s)
+    out = {
+        "value": w.n / t_full / 1e6, "unit": "Mpoints/s", "cores": 1, "kind": "oracle",
+        "sample": (f"FP64 NumPy oracle, single thread: full upward pass ({t1 - t0:.2f} s) timed; downward pass "
+                   f"timed on the {boxes_sampled} ancestors of {len(leaves)} random leaves ({t2 - t1:.2f} s) and "
+                   f"leaf pass on those leaves ({t3 - t2:.2f} s), each scaled by box/leaf counts to the full "
+                   f"workload; extrapolated evaluate {t_full:.1f} s"),
+        "seconds_measured": t3 - t0, "seconds_extrapolated": t_full,
+        "rel_l2_vs_direct_sampled": direct.rel_l2(gphi, ref), "direct_sample_targets": int(len(idx)),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cube1m_p6_d5")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sample-leaves", type=int, default=24)
+    ap.add_argument("--sample-seed", type=int, default=2)
+    ap.add_argument("--cpu-baseline-worker", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--gpu-sample", default=None, help=argparse.SUPPRESS)
+    args = ap.parse_args()
+
+    if args.cpu_baseline_worker:
+        cpu_baseline_worker(args)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2604_19243_amd import kifmm, workloads
+
+    w = workloads.WORKLOADS[args.workload]
+    print(f"# bench {w.name}: n={w.n} depth={w.depth} p={w.p} grad={w.gradient}", file=sys.stderr, flush=True)
+    x, s = workloads.make(w)
+    cube = w.cube[0] + (w.cube[1],)
+    t_setup = time.perf_counter()
+    f = kifmm.FMM(x, w.depth, w.p, cube=cube, eps_pinv=1e-7, eps_svd=1e-6)
+    t_setup = time.perf_counter() - t_setup
+    info = kifmm.kifmm_ops_get_info(f.ops)
+    stats = kifmm.kifmm_plan_get_stats(f.plan)
+    k, n = info["rank_m2l"], info["n_surface"]
+    print(f"# setup {t_setup:.1f} s, k={k}, n={n}, stats={stats}", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    charges = torch.from_numpy(s).to(dev)
+    pot = torch.empty(w.n, device=dev)
+    grad = torch.empty(w.n, 3, device=dev) if w.gradient else None
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        f.evaluate(charges, pot, grad, stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+
+    kifmm.kifmm_plan_set_timing(f.plan, True)
+    kifmm.kifmm_plan_get_stage_times(f.plan, reset=True)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(args.steps):
+        f.evaluate(charges, pot, grad, stream=stream.cuda_stream)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / args.steps
+    stages = kifmm.kifmm_plan_get_stage_times(f.plan, reset=True)
+    kifmm.kifmm_plan_set_timing(f.plan, False)
+    print(f"# {ms:.3f} ms/evaluate; stages (ms/call): "
+          + ", ".join(f"{k_}={v[0] / max(v[1], 1):.3f}" for k_, v in stages.items()), file=sys.stderr, flush=True)
+
+    # M2L (dominant kernel): 2 k^2 FLOP per (target, source) V-list pair.
+    m2l_ms = stages["m2l"][0] / max(stages["m2l"][1], 1)
+    m2l_flop = 2.0 * k * k * stats["m2l_pairs"]
+    m2l_tflops = m2l_flop / (m2l_ms * 1e-3) / 1e12
+    traffic = load_traffic(w.name, "k_m2l")
+    # P2P (fused D2T): 20 FLOP per U-list pair and per (target, downward-equivalent point) pair.
+    p2p_ms = stages["p2p"][0] / max(stages["p2p"][1], 1)
+    p2p_pairs = stats["p2p_pairs"] + w.n * n * (1 if w.depth >= 2 else 0)
+    p2p_tflops = P2P_FLOPS_PER_PAIR * p2p_pairs / (p2p_ms * 1e-3) / 1e12
+
+    result = {
+        "metric": METRIC,
+        "value": w.n / (ms * 1e-3) / 1e6,
+        "unit": "Mpoints/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "n_points": w.n, "distribution": w.distribution, "charges": w.charges,
+                   "p": w.p, "n_surface": n, "m2l_rank": k, "depth": w.depth, "nrhs": w.nrhs,
+                   "outputs": "potential+gradient" if w.gradient else "potential", "parallelism": "single-gpu"},
+        "roofline": {"kernel": "k_m2l", "bound": "mfma", "achieved": m2l_tflops, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": m2l_tflops / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "ms_per_launch": m2l_ms, "algorithmic_flop_per_launch": m2l_flop,
+                     "v_list_pairs": stats["m2l_pairs"]},
+        "p2p": {"kernel": "k_p2p", "bound": "alu", "achieved": p2p_tflops, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": p2p_tflops / PEAK_FP32_TFLOPS, "ms_per_launch": p2p_ms,
+                "pairs_per_launch": p2p_pairs, "flop_per_pair": P2P_FLOPS_PER_PAIR},
+        "stages_ms": {k_: v[0] / max(v[1], 1) for k_, v in stages.items()},
+        "setup_s": t_setup,
+        "cpu_baseline": None,
+    }
+
+    if not args.no_cpu_baseline:
+        idx = np.sort(np.random.default_rng(4002).choice(w.n, size=min(256, w.n), replace=False))
+        phi = pot.cpu().numpy()[idx].astype(np.float64)
+        with tempfile.TemporaryDirectory() as tmp:
+            path = os.path.join(tmp, "gpu_sample.npz")
+            np.savez(path, idx=idx, phi=phi)
+            env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+            print("# cpu baseline (oracle, 1 thread)...", file=sys.stderr, flush=True)
+            r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker",
+                                "--workload", w.name, "--sample-leaves", str(args.sample_leaves),
+                                "--sample-seed", str(args.sample_seed), "--gpu-sample", path],
+                               capture_output=True, text=True, env=env, timeout=900)
+            if r.returncode == 0:
+                cb = json.loads(r.stdout.strip().splitlines()[-1])
+                result["rel_l2_vs_direct_sampled"] = cb.pop("rel_l2_vs_direct_sampled")
+                result["direct_sample_targets"] = cb.pop("direct_sample_targets")
+                result["cpu_baseline"] = cb
+            else:
+                print(r.stderr[-2000:], file=sys.stderr, flush=True)
+    f.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * kifmm_mi355x.h -- C ABI of the MI355X kernel-independent FMM evaluate for the
+ * 3D Laplace kernel K(x, y) = 1 / |x - y| (eq. (2), Section 1).
+ *
+ * The library computes, for N points that are both sources and targets
+ * (Section 2.3), the potentials f(x_i) = sum_j K(x_i, x_j) s_j of eq. (1) and
+ * their gradients, approximated by the shared-memory FMM of Algorithm 1
+ * (Section 2.1) on a uniform octree: S2U/P2M, U2U/M2M, VLI/M2L, D2D/L2L,
+ * D2T/L2P and ULI/P2P, with the operators of Table 1.  Pairs at zero distance
+ * contribute nothing.
+ *
+ * Three objects, each created once and reused (Section 3 notes that a set-up
+ * tree serves new source data):
+ *   kifmm_tree  -- uniform Morton-ordered octree over the points (host build).
+ *   kifmm_ops   -- FP64 operator precompute for an expansion order p.
+ *   kifmm_plan  -- tree + operators resident on one GPU, with all device
+ *                  workspace allocated; evaluate() runs the FMM on a stream.
+ *
+ * Conventions for every entry point:
+ *   - Return value is a kifmm_status; KIFMM_OK is 0, errors are negative.  No
+ *     entry point aborts or lets a C++ exception escape.  On error a message
+ *     is available from kifmm_last_error() (thread-local) and no device work
+ *     has been enqueued.
+ *   - Arguments are validated on the host before any work starts.
+ *   - "host" pointers are CPU memory, "device" pointers are HIP device memory
+ *     on the plan's device.  The caller owns every pointer it passes; the
+ *     library never frees or retains caller memory beyond the call (for
+ *     kifmm_evaluate: beyond the point where the stream reaches its last
+ *     kernel).
+ *   - All per-point arrays are in the caller's input order.
+ *   - Objects are not thread-safe; distinct plans may run concurrently on
+ *     distinct streams.  A plan holds references to its tree and operators, so
+ *     they may be destroyed in any order.
+ */
+#ifndef KIFMM_MI355X_H
+#define KIFMM_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KIFMM_ABI_VERSION 1
+#define KIFMM_MAX_DEPTH 10
+
+typedef enum {
+  KIFMM_OK = 0,
+  KIFMM_E_INVALID = -1, /* an argument is out of range, null or non-finite */
+  KIFMM_E_NOMEM = -2,   /* a host or device allocation failed */
+  KIFMM_E_DEVICE = -3,  /* the HIP runtime reported an error */
+  KIFMM_E_NUMERIC = -4, /* the operator precompute produced a non-finite value */
+  KIFMM_E_STATE = -5    /* the object is not in a state that allows the call */
+} kifmm_status;
+
+typedef struct kifmm_tree_s* kifmm_tree;
+typedef struct kifmm_ops_s* kifmm_ops;
+typedef struct kifmm_plan_s* kifmm_plan;
+
+/* ABI version of the loaded library (KIFMM_ABI_VERSION it was built with). */
+int kifmm_abi_version(void);
+
+/* Message of the last failed call on this thread; valid until the next call. */
+const char* kifmm_last_error(void);
+
+/* ---------------------------------------------------------------- tree --- */
+
+typedef struct {
+  int64_t n_points;
+  int32_t depth;                    /* leaf level L */
+  int32_t max_leaf_points;          /* largest leaf occupancy */
+  int64_t nonempty_leaves;
+  int64_t nonempty_boxes[KIFMM_MAX_DEPTH + 1]; /* per level 0..L */
+  double center[3];                 /* enclosing cube centre */
+  double half_width;                /* enclosing cube half-width R0 */
+} kifmm_tree_info;
+
+/*
+ * Build the uniform octree of Section 2.1: the enclosing cube is split
+ * recursively into octants down to level `depth`, and points are ordered by
+ * the Morton key of their leaf (three bits per level, Section 2.1), ties kept
+ * in input order.
+ *
+ *   xyz    host, [n][3] float, point coordinates (finite), read during the call.
+ *   n      number of points, 1 <= n < 2^31.
+ *   depth  leaf level L, 0 <= L <= KIFMM_MAX_DEPTH.
+ *   cube   host, {cx, cy, cz, half_width} in double, or NULL.  NULL encloses
+ *          the points in a cube centred on the midpoint of their per-axis
+ *          range with half-width 0.5 * (max range) * (1 + 1e-6).  Points
+ *          outside a given cube are clamped into its boundary leaves.
+ *   out    receives the tree handle.
+ *
+ * Leaf grid coordinates are i_d = floor((x_d - (c_d - R0)) / h), h = 2 R0 / 2^L,
+ * computed in double precision and clamped to [0, 2^L - 1].
+ */
+kifmm_status kifmm_tree_build(const float* xyz, int64_t n, int depth, const double* cube, kifmm_tree* out);
+kifmm_status kifmm_tree_get_info(kifmm_tree tree, kifmm_tree_info* out);
+/* host, [n] int64: input index of the point at each sorted position. */
+kifmm_status kifmm_tree_get_order(kifmm_tree tree, int64_t* order);
+/* host, [n][3] int32: leaf grid coordinates of each point, input order. */
+kifmm_status kifmm_tree_get_leaf_coords(kifmm_tree tree, int32_t* ijk);
+kifmm_status kifmm_tree_destroy(kifmm_tree tree);
+
+/* ----------------------------------------------------------- operators --- */
+
+typedef struct {
+  int32_t p;            /* expansion order */
+  int32_t n_surface;    /* 6 (p - 1)^2 + 2 points per check/equivalent surface (Section 4) */
+  int32_t rank_m2l;     /* k, rank of the compressed U2D (M2L) operators */
+  int32_t rank_c2e;     /* kept singular values of the check-to-equivalent pseudo-inverse */
+  int32_t n_m2l_offsets;/* 316 distinct V-list offsets */
+  double eps_pinv;
+  double eps_svd;
+  double alpha_inner;   /* 1.05: upward-equivalent and downward-check surface radius factor */
+  double alpha_outer;   /* 2.95: upward-check and downward-equivalent surface radius factor */
+} kifmm_ops_info;
+
+/*
+ * Precompute, in FP64 on the host, the Table 1 operators for expansion order
+ * p on a box of unit half-width (all are scale-free for the Laplace kernel
+ * except the leaf S2U factor, scaled at evaluate time):
+ *   - the surface S_p: grid points of {-1, .., 1}^3 with p per edge on the
+ *     cube boundary, n = 6 (p - 1)^2 + 2 of them;
+ *   - check-to-equivalent pseudo-inverses by truncated SVD (relative cutoff
+ *     eps_pinv, never splitting a cluster of equal singular values), kept as
+ *     two factors for S2U;
+ *   - U2U (M2M) and D2D (L2L) operators for the 8 child positions, each a
+ *     product formed in FP64 and rounded once;
+ *   - the U2D (M2L) operators of the 316 V-list offsets compressed with a
+ *     shared basis (the "BLAS M2L" that exploits the translational symmetry
+ *     of Section 2.2): K_t ~ U_k C_t V_k^T, k from eps_svd (or `rank` when
+ *     rank > 0), extended to the end of a singular-value cluster.
+ *
+ *   p         2 <= p <= 12.
+ *   eps_pinv  in (0, 1): relative pseudo-inverse cutoff (1e-7 suits FP32 use).
+ *   eps_svd   in (0, 1): relative M2L compression cutoff; ignored if rank > 0.
+ *   rank      0 to use eps_svd, else 1 <= rank <= n.
+ */
+kifmm_status kifmm_ops_precompute(int p, double eps_pinv, double eps_svd, int rank, kifmm_ops* out);
+kifmm_status kifmm_ops_get_info(kifmm_ops ops, kifmm_ops_info* out);
+
+/* Operator inspection (host FP64 copies, row-major), for tests:
+ *   KIFMM_OP_SURFACE     [n][3]            index ignored
+ *   KIFMM_OP_UC2E        [n][n]            pinv(K(UC, UE)) at unit half-width
+ *   KIFMM_OP_DC2E        [n][n]            pinv(K(DC, DE)) at unit half-width
+ *   KIFMM_OP_M2M         [n][n]            child position index 0..7 -> parent
+ *   KIFMM_OP_L2L         [n][n]            parent -> child position index 0..7
+ *   KIFMM_OP_M2L_U       [n][k]            U_k
+ *   KIFMM_OP_M2L_V       [n][k]            V_k
+ *   KIFMM_OP_M2L_CORE    [k][k]            C_t for offset index 0..315
+ *   KIFMM_OP_M2L_OFFSET  [3] (as doubles)  integer offset t of index 0..315
+ *   KIFMM_OP_M2L_POST    [n][k]            DC2E U_k
+ * `capacity` is the number of doubles `out` can hold. */
+enum {
+  KIFMM_OP_SURFACE = 0, KIFMM_OP_UC2E = 1, KIFMM_OP_DC2E = 2, KIFMM_OP_M2M = 3, KIFMM_OP_L2L = 4,
+  KIFMM_OP_M2L_U = 5, KIFMM_OP_M2L_V = 6, KIFMM_OP_M2L_CORE = 7, KIFMM_OP_M2L_OFFSET = 8,
+  KIFMM_OP_M2L_POST = 9
+};
+kifmm_status kifmm_ops_get_matrix(kifmm_ops ops, int which, int index, double* out, int64_t capacity);
+kifmm_status kifmm_ops_destroy(kifmm_ops ops);
+
+/* ---------------------------------------------------------------- plan --- */
+
+/* Flags of kifmm_plan_create: which outputs evaluate may be asked for. */
+#define KIFMM_POTENTIAL 1u
+#define KIFMM_GRADIENT 2u
+
+/*
+ * Place a tree and its operators on HIP device `device`: uploads the sorted
+ * points, interaction tables and FP32 operators, and allocates all workspace,
+ * so that kifmm_evaluate allocates nothing and never synchronises the host.
+ * Blocks until the uploads are complete.
+ */
+kifmm_status kifmm_plan_create(kifmm_tree tree, kifmm_ops ops, unsigned flags, int device, kifmm_plan* out);
+
+/*
+ * One FMM evaluate (Algorithm 1) on `stream` (a hipStream_t; NULL = the null
+ * stream), asynchronous with respect to the host:
+ *
+ *   charges    device, [n] float, densities s in input order.
+ *   potential  device, [n] float, receives f in input order; or NULL.
+ *   gradient   device, [n][3] float, receives grad f in input order; or NULL
+ *              (requires KIFMM_GRADIENT at plan creation).
+ *
+ * At least one output must be non-NULL.  The buffers must stay valid until
+ * the stream has passed this call's last kernel; the plan may not be used on
+ * two streams at once.  Arithmetic is FP32 (operators rounded once from FP64).
+ */
+kifmm_status kifmm_evaluate(kifmm_plan plan, const float* charges, float* potential, float* gradient,
+                            void* stream);
+kifmm_status kifmm_plan_destroy(kifmm_plan plan);
+
+/* ------------------------------------------------- inspection, timing --- */
+
+/* Stages of one evaluate, in launch order. */
+enum {
+  KIFMM_STAGE_PERMUTE = 0, /* gather charges into sorted order */
+  KIFMM_STAGE_P2M = 1,     /* leaf sources -> upward-check field (S2U, first half) */
+  KIFMM_STAGE_UC2E = 2,    /* upward-check field -> upward density, two factors */
+  KIFMM_STAGE_M2M = 3,     /* U2U, all levels */
+  KIFMM_STAGE_COMPRESS = 4,/* u -> V_k^T u, levels 2..L */
+  KIFMM_STAGE_M2L = 5,     /* compressed VLI over all levels */
+  KIFMM_STAGE_L2L = 6,     /* post (DC2E U_k) and D2D, levels 2..L */
+  KIFMM_STAGE_P2P = 7,     /* fused D2T + ULI at the leaves, then un-permute */
+  KIFMM_N_STAGES = 8
+};
+
+/* When enabled, evaluate records HIP events around every stage on its stream
+ * and kifmm_plan_get_stage_times returns the summed milliseconds and call counts
+ * since the last reset (it synchronises on the recorded events). */
+kifmm_status kifmm_plan_set_timing(kifmm_plan plan, int enable);
+kifmm_status kifmm_plan_get_stage_times(kifmm_plan plan, double* ms, int64_t* counts, int reset);
+
+/* Plan shape: box counts and work counts used for roofline accounting.
+ *   stats[0] = leaf-level pairs (target point, source point) of the U-list sum
+ *   stats[1] = V-list (target box, source box) pairs over levels 2..L
+ *   stats[2] = leaf slots, stats[3] = M2L target boxes, stats[4] = k, stats[5] = n */
+kifmm_status kifmm_plan_get_stats(kifmm_plan plan, int64_t* stats, int count);
+
+/* Copy a level's densities to the host after the stream is idle, as float in
+ * the same order as the tree's non-empty boxes at that level (Morton order):
+ *   kind 0 = u (upward-equivalent, [boxes][n]), 1 = d (downward-equivalent, [boxes][n]).
+ * Synchronises the device. */
+kifmm_status kifmm_plan_read_density(kifmm_plan plan, int kind, int level, float* host_out, int64_t capacity);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KIFMM_MI355X_H */

@@ -1,0 +1,489 @@
+// Device plan of the kiFMM evaluate: data layout in HBM, interaction tables,
+// and the launch sequence of Algorithm 1.
+//
+// Box layout ("slots").  Level 0 has one slot.  At level l >= 1 the slots are
+// 8 per non-empty box of level l-1, in Morton order: the child at position o
+// (x bit 0, y bit 1, z bit 2) of the j-th non-empty parent is slot 8 j + o.
+// Siblings are therefore contiguous, so U2U reads and D2D writes the eight
+// children of a parent as one row, and slot order is Morton order.  Slots of
+// empty boxes hold zeros.  Per-box vectors of levels 2..L are stored in one
+// array per kind (u, d: row stride nst = n rounded up to 4; uhat, chat: kst),
+// indexed by base[l] + slot.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace kifmm {
+
+namespace {
+
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  (void)hipGetLastError();
+  fail(e == hipErrorOutOfMemory ? KIFMM_E_NOMEM : KIFMM_E_DEVICE,
+       std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class T>
+T* dev_upload(std::vector<void*>& owned, const T* host, size_t count, const char* what) {
+  void* p = nullptr;
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  hip_check(hipMalloc(&p, bytes), what);
+  owned.push_back(p);
+  if (host && count) hip_check(hipMemcpy(p, host, count * sizeof(T), hipMemcpyHostToDevice), what);
+  else hip_check(hipMemset(p, 0, bytes), what);
+  return static_cast<T*>(p);
+}
+
+// The 189 V-list offsets t = target - source available to a box at sibling
+// position `oct`, as indices into the ops offset table (Table 1: children of the
+// parent's colleagues that are not adjacent).
+std::vector<int> offsets_of_octant(const Ops& ops, int oct) {
+  std::vector<int> out;
+  const int b[3] = {oct & 1, (oct >> 1) & 1, (oct >> 2) & 1};
+  for (int t = 0; t < kNumOffsets; ++t) {
+    bool ok = true;
+    for (int d = 0; d < 3; ++d) {
+      const int a = b[d] - ops.offsets[3 * t + d];  // source position relative to the target's parent corner
+      const int pa = a >= 0 ? a / 2 : -((1 - a) / 2);  // floor(a / 2)
+      ok = ok && pa >= -1 && pa <= 1;
+    }
+    if (ok) out.push_back(t);
+  }
+  return out;
+}
+
+}  // namespace
+
+Plan::~Plan() {
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(device);
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  for (void* p : owned) (void)hipFree(p);
+  (void)hipSetDevice(prev);
+  release(tree);
+  release(ops);
+}
+
+Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
+  require(tree && ops, "null tree or ops");
+  require((flags & ~(KIFMM_POTENTIAL | KIFMM_GRADIENT)) == 0 && flags != 0, "flags must be POTENTIAL and/or GRADIENT");
+  int ndev = 0;
+  hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+  require(device >= 0 && device < ndev, "device index out of range");
+  int prev = 0;
+  hip_check(hipGetDevice(&prev), "hipGetDevice");
+  hip_check(hipSetDevice(device), "hipSetDevice");
+
+  Plan* P = new Plan();
+  P->device = device;
+  tree->refs.fetch_add(1);
+  ops->refs.fetch_add(1);
+  P->tree = tree;
+  P->ops = ops;
+  try {
+    const Tree& T = *tree;
+    const Ops& O = *ops;
+    const int L = T.depth;
+    P->flags = flags;
+    P->L = L;
+    P->N = T.n;
+    P->far = L >= 2;
+    P->n = O.n;
+    P->nst = round_up(O.n, 4);
+    P->k = O.k;
+    P->kst = round_up(O.k, 4);
+    P->kc = O.kc;
+    P->kcst = round_up(O.kc, 4);
+    auto& own = P->owned;
+
+    // Slots per level and the slot of every non-empty box.
+    std::vector<std::vector<int>> slot_of(L + 1);  // [level][compact index] -> local slot
+    P->slots.assign(L + 1, 0);
+    for (int l = 0; l <= L; ++l) {
+      const auto& keys = T.keys[l];
+      slot_of[l].resize(keys.size());
+      if (l == 0) {
+        P->slots[0] = 1;
+        slot_of[0][0] = 0;
+        continue;
+      }
+      P->slots[l] = 8 * (int64_t)T.keys[l - 1].size();
+      int64_t parent = 0;
+      for (size_t i = 0; i < keys.size(); ++i) {
+        while (T.keys[l - 1][parent] != (keys[i] >> 3)) ++parent;
+        slot_of[l][i] = (int)(8 * parent + (keys[i] & 7));
+      }
+    }
+    const int64_t SL = P->slots[L];
+    const int64_t NBL = (int64_t)T.keys[L].size();
+    P->n_leaves = NBL;
+
+    // Sorted points (xyz; the charge is written per evaluate) and order.
+    std::vector<float> pts4(4 * T.n);
+    std::vector<int> order(T.n);
+    for (int64_t s = 0; s < T.n; ++s) {
+      const int64_t i = T.order[s];
+      order[s] = (int)i;
+      for (int d = 0; d < 3; ++d) pts4[4 * s + d] = T.xyz[3 * i + d];
+      pts4[4 * s + 3] = 0.f;
+    }
+    P->d_pts = reinterpret_cast<float4*>(dev_upload(own, pts4.data(), pts4.size(), "points"));
+    P->d_order = dev_upload(own, order.data(), order.size(), "order");
+
+    // Leaf slots: CSR point ranges (empty slots have empty ranges) and centres as
+    // two floats per coordinate (c = hi + lo), so that kernels can form
+    // centre-relative coordinates with rounding relative to the box size.
+    std::vector<int> start(SL + 1, 0), leaves(NBL);
+    std::vector<float> centers(8 * SL, 0.f);
+    const double rL = T.radius(L);
+    {
+      std::vector<int> cnt(SL, 0);
+      for (int64_t i = 0; i < NBL; ++i) {
+        const int s = slot_of[L][i];
+        leaves[i] = s;
+        cnt[s] = (int)(T.leaf_start[i + 1] - T.leaf_start[i]);
+      }
+      for (int64_t s = 0; s < SL; ++s) {
+        start[s + 1] = start[s] + cnt[s];
+        // every slot's centre, empty ones included (a slot is a child position of a known parent)
+        int32_t pc[3] = {0, 0, 0};
+        if (L > 0) morton_decode(T.keys[L - 1][s / 8], L - 1, pc);
+        for (int d = 0; d < 3; ++d) {
+          const int c = L > 0 ? 2 * pc[d] + (int)((s % 8) >> d & 1) : 0;
+          const double v = (T.center[d] - T.half) + (2.0 * c + 1.0) * rL;
+          const float hi = (float)v;
+          centers[8 * s + d] = hi;
+          centers[8 * s + 4 + d] = (float)(v - (double)hi);
+        }
+        centers[8 * s + 3] = (float)rL;
+      }
+    }
+    P->d_start = dev_upload(own, start.data(), start.size(), "leaf ranges");
+    P->d_leaves = dev_upload(own, leaves.data(), leaves.size(), "leaf list");
+    P->d_centers = reinterpret_cast<float4*>(dev_upload(own, centers.data(), centers.size(), "leaf centres"));
+
+    // Leaf groups (the children of each non-empty parent, or the root alone when
+    // L = 0) and the 4 x 4 x 4 block of leaves around each group that holds the
+    // U lists of its members.
+    const int64_t m = 1ll << L;
+    const int64_t ngroups = L > 0 ? (int64_t)T.keys[L - 1].size() : 1;
+    P->n_groups = ngroups;
+    P->group_slots = L > 0 ? 8 : 1;
+    std::vector<int> blk(64 * ngroups, -1);
+    for (int64_t g = 0; g < ngroups; ++g) {
+      int32_t pc[3] = {0, 0, 0};
+      if (L > 0) morton_decode(T.keys[L - 1][g], L - 1, pc);
+      for (int bz = 0; bz < 4; ++bz)
+        for (int by = 0; by < 4; ++by)
+          for (int bx = 0; bx < 4; ++bx) {
+            const int64_t x = 2 * pc[0] - 1 + bx, y = 2 * pc[1] - 1 + by, z = 2 * pc[2] - 1 + bz;
+            if (x < 0 || y < 0 || z < 0 || x >= m || y >= m || z >= m) continue;
+            const int64_t j = T.find(L, morton_encode((uint32_t)x, (uint32_t)y, (uint32_t)z, L));
+            if (j >= 0) blk[64 * g + bx + 4 * by + 16 * bz] = slot_of[L][j];
+          }
+    }
+    P->d_blk = dev_upload(own, blk.data(), blk.size(), "leaf blocks");
+    // U-list pair count (target, source), for throughput accounting.
+    int64_t pairs = 0;
+    for (int64_t i = 0; i < NBL; ++i) {
+      int32_t c[3];
+      morton_decode(T.keys[L][i], L, c);
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int64_t x = c[0] + dx, y = c[1] + dy, z = c[2] + dz;
+            if (x < 0 || y < 0 || z < 0 || x >= m || y >= m || z >= m) continue;
+            const int64_t j = T.find(L, morton_encode((uint32_t)x, (uint32_t)y, (uint32_t)z, L));
+            if (j >= 0) pairs += (T.leaf_start[i + 1] - T.leaf_start[i]) * (T.leaf_start[j + 1] - T.leaf_start[j]);
+          }
+    }
+    P->p2p_pairs = pairs;
+
+    // Surface and operators (rounded once to FP32, zero-padded).
+    std::vector<float> surf(3 * O.n);
+    for (int i = 0; i < 3 * O.n; ++i) surf[i] = (float)O.surf[i];
+    P->d_surf = dev_upload(own, surf.data(), surf.size(), "surface");
+
+    if (P->far) {
+      require(O.n <= 304, "the leaf kernel supports p <= 8 when the tree has a far field");
+      const int n = O.n, nst = P->nst, k = O.k, kst = P->kst, kc = O.kc, kcst = P->kcst;
+      // Level bases of the per-box arrays (levels 2..L).
+      P->base.assign(L + 1, 0);
+      int64_t total = 0;
+      for (int l = 2; l <= L; ++l) {
+        P->base[l] = total;
+        total += P->slots[l];
+      }
+      P->total_slots = total;
+      P->d_q = dev_upload<float>(own, nullptr, (size_t)SL * nst, "check field");
+      P->d_t = dev_upload<float>(own, nullptr, (size_t)SL * kcst, "check coefficients");
+      P->d_u = dev_upload<float>(own, nullptr, (size_t)total * nst, "u");
+      P->d_d = dev_upload<float>(own, nullptr, (size_t)total * nst, "d");
+      P->d_uhat = dev_upload<float>(own, nullptr, (size_t)total * kst, "uhat");
+      P->d_chat = dev_upload<float>(own, nullptr, (size_t)total * kst, "chat");
+      P->d_zero = dev_upload<float>(own, nullptr, (size_t)kst + nst, "zero row");
+
+      auto pad_rows = [](int rows) { return round_up(rows, 64); };
+      // f1: [kc][n] -> W [pad(kcst)][nst]
+      std::vector<float> w1((size_t)pad_rows(kcst) * nst, 0.f);
+      for (int c = 0; c < kc; ++c)
+        for (int i = 0; i < n; ++i) w1[(size_t)c * nst + i] = (float)O.f1[(size_t)c * n + i];
+      P->d_f1 = dev_upload(own, w1.data(), w1.size(), "f1");
+      // f2: [n][kc] -> W [pad(nst)][kcst]
+      std::vector<float> w2((size_t)pad_rows(nst) * kcst, 0.f);
+      for (int i = 0; i < n; ++i)
+        for (int c = 0; c < kc; ++c) w2[(size_t)i * kcst + c] = (float)O.f2[(size_t)i * kc + c];
+      P->d_f2 = dev_upload(own, w2.data(), w2.size(), "f2");
+      // U2U: W[i][oc * nst + c] = M2M_oc[i][c]
+      std::vector<float> wm((size_t)pad_rows(nst) * 8 * nst, 0.f);
+      for (int oc = 0; oc < 8; ++oc)
+        for (int i = 0; i < n; ++i)
+          for (int c = 0; c < n; ++c)
+            wm[(size_t)i * 8 * nst + oc * nst + c] = (float)O.m2m[((size_t)oc * n + i) * n + c];
+      P->d_m2m = dev_upload(own, wm.data(), wm.size(), "m2m");
+      // compression: W[c][i] = V_k[i][c]
+      std::vector<float> wv((size_t)pad_rows(kst) * nst, 0.f);
+      for (int c = 0; c < k; ++c)
+        for (int i = 0; i < n; ++i) wv[(size_t)c * nst + i] = (float)O.mv[(size_t)i * k + c];
+      P->d_vt = dev_upload(own, wv.data(), wv.size(), "V_k^T");
+      // post: W[i][c] = (DC2E U_k)[i][c]
+      std::vector<float> wp((size_t)pad_rows(nst) * kst, 0.f);
+      for (int i = 0; i < n; ++i)
+        for (int c = 0; c < k; ++c) wp[(size_t)i * kst + c] = (float)O.post[(size_t)i * k + c];
+      P->d_post = dev_upload(own, wp.data(), wp.size(), "post");
+      // D2D: W[oc * nst + i][c] = L2L_oc[i][c]
+      std::vector<float> wl((size_t)pad_rows(8 * nst) * nst, 0.f);
+      for (int oc = 0; oc < 8; ++oc)
+        for (int i = 0; i < n; ++i)
+          for (int c = 0; c < n; ++c)
+            wl[((size_t)oc * nst + i) * nst + c] = (float)O.l2l[((size_t)oc * n + i) * n + c];
+      P->d_l2l = dev_upload(own, wl.data(), wl.size(), "l2l");
+      // M2L cores: [316][core_rows][kst], row blocks of 16 split over two waves.
+      const int blocks = kst / 16 + (kst % 16 ? 1 : 0);
+      P->m2l_rb = (blocks + 1) / 2;
+      require(P->m2l_rb <= 10, "M2L rank too large for the M2L kernel (k <= 320)");
+      P->core_rows = 32 * P->m2l_rb;
+      std::vector<float> wc((size_t)kNumOffsets * P->core_rows * kst, 0.f);
+      for (int t = 0; t < kNumOffsets; ++t)
+        for (int a = 0; a < k; ++a)
+          for (int b = 0; b < k; ++b)
+            wc[((size_t)t * P->core_rows + a) * kst + b] = (float)O.cores[((size_t)t * k + a) * k + b];
+      P->d_cores = dev_upload(own, wc.data(), wc.size(), "m2l cores");
+
+      // Per-level lists of non-empty boxes' slots (U2U scatter, D2D gather).
+      P->d_nbslot.assign(L + 1, nullptr);
+      for (int l = 2; l <= L; ++l)
+        P->d_nbslot[l] = dev_upload(own, slot_of[l].data(), slot_of[l].size(), "box slots");
+
+      // V lists: per (level, sibling position) group, targets and a [189][T] source table.
+      std::vector<int> offidx(8 * kOffsetsPerOctant);
+      std::vector<std::vector<int>> oct_offs(8);
+      for (int oc = 0; oc < 8; ++oc) {
+        oct_offs[oc] = offsets_of_octant(O, oc);
+        require((int)oct_offs[oc].size() == kOffsetsPerOctant, "internal: V-list offsets per position != 189");
+        std::copy(oct_offs[oc].begin(), oct_offs[oc].end(), offidx.begin() + oc * kOffsetsPerOctant);
+      }
+      P->d_offidx = dev_upload(own, offidx.data(), offidx.size(), "offset index");
+      std::vector<int> tgt, vsrc;
+      std::vector<M2LTile> tiles;
+      std::vector<std::vector<M2LTile>> group_tiles;
+      int64_t vpairs = 0;
+      for (int l = L; l >= 2; --l) {
+        const int64_t ml = 1ll << l;
+        std::vector<std::vector<int>> by_oct(8);
+        for (size_t i = 0; i < T.keys[l].size(); ++i) by_oct[T.keys[l][i] & 7].push_back((int)i);
+        std::vector<std::vector<M2LTile>> lt(8);
+        size_t most = 0;
+        for (int oc = 0; oc < 8; ++oc) {
+          const auto& members = by_oct[oc];
+          const int cnt = (int)members.size();
+          if (!cnt) continue;
+          const int tgt_base = (int)tgt.size();
+          const long long vs_base = (long long)vsrc.size();
+          for (int i : members) tgt.push_back((int)(P->base[l] + slot_of[l][i]));
+          vsrc.resize(vsrc.size() + (size_t)kOffsetsPerOctant * cnt, -1);
+          for (int jj = 0; jj < kOffsetsPerOctant; ++jj) {
+            const int t = oct_offs[oc][jj];
+            for (int ii = 0; ii < cnt; ++ii) {
+              int32_t c[3];
+              morton_decode(T.keys[l][members[ii]], l, c);
+              const int64_t x = c[0] - O.offsets[3 * t], y = c[1] - O.offsets[3 * t + 1], z = c[2] - O.offsets[3 * t + 2];
+              if (x < 0 || y < 0 || z < 0 || x >= ml || y >= ml || z >= ml) continue;
+              const int64_t j = T.find(l, morton_encode((uint32_t)x, (uint32_t)y, (uint32_t)z, l));
+              if (j < 0) continue;
+              vsrc[vs_base + (size_t)jj * cnt + ii] = (int)(P->base[l] + slot_of[l][j]);
+              ++vpairs;
+            }
+          }
+          for (int i0 = 0; i0 < cnt; i0 += 64)
+            lt[oc].push_back(M2LTile{oc, i0, std::min(64, cnt - i0), cnt, tgt_base, vs_base});
+          most = std::max(most, lt[oc].size());
+        }
+        // Interleave sibling positions so that consecutive workgroups (spread over
+        // the XCDs round-robin) use the same offset set per XCD when counts agree.
+        for (size_t ib = 0; ib < most; ++ib)
+          for (int oc = 0; oc < 8; ++oc)
+            if (ib < lt[oc].size()) tiles.push_back(lt[oc][ib]);
+      }
+      P->m2l_pairs = vpairs;
+      P->m2l_targets = (int64_t)tgt.size();
+      P->n_tiles = (int)tiles.size();
+      P->d_tgt = dev_upload(own, tgt.data(), tgt.size(), "m2l targets");
+      P->d_vsrc = dev_upload(own, vsrc.data(), vsrc.size(), "m2l sources");
+      P->d_tiles = dev_upload(own, tiles.data(), tiles.size(), "m2l tiles");
+      P->keys_per_level.assign(L + 1, 0);
+      for (int l = 0; l <= L; ++l) P->keys_per_level[l] = (int64_t)T.keys[l].size();
+      P->slot_of = slot_of;
+    }
+    hip_check(hipDeviceSynchronize(), "plan upload");
+  } catch (...) {
+    delete P;
+    (void)hipSetDevice(prev);
+    throw;
+  }
+  (void)hipSetDevice(prev);
+  return P;
+}
+
+void Plan::timing_begin_call() {
+  ring_slot = -1;
+  if (!timing) return;
+  if (ev.empty()) {
+    ev.resize((size_t)kRing * KIFMM_N_STAGES * 2);
+    for (auto& e : ev) hip_check(hipEventCreate(&e), "hipEventCreate");
+    recorded.assign((size_t)kRing * KIFMM_N_STAGES, 0);
+  }
+  if (ring_used == kRing) collect_times();
+  ring_slot = ring_used++;
+}
+
+void Plan::stage_begin(int s, hipStream_t st) {
+  if (ring_slot < 0) return;
+  hip_check(hipEventRecord(ev[((size_t)ring_slot * KIFMM_N_STAGES + s) * 2], st), "hipEventRecord");
+}
+
+void Plan::stage_end(int s, hipStream_t st) {
+  if (ring_slot < 0) return;
+  hip_check(hipEventRecord(ev[((size_t)ring_slot * KIFMM_N_STAGES + s) * 2 + 1], st), "hipEventRecord");
+  recorded[(size_t)ring_slot * KIFMM_N_STAGES + s] = 1;
+}
+
+void Plan::collect_times() {
+  for (int c = 0; c < ring_used; ++c)
+    for (int s = 0; s < KIFMM_N_STAGES; ++s) {
+      unsigned char& r = recorded[(size_t)c * KIFMM_N_STAGES + s];
+      if (!r) continue;
+      const size_t e = ((size_t)c * KIFMM_N_STAGES + s) * 2;
+      hip_check(hipEventSynchronize(ev[e + 1]), "hipEventSynchronize");
+      float ms = 0.f;
+      hip_check(hipEventElapsedTime(&ms, ev[e], ev[e + 1]), "hipEventElapsedTime");
+      stage_ms[s] += ms;
+      stage_count[s] += 1;
+      r = 0;
+    }
+  ring_used = 0;
+}
+
+void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipStream_t st) {
+  require(charges != nullptr, "charges is null");
+  require(pot || grad, "at least one of potential / gradient must be given");
+  require(!grad || (P->flags & KIFMM_GRADIENT), "plan was created without KIFMM_GRADIENT");
+  require(!pot || (P->flags & KIFMM_POTENTIAL) || (P->flags & KIFMM_GRADIENT), "potential not enabled");
+  int prev = 0;
+  hip_check(hipGetDevice(&prev), "hipGetDevice");
+  if (prev != P->device) hip_check(hipSetDevice(P->device), "hipSetDevice");
+  P->timing_begin_call();
+
+  const int N = (int)P->N;
+  const int L = P->L;
+  P->stage_begin(KIFMM_STAGE_PERMUTE, st);
+  launch_permute(P->d_pts, charges, P->d_order, N, st);
+  P->stage_end(KIFMM_STAGE_PERMUTE, st);
+
+  if (P->far) {
+    const int n = P->n, nst = P->nst, kst = P->kst, kcst = P->kcst;
+    const int SL = (int)P->slots[L];
+    const int nleaves = (int)P->n_leaves;
+    float* uL = P->d_u + P->base[L] * nst;
+    // (1a) S2U: check field, then the two pseudo-inverse factors (scaled by r_L).
+    P->stage_begin(KIFMM_STAGE_P2M, st);
+    launch_p2m(P->d_pts, P->d_start, P->d_leaves, P->d_centers, P->d_surf, n, (float)kAlphaOuter, P->d_q, nst,
+               nleaves, st);
+    P->stage_end(KIFMM_STAGE_P2M, st);
+    P->stage_begin(KIFMM_STAGE_UC2E, st);
+    launch_gemm_nt(P->d_f1, nst, P->d_q, nst, P->d_leaves, P->d_t, kcst, P->d_leaves, nleaves, kcst, nst, 1.0f, 0, st);
+    launch_gemm_nt(P->d_f2, kcst, P->d_t, kcst, P->d_leaves, uL, nst, P->d_leaves, nleaves, nst, kcst,
+                   (float)P->tree->radius(L), 0, st);
+    P->stage_end(KIFMM_STAGE_UC2E, st);
+    (void)SL;
+    // (1b) U2U, child level l -> parent level l - 1, down to level 2.
+    P->stage_begin(KIFMM_STAGE_M2M, st);
+    for (int l = L; l >= 3; --l) {
+      const int parents = (int)P->keys_per_level[l - 1];
+      launch_gemm_nt(P->d_m2m, 8 * nst, P->d_u + P->base[l] * nst, 8 * nst, nullptr, P->d_u + P->base[l - 1] * nst,
+                     nst, P->d_nbslot[l - 1], parents, nst, 8 * nst, 1.0f, 0, st);
+    }
+    P->stage_end(KIFMM_STAGE_M2M, st);
+    // (2a) VLI: compress, translate with the shared cores, all levels at once.
+    P->stage_begin(KIFMM_STAGE_COMPRESS, st);
+    launch_gemm_nt(P->d_vt, nst, P->d_u, nst, nullptr, P->d_uhat, kst, nullptr, (int)P->total_slots, kst, nst, 1.0f,
+                   0, st);
+    P->stage_end(KIFMM_STAGE_COMPRESS, st);
+    P->stage_begin(KIFMM_STAGE_M2L, st);
+    launch_m2l(P->m2l_rb, P->d_cores, P->core_rows, kst, kst, P->d_offidx, P->d_uhat, P->d_chat, P->d_zero,
+               P->d_tiles, P->n_tiles, P->d_tgt, P->d_vsrc, st);
+    P->stage_end(KIFMM_STAGE_M2L, st);
+    // (2c) post (DC2E U_k) and D2D, coarse to fine.
+    P->stage_begin(KIFMM_STAGE_L2L, st);
+    for (int l = 2; l <= L; ++l) {
+      launch_gemm_nt(P->d_post, kst, P->d_chat + P->base[l] * kst, kst, nullptr, P->d_d + P->base[l] * nst, nst,
+                     nullptr, (int)P->slots[l], nst, kst, 1.0f, 0, st);
+      if (l > 2) {
+        const int parents = (int)P->keys_per_level[l - 1];
+        launch_gemm_nt(P->d_l2l, nst, P->d_d + P->base[l - 1] * nst, nst, P->d_nbslot[l - 1],
+                       P->d_d + P->base[l] * nst, 8 * nst, nullptr, parents, 8 * nst, nst, 1.0f, 1, st);
+      }
+    }
+    P->stage_end(KIFMM_STAGE_L2L, st);
+  }
+  // (3b) D2T + (3c) ULI, written in input order.
+  P->stage_begin(KIFMM_STAGE_P2P, st);
+  launch_p2p(P->d_pts, P->d_start, P->d_blk, (int)P->n_groups, P->group_slots, P->d_centers, P->d_surf, P->n,
+             (float)kAlphaOuter, P->far ? P->d_d + P->base[L] * P->nst : nullptr, P->nst, P->far ? 1 : 0,
+             P->d_order, pot, grad, st);
+  P->stage_end(KIFMM_STAGE_P2P, st);
+  hip_check(hipGetLastError(), "kernel launch");
+  if (prev != P->device) (void)hipSetDevice(prev);
+}
+
+void read_density(Plan* P, int kind, int level, float* out, int64_t capacity) {
+  require(out != nullptr, "output is null");
+  require(kind == 0 || kind == 1, "kind must be 0 (u) or 1 (d)");
+  require(P->far, "the tree has no far field (depth < 2)");
+  require(level >= 2 && level <= P->L, "level must be in [2, depth]");
+  const int64_t nb = P->keys_per_level[level];
+  require(capacity >= nb * P->n, "capacity too small");
+  int prev = 0;
+  hip_check(hipGetDevice(&prev), "hipGetDevice");
+  hip_check(hipSetDevice(P->device), "hipSetDevice");
+  hip_check(hipDeviceSynchronize(), "synchronise");
+  std::vector<float> all((size_t)P->slots[level] * P->nst);
+  const float* src = (kind == 0 ? P->d_u : P->d_d) + P->base[level] * P->nst;
+  hip_check(hipMemcpy(all.data(), src, all.size() * sizeof(float), hipMemcpyDeviceToHost), "copy density");
+  for (int64_t i = 0; i < nb; ++i)
+    std::memcpy(out + i * P->n, all.data() + (size_t)P->slot_of[level][i] * P->nst, P->n * sizeof(float));
+  (void)hipSetDevice(prev);
+}
+
+}  // namespace kifmm

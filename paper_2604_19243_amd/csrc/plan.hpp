@@ -1,0 +1,69 @@
+// Device plan of the kiFMM evaluate (plan.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace kifmm {
+
+struct Plan : Object {
+  Tree* tree = nullptr;
+  Ops* ops = nullptr;
+  unsigned flags = 0;
+  int device = 0;
+  int L = 0;
+  int64_t N = 0;
+  bool far = false;
+  int n = 0, nst = 0, k = 0, kst = 0, kc = 0, kcst = 0;
+  std::vector<int64_t> slots, base, keys_per_level;
+  std::vector<std::vector<int>> slot_of;
+  int64_t total_slots = 0, n_leaves = 0;
+  int64_t p2p_pairs = 0, m2l_pairs = 0, m2l_targets = 0;
+  int m2l_rb = 0, core_rows = 0, n_tiles = 0;
+
+  std::vector<void*> owned;  // device allocations
+  float4* d_pts = nullptr;
+  int* d_order = nullptr;
+  int* d_start = nullptr;
+  int* d_leaves = nullptr;
+  float4* d_centers = nullptr;
+  int* d_blk = nullptr;
+  int64_t n_groups = 0;
+  int group_slots = 8;
+  float* d_surf = nullptr;
+  float *d_q = nullptr, *d_t = nullptr, *d_u = nullptr, *d_d = nullptr, *d_uhat = nullptr, *d_chat = nullptr;
+  float* d_zero = nullptr;
+  float *d_f1 = nullptr, *d_f2 = nullptr, *d_m2m = nullptr, *d_vt = nullptr, *d_post = nullptr, *d_l2l = nullptr;
+  float* d_cores = nullptr;
+  std::vector<int*> d_nbslot;
+  int* d_offidx = nullptr;
+  int* d_tgt = nullptr;
+  int* d_vsrc = nullptr;
+  M2LTile* d_tiles = nullptr;
+
+  // Stage timing: a ring of event pairs per call, read back only when full or
+  // on request, so timed evaluates never wait on the host.
+  static constexpr int kRing = 128;
+  bool timing = false;
+  std::vector<hipEvent_t> ev;            // [kRing][KIFMM_N_STAGES][2]
+  std::vector<unsigned char> recorded;   // [kRing][KIFMM_N_STAGES]
+  int ring_used = 0, ring_slot = -1;
+  double stage_ms[KIFMM_N_STAGES] = {};
+  int64_t stage_count[KIFMM_N_STAGES] = {};
+
+  ~Plan() override;
+  void timing_begin_call();
+  void stage_begin(int s, hipStream_t st);
+  void stage_end(int s, hipStream_t st);
+  void collect_times();
+};
+
+Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device);
+void evaluate_plan(Plan* plan, const float* charges, float* pot, float* grad, hipStream_t st);
+void read_density(Plan* plan, int kind, int level, float* out, int64_t capacity);
+
+}  // namespace kifmm

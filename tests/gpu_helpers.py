@@ -1,0 +1,39 @@
+"""Helpers for the GPU parity tests: run the HIP path through the C ABI and the
+oracle on the same seeded inputs."""
+
+import sys
+
+import numpy as np
+
+from oracle import direct, fmm, operators, tree
+from paper_2604_19243_amd import kifmm
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_evaluate(points, charges, depth, p, cube, eps_svd=1e-6, rank=0, gradient=True, fmm_obj=None):
+    """HIP path: returns (phi [n], grad [n,3] or None, FMM object) as float64 numpy arrays."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    f = fmm_obj or kifmm.FMM(points, depth, p, cube=cube, eps_svd=eps_svd, rank=rank)
+    dev = torch.device("cuda:0")
+    s = torch.from_numpy(np.ascontiguousarray(charges, dtype=np.float32)).to(dev)
+    pot = torch.full((len(points),), float("nan"), device=dev)
+    grad = torch.full((len(points), 3), float("nan"), device=dev) if gradient else None
+    f.evaluate(s, pot, grad, stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return (pot.cpu().double().numpy(), None if grad is None else grad.cpu().double().numpy(), f)
+
+
+def oracle_evaluate(points, charges, depth, p, cube, eps_svd=1e-6, rank=None, gradient=True, target_leaves=None):
+    t = tree.Tree(np.asarray(points, dtype=np.float64), depth, cube[:3], cube[3])
+    ops = operators.Operators(p, eps_pinv=1e-7, m2l="compressed", eps_svd=eps_svd, rank=rank)
+    phi, g = fmm.evaluate(t, ops, np.asarray(charges, dtype=np.float64), gradient=gradient,
+                          target_leaves=target_leaves)
+    return phi, g, t, ops
+
+
+rel_l2 = direct.rel_l2

@@ -1,0 +1,118 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on seeded inputs.
+
+Tolerance: relative L2 <= 1e-6 for potentials and gradients of the plain FP32 path.
+"""
+
+import numpy as np
+import pytest
+
+from gpu_helpers import gpu_evaluate, log, oracle_evaluate, rel_l2
+from oracle import direct
+from paper_2604_19243_amd import kifmm, workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+UNIT = (0.5, 0.5, 0.5, 0.5)
+
+
+@pytest.mark.parametrize("depth,n", [(0, 700), (1, 3000), (1, 1)])
+def test_shallow_tree_equals_direct_sum(depth, n):
+    # depth <= 1: every leaf is in every U list, so the HIP path is the direct sum (P2P only).
+    log(f"shallow depth={depth} n={n}")
+    x = workloads.points("cube", n, 10 + depth)
+    s = workloads.charges("uniform01", n, 20 + depth)
+    phi, g, f = gpu_evaluate(x, s, depth, 4, UNIT)
+    f.close()
+    x64, s64 = x.astype(np.float64), s.astype(np.float64)
+    ref = direct.potential(x64, x64, s64)
+    gref = direct.gradient(x64, x64, s64)
+    if n == 1:
+        assert phi[0] == 0.0 and np.all(g[0] == 0.0)
+        return
+    assert rel_l2(phi, ref) < TOL
+    assert rel_l2(g, gref) < TOL
+
+
+@pytest.mark.parametrize("name,n,depth,p,dist", [
+    ("cube20k_p6_d3", 20_000, 3, 6, "cube"),   # the FP64 validation workload, full size
+    ("ragged", 7_777, 4, 5, "cube"),           # ragged leaves and tiles, many boundary boxes
+    ("sphere", 30_000, 4, 6, "sphere"),        # strongly non-uniform: most boxes empty
+    ("sparse_deep", 2_000, 5, 4, "cube"),      # ~0.06 points per leaf
+])
+def test_parity_with_oracle(name, n, depth, p, dist):
+    log(f"parity {name} n={n} depth={depth} p={p}")
+    x = workloads.points(dist, n, 1001 if name.startswith("cube20k") else 500 + n)
+    s = workloads.charges("uniform01", n, 2001 if name.startswith("cube20k") else 600 + n)
+    cube = UNIT if dist == "cube" else (0.0, 0.0, 0.0, 1.0)
+    phi, g, f = gpu_evaluate(x, s, depth, p, cube)
+    k = kifmm.kifmm_ops_get_info(f.ops)["rank_m2l"]
+    f.close()
+    rphi, rg, _, ops = oracle_evaluate(x, s, depth, p, cube)
+    assert ops.compression(1.0)[0].shape[1] == k
+    e, eg = rel_l2(phi, rphi), rel_l2(g, rg)
+    log(f"  rel-L2 phi {e:.3e} grad {eg:.3e} (k={k})")
+    assert e < TOL and eg < TOL
+
+
+def test_linearity_and_determinism():
+    log("linearity/determinism")
+    w = workloads.WORKLOADS["cube20k_p6_d3"]
+    x, s1 = workloads.make(w)
+    s2 = workloads.charges("normal", len(x), 99)
+    c = w.cube[0] + (w.cube[1],)
+    p1, g1, f = gpu_evaluate(x, s1, w.depth, w.p, c)
+    p1b, g1b, _ = gpu_evaluate(x, s1, w.depth, w.p, c, fmm_obj=f)
+    np.testing.assert_array_equal(p1, p1b)   # no atomics: bitwise repeatable
+    np.testing.assert_array_equal(g1, g1b)
+    p2, g2, _ = gpu_evaluate(x, s2, w.depth, w.p, c, fmm_obj=f)
+    s12 = (0.5 * s1.astype(np.float64) - 2.0 * s2.astype(np.float64)).astype(np.float32)
+    p12, g12, _ = gpu_evaluate(x, s12, w.depth, w.p, c, fmm_obj=f)
+    f.close()
+    assert rel_l2(p12, 0.5 * p1 - 2.0 * p2) < 1e-5
+    assert rel_l2(g12, 0.5 * g1 - 2.0 * g2) < 1e-5
+
+
+def test_full_size_hot_path_sampled():
+    # 1,000,000 points, depth 5, p = 6: the benchmarked workload in the benchmarked launch
+    # configuration, checked against the oracle on the points of 24 sampled leaves.
+    w = workloads.WORKLOADS["cube1m_p6_d5"]
+    log("full size cube1m_p6_d5")
+    x, s = workloads.make(w)
+    c = w.cube[0] + (w.cube[1],)
+    phi, g, f = gpu_evaluate(x, s, w.depth, w.p, c)
+    f.close()
+    assert np.isfinite(phi).all() and np.isfinite(g).all()
+    rng = np.random.default_rng(4002)
+    m = 2 ** w.depth
+    leaves = {tuple(int(v) for v in rng.integers(0, m, 3)) for _ in range(20)}
+    leaves |= {(0, 0, 0), (m - 1, m - 1, m - 1), (0, m - 1, 5), (m // 2, 0, m - 1)}
+    leaves = sorted(leaves)
+    rphi, rg, t, _ = oracle_evaluate(x, s, w.depth, w.p, c, target_leaves=leaves)
+    idx = np.concatenate([t.leaf_points[b] for b in leaves if b in t.leaf_points])
+    e, eg = rel_l2(phi[idx], rphi[idx]), rel_l2(g[idx], rg[idx])
+    log(f"  sampled {len(idx)} points: rel-L2 phi {e:.3e} grad {eg:.3e}")
+    assert e < TOL and eg < TOL
+
+
+def test_stream_and_outputs_subset():
+    import torch
+    log("stream/outputs")
+    x = workloads.points("cube", 5000, 3)
+    s = workloads.charges("uniform01", 5000, 4)
+    f = kifmm.FMM(x, 3, 4, cube=UNIT)
+    dev = torch.device("cuda:0")
+    st = torch.cuda.Stream()
+    sd = torch.from_numpy(s).to(dev)
+    pot = torch.zeros(5000, device=dev)
+    grad = torch.zeros(5000, 3, device=dev)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(st):
+        f.evaluate(sd, pot, grad, stream=st.cuda_stream)
+        pot_only = torch.zeros(5000, device=dev)
+        f.evaluate(sd, pot_only, None, stream=st.cuda_stream)
+    st.synchronize()
+    np.testing.assert_array_equal(pot.cpu().numpy(), pot_only.cpu().numpy())
+    with pytest.raises(kifmm.KifmmError):
+        f.evaluate(sd, None, None)
+    f.close()

@@ -1,0 +1,189 @@
+"""CPU tests of the C-ABI library: exports, tree build and operator precompute against
+the oracle, and error paths.  No device work is done (no GPU needed)."""
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import operators as oops
+from oracle import surface as osurf
+from oracle import tree as otree
+from paper_2604_19243_amd import kifmm, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return kifmm.library()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    header = open(os.path.join(ROOT, "include", "kifmm_mi355x.h")).read()
+    names = set(re.findall(r"\b(kifmm_[a-z_0-9]+)\s*\(", header))
+    assert len(names) >= 18
+    for name in sorted(names):
+        assert hasattr(lib, name), name
+    assert kifmm.kifmm_abi_version() == 1
+
+
+@pytest.mark.parametrize("dist,depth,n", [("cube", 3, 20_000), ("cube", 5, 50_000), ("sphere", 4, 30_000),
+                                          ("cube", 0, 100), ("cube", 1, 500)])
+def test_tree_matches_oracle(dist, depth, n):
+    x = workloads.points(dist, n, 77)
+    cube = (0.5, 0.5, 0.5, 0.5) if dist == "cube" else (0.0, 0.0, 0.0, 1.0)
+    t = kifmm.kifmm_tree_build(x, depth, cube)
+    try:
+        ref = otree.Tree(x.astype(np.float64), depth, cube[:3], cube[3])
+        np.testing.assert_array_equal(kifmm.kifmm_tree_get_leaf_coords(t, n), ref.leaf_index)
+        np.testing.assert_array_equal(kifmm.kifmm_tree_get_order(t, n), ref.order)
+        info = kifmm.kifmm_tree_get_info(t)
+        assert info["nonempty_boxes"] == [len(b) for b in ref.boxes]
+        assert info["max_leaf_points"] == max(len(v) for v in ref.leaf_points.values())
+    finally:
+        kifmm.kifmm_tree_destroy(t)
+
+
+def test_tree_auto_cube_and_boundary_points():
+    rng = np.random.default_rng(5)
+    x = (rng.random((3000, 3)) * [2.0, 1.0, 0.5] - 0.3).astype(np.float32)
+    x[0] = x.min(axis=0)
+    x[1] = x.max(axis=0)
+    t = kifmm.kifmm_tree_build(x, 4, None)
+    try:
+        ref = otree.Tree(x.astype(np.float64), 4)
+        info = kifmm.kifmm_tree_get_info(t)
+        assert info["half_width"] == ref.half_width
+        assert info["center"] == tuple(ref.center)
+        np.testing.assert_array_equal(kifmm.kifmm_tree_get_leaf_coords(t, 3000), ref.leaf_index)
+    finally:
+        kifmm.kifmm_tree_destroy(t)
+
+
+@pytest.fixture(scope="module", params=[(6, 1e-6), (5, 1e-7)])
+def ops_pair(request):
+    p, eps_svd = request.param
+    h = kifmm.kifmm_ops_precompute(p, 1e-7, eps_svd, 0)
+    ref = oops.Operators(p, eps_pinv=1e-7, m2l="compressed", eps_svd=eps_svd)
+    yield p, h, ref
+    kifmm.kifmm_ops_destroy(h)
+
+
+def test_ops_info_and_surface(ops_pair):
+    p, h, ref = ops_pair
+    info = kifmm.kifmm_ops_get_info(h)
+    n = osurf.n_points(p)
+    assert info["n_surface"] == n and info["n_m2l_offsets"] == 316
+    uk = ref.compression(1.0)[0]
+    assert info["rank_m2l"] == uk.shape[1]
+    np.testing.assert_array_equal(kifmm.kifmm_ops_get_matrix(h, kifmm.KIFMM_OP_SURFACE, 0, (n, 3)), osurf.reference_surface(p))
+    if p == 6:
+        assert info["rank_m2l"] == 116
+
+
+def test_check_to_equivalent_matches_oracle(ops_pair):
+    p, h, ref = ops_pair
+    n = osurf.n_points(p)
+    for which, mine in ((kifmm.KIFMM_OP_UC2E, ref.uc2e(1.0)), (kifmm.KIFMM_OP_DC2E, ref.dc2e(1.0))):
+        got = kifmm.kifmm_ops_get_matrix(h, which, 0, (n, n))
+        # pinv of a matrix whose kept condition number is <= 1e7: agreement ~1e-16 * 1e7
+        assert np.linalg.norm(got - mine) <= 1e-7 * np.linalg.norm(mine)
+
+
+def test_translations_match_oracle(ops_pair):
+    p, h, ref = ops_pair
+    n = osurf.n_points(p)
+    for oc in (0, 3, 7):
+        m2m = kifmm.kifmm_ops_get_matrix(h, kifmm.KIFMM_OP_M2M, oc, (n, n))
+        want = ref.uc2e(2.0) @ ref.m2m_check(1.0, oc)
+        assert np.linalg.norm(m2m - want) <= 1e-7 * np.linalg.norm(want)
+        l2l = kifmm.kifmm_ops_get_matrix(h, kifmm.KIFMM_OP_L2L, oc, (n, n))
+        want = ref.dc2e(1.0) @ ref.l2l_check(1.0, oc)
+        assert np.linalg.norm(l2l - want) <= 1e-7 * np.linalg.norm(want)
+
+
+def test_compressed_m2l_matches_oracle(ops_pair):
+    # Bases are not unique; compare the approximate operators U_k C_t V_k^T and the folded
+    # post C_t V_k^T = DC2E U_k C_t V_k^T.
+    p, h, ref = ops_pair
+    n = osurf.n_points(p)
+    k = kifmm.kifmm_ops_get_info(h)["rank_m2l"]
+    U = kifmm.kifmm_ops_get_matrix(h, kifmm.KIFMM_OP_M2L_U, 0, (n, k))
+    V = kifmm.kifmm_ops_get_matrix(h, kifmm.KIFMM_OP_M2L_V, 0, (n, k))
+    post = kifmm.kifmm_ops_get_matrix(h, kifmm.KIFMM_OP_M2L_POST, 0, (n, k))
+    np.testing.assert_allclose(U.T @ U, np.eye(k), atol=1e-12)
+    np.testing.assert_allclose(V.T @ V, np.eye(k), atol=1e-12)
+    ruk, rvk, rcores, _ = ref.compression(1.0)
+    offs = oops.v_list_offsets()
+    for idx in (0, 57, 150, 315):
+        t = tuple(int(v) for v in kifmm.kifmm_ops_get_matrix(h, kifmm.KIFMM_OP_M2L_OFFSET, idx, (3,)))
+        assert t == offs[idx]
+        C = kifmm.kifmm_ops_get_matrix(h, kifmm.KIFMM_OP_M2L_CORE, idx, (k, k))
+        mine = U @ C @ V.T
+        want = ruk @ rcores[t] @ rvk.T
+        assert np.linalg.norm(mine - want) <= 1e-10 * np.linalg.norm(want)
+        mine_post = post @ C @ V.T
+        want_post = ref.dc2e(1.0) @ want
+        assert np.linalg.norm(mine_post - want_post) <= 1e-7 * np.linalg.norm(want_post)
+
+
+def _status(fn, *args):
+    with pytest.raises(kifmm.KifmmError) as e:
+        fn(*args)
+    return e.value.status
+
+
+def test_error_paths(lib):
+    x = workloads.points("cube", 100, 1)
+    assert _status(kifmm.kifmm_tree_build, x, -1) == kifmm.KIFMM_E_INVALID
+    assert _status(kifmm.kifmm_tree_build, x, 11) == kifmm.KIFMM_E_INVALID
+    assert _status(kifmm.kifmm_tree_build, x[:0], 2) == kifmm.KIFMM_E_INVALID
+    bad = x.copy()
+    bad[3, 1] = np.nan
+    assert _status(kifmm.kifmm_tree_build, bad, 2) == kifmm.KIFMM_E_INVALID
+    assert _status(kifmm.kifmm_tree_build, x, 2, (0.5, 0.5, 0.5, 0.0)) == kifmm.KIFMM_E_INVALID
+    assert _status(kifmm.kifmm_tree_build, x, 2, (0.5, math.inf, 0.5, 1.0)) == kifmm.KIFMM_E_INVALID
+    assert _status(kifmm.kifmm_ops_precompute, 1) == kifmm.KIFMM_E_INVALID
+    assert _status(kifmm.kifmm_ops_precompute, 13) == kifmm.KIFMM_E_INVALID
+    assert _status(kifmm.kifmm_ops_precompute, 4, 0.0) == kifmm.KIFMM_E_INVALID
+    assert _status(kifmm.kifmm_ops_precompute, 4, 1e-7, 2.0) == kifmm.KIFMM_E_INVALID
+    assert _status(kifmm.kifmm_ops_precompute, 4, 1e-7, 1e-6, 1000) == kifmm.KIFMM_E_INVALID
+    # null handles and pointers
+    out = ctypes.c_void_p()
+    assert lib.kifmm_tree_build(None, 10, 2, None, ctypes.byref(out)) == kifmm.KIFMM_E_INVALID
+    assert lib.kifmm_tree_get_info(None, None) == kifmm.KIFMM_E_INVALID
+    assert lib.kifmm_evaluate(None, None, None, None, None) == kifmm.KIFMM_E_INVALID
+    assert b"null" in lib.kifmm_last_error()
+    assert lib.kifmm_plan_destroy(None) == kifmm.KIFMM_E_INVALID
+    t = kifmm.kifmm_tree_build(x, 2, (0.5, 0.5, 0.5, 0.5))
+    o = kifmm.kifmm_ops_precompute(3)
+    try:
+        assert lib.kifmm_ops_get_matrix(o, 99, 0, None, 0) == kifmm.KIFMM_E_INVALID
+        buf = np.zeros(4)
+        assert lib.kifmm_ops_get_matrix(o, kifmm.KIFMM_OP_SURFACE, 0, buf.ctypes.data, 4) == kifmm.KIFMM_E_INVALID
+        assert b"capacity" in lib.kifmm_last_error()
+        assert lib.kifmm_plan_create(t, o, 0, 0, ctypes.byref(out)) == kifmm.KIFMM_E_INVALID
+        assert lib.kifmm_plan_create(t, o, 1, -1, ctypes.byref(out)) in (kifmm.KIFMM_E_INVALID, kifmm.KIFMM_E_DEVICE)
+    finally:
+        kifmm.kifmm_ops_destroy(o)
+        kifmm.kifmm_tree_destroy(t)
+
+
+def test_plan_without_device_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    x = workloads.points("cube", 100, 1)
+    t = kifmm.kifmm_tree_build(x, 2, (0.5, 0.5, 0.5, 0.5))
+    o = kifmm.kifmm_ops_precompute(3)
+    try:
+        with pytest.raises(kifmm.KifmmError) as e:
+            kifmm.kifmm_plan_create(t, o)
+        assert e.value.status in (kifmm.KIFMM_E_DEVICE, kifmm.KIFMM_E_INVALID)
+    finally:
+        kifmm.kifmm_ops_destroy(o)
+        kifmm.kifmm_tree_destroy(t)
