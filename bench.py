@@ -111,12 +111,23 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample-leaves", type=int, default=24)
     ap.add_argument("--sample-seed", type=int, default=2)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer 5 times (calibrates HBM byte counters) and exit")
     ap.add_argument("--cpu-baseline-worker", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--gpu-sample", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
 
     if args.cpu_baseline_worker:
         cpu_baseline_worker(args)
+        return
+    if args.copy_probe:
+        import torch
+        src = torch.ones(args.copy_probe * (1 << 20) // 4, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_mib": args.copy_probe, "launches": 5}), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",

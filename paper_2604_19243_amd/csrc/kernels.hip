@@ -111,106 +111,239 @@ void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int*
 }
 
 // ----------------------------------------------------------------- M2L ---
-// Compressed VLI: for every target box B of a tile,
-//   chat[B][o] = sum_{j < 189} sum_k C_{t(j)}[o][k] uhat[src(B, j)][k],
-// where t(j) is the j-th V-list offset of B's position among its siblings and
-// src(B, j) is the source box at that offset (-1: none).  One workgroup owns
-// 64 targets of one level and one sibling position, and all output rows.
-// Waves are 2 (row halves) x 2 (32 targets); a wave holds RB row blocks of 16.
-template <int RB>
-__global__ __launch_bounds__(256) void k_m2l(const float* __restrict__ cores, int core_rows, int ldk, int K,
-                                             const int* __restrict__ offidx, const float* __restrict__ uhat,
-                                             float* __restrict__ chat, const float* __restrict__ zero_row,
-                                             const M2LTile* __restrict__ tiles, const int* __restrict__ tgt,
-                                             const int* __restrict__ vsrc) {
-  const M2LTile tile = tiles[blockIdx.x];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int i16 = lane & 15, q = lane >> 4;
-  const int row0 = (wave & 1) * RB * 16;
-  const int col0 = (wave >> 1) * 32;
+// Compressed VLI over blocks.  A work item is (level, an aligned 4 x 4 x 4 block
+// of parent boxes, target position o, source position o').  Its targets are the
+// children at position o of the block's parents (up to 64); its sources are the
+// children at position o' of the 6 x 6 x 6 parents around the block (216 rows,
+// staged once in LDS, missing boxes as zero rows).  Every V-list offset between
+// such a target and source is a parent shift d in {-1,0,1}^3, i.e. a fixed row
+// shift in the staged block, and the item computes for each target
+//   chat_part[o'][target] = sum_{d} C_{t(o, o', d)} uhat[child o' of (parent + d)].
+// The eight source positions' partial sums are added afterwards (k_sum_parts).
+//
+// One wave per 16 output rows (blockDim = 64 * ceil(k / 16)); each wave covers
+// all 64 targets as four 16-column blocks.  Operator rows are read from global
+// memory (L2: the items of one (o, o') pair are dealt to one XCD) exactly once
+// per workgroup, sources from LDS.  The k loop runs over "chunks" of 16 k (plus
+// a TAIL of 4, 8 or 12 k per offset) with the next chunk's operands loaded into
+// a second register set while the current one feeds the matrix cores.
+template <int TAIL>
+struct M2LRegs {
+  float4 a;
+  float4 b[4];
+  float at[TAIL / 4 > 0 ? TAIL / 4 : 1];
+  float bt[TAIL / 4 > 0 ? TAIL / 4 : 1][4];
+};
 
-  v4f acc[RB][2];
-#pragma unroll
-  for (int m = 0; m < RB; ++m)
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb) acc[m][nb] = v4f{0.f, 0.f, 0.f, 0.f};
+extern __shared__ float4 s_m2l[];  // [217][ld4] float4: the current k-slab of the staged sources
 
-  int col_ok[2];
-#pragma unroll
-  for (int nb = 0; nb < 2; ++nb) col_ok[nb] = (col0 + 16 * nb + i16) < tile.count;
-  const int* vs = vsrc + tile.vsrc_base + tile.i0 + col0 + i16;
-  const int* offs = offidx + tile.octant * 189;
+constexpr int kM2LSlab = 64;  // k per LDS slab
 
-  for (int j = 0; j < 189; ++j) {
-    int s[2];
+// Operands of chunk c (16 k) of the current slab; `ka` is the slab's first k in
+// the operator row.  The tail of the last slab is fetched with every chunk (used
+// only with the last one), so no load is conditional and wait counts stay exact.
+template <int TAIL>
+__device__ __forceinline__ void m2l_load(M2LRegs<TAIL>& r, const float* __restrict__ arow_ptr, const int* brow,
+                                         int c, int nch, int ld4, int q) {
+  r.a = *reinterpret_cast<const float4*>(arow_ptr + 16 * c + 4 * q);
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) s[nb] = col_ok[nb] ? vs[(size_t)j * tile.stride + 16 * nb] : -1;
-    if (!__any(s[0] >= 0 || s[1] >= 0)) continue;
-    const float* ap[RB];
-    const float* base = cores + (size_t)offs[j] * core_rows * ldk;
+  for (int nb = 0; nb < 4; ++nb) r.b[nb] = s_m2l[brow[nb] * ld4 + 4 * c + q];
 #pragma unroll
-    for (int m = 0; m < RB; ++m) ap[m] = base + (size_t)(row0 + 16 * m + i16) * ldk;
-    const float* bp[2];
+  for (int st = 0; st < TAIL / 4; ++st) {
+    r.at[st] = arow_ptr[16 * nch + 4 * st + q];
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) bp[nb] = s[nb] >= 0 ? uhat + (size_t)s[nb] * ldk : zero_row;
-    int k = 0;
-    for (; k + 16 <= K; k += 16) {
-      float4 a[RB], b[2];
+    for (int nb = 0; nb < 4; ++nb)
+      r.bt[st][nb] = reinterpret_cast<const float*>(s_m2l)[4 * (brow[nb] * ld4 + 4 * nch + st) + q];
+  }
+}
+
+template <int TAIL>
+__device__ __forceinline__ void m2l_compute(const M2LRegs<TAIL>& r, v4f* acc, bool tail) {
 #pragma unroll
-      for (int m = 0; m < RB; ++m) a[m] = *reinterpret_cast<const float4*>(ap[m] + k + 4 * q);
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16(r.a.x, r.b[nb].x, acc[nb]);
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb) b[nb] = *reinterpret_cast<const float4*>(bp[nb] + k + 4 * q);
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16(r.a.y, r.b[nb].y, acc[nb]);
 #pragma unroll
-      for (int m = 0; m < RB; ++m)
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16(r.a.z, r.b[nb].z, acc[nb]);
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb) acc[m][nb] = mfma16x4(a[m], b[nb], acc[m][nb]);
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16(r.a.w, r.b[nb].w, acc[nb]);
+  if (TAIL && tail) {
+#pragma unroll
+    for (int st = 0; st < TAIL / 4; ++st)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16(r.at[st], r.bt[st][nb], acc[nb]);
+  }
+}
+
+// All offsets of the item over one k-slab: nch full chunks per offset (and the
+// TAIL after the last chunk when `with_tail`), prefetching one chunk ahead.
+template <int TAIL>
+__device__ __forceinline__ void m2l_slab(v4f* acc, const float* abase, size_t core_stride, int po_reg, int noffs,
+                                         const int* bbase, int nch, bool with_tail, int ld4, int q) {
+  const int nv = noffs * nch;
+  auto setup = [&](int j, const float*& ap, int* brow) {
+    const int e = __builtin_amdgcn_readlane(po_reg, j);
+    ap = abase + (e & 511) * core_stride;
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) brow[nb] = bbase[nb] + (e >> 9);
+  };
+  M2LRegs<TAIL> r0, r1;
+  int j0 = 0, c0 = 0;
+  int brow0[4], brow1[4];
+  const float* ap0;
+  const float* ap1;
+  setup(0, ap0, brow0);
+  m2l_load(r0, ap0, brow0, 0, nch, ld4, q);
+  for (int v = 0; v < nv; v += 2) {
+    int j1 = c0 + 1 < nch ? j0 : j0 + 1;
+    int c1 = c0 + 1 < nch ? c0 + 1 : 0;
+    if (j1 >= noffs) {
+      j1 = noffs - 1;
+      c1 = nch - 1;
     }
-    for (; k < K; k += 4) {
+    setup(j1, ap1, brow1);
+    m2l_load(r1, ap1, brow1, c1, nch, ld4, q);
+    __builtin_amdgcn_sched_barrier(0);
+    m2l_compute(r0, acc, with_tail && c0 == nch - 1);
+    __builtin_amdgcn_sched_barrier(0);
+    j0 = c1 + 1 < nch ? j1 : j1 + 1;
+    c0 = c1 + 1 < nch ? c1 + 1 : 0;
+    if (j0 >= noffs) {
+      j0 = noffs - 1;
+      c0 = nch - 1;
+    }
+    setup(j0, ap0, brow0);
+    m2l_load(r0, ap0, brow0, c0, nch, ld4, q);
+    __builtin_amdgcn_sched_barrier(0);
+    if (v + 1 < nv) m2l_compute(r1, acc, with_tail && c1 == nch - 1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int TAIL>
+__global__ __launch_bounds__(1024) void k_m2l(const float* __restrict__ cores, int core_rows, int ldk, int ld4,
+                                              const M2LItem* __restrict__ items, const int* __restrict__ tgt_blk,
+                                              const int* __restrict__ src_blk, const int* __restrict__ pair_offs,
+                                              const float* __restrict__ uhat, float* __restrict__ chat_part,
+                                              long long part_stride) {
+  const M2LItem it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;  // 16-row block of the output
+  const int i16 = lane & 15, q = lane >> 4;
+
+  int tslot[4], bbase[4];
 #pragma unroll
-      for (int m = 0; m < RB; ++m)
+  for (int nb = 0; nb < 4; ++nb) {
+    const int pi = 16 * nb + i16;  // position in the 4x4x4 parent block, x fastest
+    tslot[nb] = tgt_blk[it.tgt_base + pi];
+    bbase[nb] = ((pi & 3) + 1) + 6 * (((pi >> 2) & 3) + 1) + 36 * ((pi >> 4) + 1) - 43;
+  }
+  v4f acc[4];
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb) acc[m][nb] = mfma16(ap[m][k + q], bp[nb][k + q], acc[m][nb]);
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = v4f{0.f, 0.f, 0.f, 0.f};
+  // offset table of the item in one VGPR (lane j holds entry j), read with readlane
+  const int po_reg = pair_offs[it.pair * 27 + min(lane, 26)];
+  const float* arow = cores + (size_t)(16 * wave + i16) * ldk;
+  const size_t core_stride = (size_t)core_rows * ldk;
+  const int* srcs = src_blk + it.src_base;
+
+  for (int k0 = 0; k0 < ldk; k0 += kM2LSlab) {
+    const int kw = min(kM2LSlab, ldk - k0);  // slab width, a multiple of 4
+    const int w4 = kw >> 2;
+    if (k0) __syncthreads();  // previous slab fully consumed
+    for (int idx = tid; idx < 216 * w4; idx += blockDim.x) {
+      const int r = idx / w4, c4 = idx - r * w4;
+      const int slot = srcs[r];
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (slot >= 0) v = *reinterpret_cast<const float4*>(uhat + (size_t)slot * ldk + k0 + 4 * c4);
+      s_m2l[r * ld4 + c4] = v;
+    }
+    __syncthreads();
+    const int nch = kw / 16;
+    const bool last = k0 + kM2LSlab >= ldk;
+    if (nch > 0) {
+      m2l_slab<TAIL>(acc, arow + k0, core_stride, po_reg, it.noffs, bbase, nch, last, ld4, q);
+    } else {
+      // a slab narrower than 16 (small rank): plain 4-k steps
+      for (int j = 0; j < it.noffs; ++j) {
+        const int e = __builtin_amdgcn_readlane(po_reg, j);
+        const float* ap = arow + k0 + (e & 511) * core_stride;
+        for (int k = 0; k < kw; k += 4)
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb)
+            acc[nb] = mfma16(ap[k + q], reinterpret_cast<const float*>(s_m2l)[4 * ((bbase[nb] + (e >> 9)) * ld4) + k + q],
+                             acc[nb]);
+      }
     }
   }
+  float* out = chat_part + (size_t)it.part * part_stride;
+  const int o = 16 * wave + 4 * q;
+  if (o < ldk) {
 #pragma unroll
-  for (int nb = 0; nb < 2; ++nb) {
-    if (!col_ok[nb]) continue;
-    const int b = tgt[tile.tgt_base + tile.i0 + col0 + 16 * nb + i16];
-#pragma unroll
-    for (int m = 0; m < RB; ++m) {
-      const int o = row0 + 16 * m + 4 * q;
-      if (o >= K) continue;
-      *reinterpret_cast<float4*>(chat + (size_t)b * ldk + o) =
-          make_float4(acc[m][nb][0], acc[m][nb][1], acc[m][nb][2], acc[m][nb][3]);
+    for (int nb = 0; nb < 4; ++nb) {
+      if (tslot[nb] < 0) continue;
+      *reinterpret_cast<float4*>(out + (size_t)tslot[nb] * ldk + o) =
+          make_float4(acc[nb][0], acc[nb][1], acc[nb][2], acc[nb][3]);
     }
   }
 }
 
-void launch_m2l(int rb, const float* cores, int core_rows, int ldk, int K, const int* offidx, const float* uhat,
-                float* chat, const float* zero_row, const M2LTile* tiles, int ntiles, const int* tgt,
-                const int* vsrc, hipStream_t s) {
-  if (ntiles <= 0) return;
-#define KIFMM_M2L_CASE(R)                                                                                         \
-  case R:                                                                                                         \
-    hipLaunchKernelGGL(k_m2l<R>, dim3(ntiles), dim3(256), 0, s, cores, core_rows, ldk, K, offidx, uhat, chat,     \
-                       zero_row, tiles, tgt, vsrc);                                                               \
-    break;
-  switch (rb) {
-    KIFMM_M2L_CASE(1)
-    KIFMM_M2L_CASE(2)
-    KIFMM_M2L_CASE(3)
-    KIFMM_M2L_CASE(4)
-    KIFMM_M2L_CASE(5)
-    KIFMM_M2L_CASE(6)
-    KIFMM_M2L_CASE(7)
-    KIFMM_M2L_CASE(8)
-    KIFMM_M2L_CASE(9)
-    KIFMM_M2L_CASE(10)
-    default:
-      break;
+bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int lds_ld, const M2LItem* items,
+                int nitems, const int* tgt_blk, const int* src_blk, const int* pair_offs, const float* uhat,
+                float* chat_part, long long part_stride, hipStream_t s) {
+  if (nitems <= 0) return true;
+  if (row_blocks < 1 || row_blocks > 16 || (lds_ld & 3)) return false;
+  const int last_w = ldk - kM2LSlab * ((ldk - 1) / kM2LSlab);
+  const int tail = last_w % 16;
+  // 216 staged rows plus one spare row: in slabs other than the last, the
+  // (unused) tail operands are read up to 12 floats past a row's 64 k.
+  const size_t lds = (size_t)217 * lds_ld * sizeof(float);
+  if (lds_ld < 68) return false;
+#define KIFMM_M2L_CASE(T)                                                                                          \
+  if (tail == T) {                                                                                                 \
+    static size_t attr = 0;                                                                                        \
+    if (lds > attr) {                                                                                              \
+      if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l<T>), hipFuncAttributeMaxDynamicSharedMemorySize, \
+                              (int)lds) != hipSuccess)                                                             \
+        return false;                                                                                              \
+      attr = lds;                                                                                                  \
+    }                                                                                                              \
+    hipLaunchKernelGGL((k_m2l<T>), dim3(nitems), dim3(64 * row_blocks), lds, s, cores, core_rows, ldk, lds_ld / 4, \
+                       items, tgt_blk, src_blk, pair_offs, uhat, chat_part, part_stride);                          \
+    return true;                                                                                                   \
   }
+  KIFMM_M2L_CASE(0)
+  KIFMM_M2L_CASE(4)
+  KIFMM_M2L_CASE(8)
+  KIFMM_M2L_CASE(12)
 #undef KIFMM_M2L_CASE
+  return false;
+}
+
+// Sum of the eight source positions' partial sums, in a fixed order:
+// chat[i] = sum_p part[p][i] over n4 float4s.
+__global__ void k_sum_parts(const float4* __restrict__ part, float4* __restrict__ chat, long long n4,
+                            long long stride4) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n4) return;
+  float4 acc = part[i];
+#pragma unroll
+  for (int p = 1; p < 8; ++p) {
+    const float4 v = part[i + p * stride4];
+    acc.x += v.x;
+    acc.y += v.y;
+    acc.z += v.z;
+    acc.w += v.w;
+  }
+  chat[i] = acc;
+}
+
+void launch_sum_parts(const float* part, float* chat, long long n, long long stride, hipStream_t s) {
+  const long long n4 = n / 4;
+  if (n4 <= 0) return;
+  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<const float4*>(part), reinterpret_cast<float4*>(chat), n4, stride / 4);
 }
 
 // ------------------------------------------------------------- permute ---
@@ -269,14 +402,18 @@ void launch_p2m(const float4* pts, const int* start, const int* leaves, const fl
 //
 // The siblings' U lists together cover the 4 x 4 x 4 block of leaves around
 // the parent; `blk` lists their slots (x fastest, -1 = none).  Their sources
-// are staged once in LDS; each thread owns one target and walks the 27 block
-// entries around its own leaf.  Only the leaf's own entry can hold a source at
-// zero distance, so only that loop tests r > 0.  D2T evaluates the downward-
-// equivalent surface (alpha_outer r S_m relative to the leaf centre, density
-// d[m]) as n more sources, in centre-relative coordinates.  If a block's
-// sources exceed the LDS capacity they are read from global memory instead.
-constexpr int kP2PCap = 2560;   // sources staged per block (40 KB)
-constexpr int kP2PMaxN = 304;   // largest n (p <= 8) rounded up to 16
+// are staged once in LDS, each leaf's range padded to a multiple of 4 with
+// zero-charge dummies at (FLT_MAX, FLT_MAX, FLT_MAX): r^2 overflows to +inf,
+// rsqrt gives 0 and the dummy adds exactly zero.  Each thread owns one target
+// and walks the 27 block entries around its own leaf, 4 sources per step.  Only
+// the leaf's own entry can hold a source at zero distance, so only that loop
+// tests r > 0.  D2T evaluates the downward-equivalent surface (alpha_outer r S_m
+// relative to the leaf centre, density d[m]) as n more sources, in
+// centre-relative coordinates.  A block whose padded sources exceed `cap` reads
+// them from global memory instead.
+//
+// Dynamic LDS: [cap] float4 sources, [n] float4 surface points, [8 n] floats d.
+extern __shared__ float4 s_p2p[];
 
 __device__ __forceinline__ void p2p_pair(float xx, float xy, float xz, float4 y, float& phi, float& gx, float& gy,
                                          float& gz) {
@@ -304,16 +441,17 @@ __device__ __forceinline__ void p2p_pair_masked(float xx, float xy, float xz, fl
 }
 
 __global__ __launch_bounds__(256) void k_p2p(const float4* __restrict__ pts, const int* __restrict__ start,
-                                             const int* __restrict__ blk, int group_slots,
+                                             const int* __restrict__ blk, int group_slots, int cap,
                                              const float4* __restrict__ centers, const float* __restrict__ surf,
                                              int n, float alpha, const float* __restrict__ d, int ldd, int far,
                                              const int* __restrict__ order, float* __restrict__ pot,
                                              float* __restrict__ grad) {
-  __shared__ float4 s_src[kP2PCap];
-  __shared__ float4 s_de[kP2PMaxN];
-  __shared__ float s_d[8 * kP2PMaxN];
+  float4* s_src = s_p2p;
+  float4* s_de = s_p2p + cap;
+  float* s_d = reinterpret_cast<float*>(s_p2p + cap + n);
   __shared__ int s_off[65];
   __shared__ int s_slot[64];
+  __shared__ int s_cnt[64];
   __shared__ int s_cs[9];
 
   const int g = blockIdx.x;
@@ -323,21 +461,23 @@ __global__ __launch_bounds__(256) void k_p2p(const float4* __restrict__ pts, con
   if (tid < 64) {
     const int slot = blk[(size_t)g * 64 + tid];
     const int cnt = slot >= 0 ? start[slot + 1] - start[slot] : 0;
-    int incl = cnt;
+    int incl = (cnt + 3) & ~3;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const int v = __shfl_up(incl, o);
       if (tid >= o) incl += v;
     }
     s_slot[tid] = slot;
+    s_cnt[tid] = cnt;
     s_off[tid + 1] = incl;
     if (tid == 0) s_off[0] = 0;
   }
   if (tid <= group_slots) s_cs[tid] = start[c0 + tid];
   __syncthreads();
   const int total = s_off[64];
-  const bool in_lds = total <= kP2PCap;
+  const bool in_lds = total <= cap;
   if (in_lds) {
+    const float big = 3.402823466e38f;
     for (int i = tid; i < total; i += 256) {
       int lo = 0, hi = 64;  // entry e with s_off[e] <= i < s_off[e + 1]
       while (hi - lo > 1) {
@@ -345,7 +485,8 @@ __global__ __launch_bounds__(256) void k_p2p(const float4* __restrict__ pts, con
         if (s_off[mid] <= i) lo = mid;
         else hi = mid;
       }
-      s_src[i] = pts[start[s_slot[lo]] + (i - s_off[lo])];
+      const int r = i - s_off[lo];
+      s_src[i] = r < s_cnt[lo] ? pts[start[s_slot[lo]] + r] : make_float4(big, big, big, 0.f);
     }
   }
   const float sc = alpha * centers[2 * c0].w;
@@ -377,11 +518,24 @@ __global__ __launch_bounds__(256) void k_p2p(const float4* __restrict__ pts, con
           const bool self = (dx == 0) & (dy == 0) & (dz == 0);
           float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
           if (in_lds) {
-            const int a = s_off[e], b = s_off[e + 1];
-            if (self)
-              for (int j = a; j < b; ++j) p2p_pair_masked(x.x, x.y, x.z, s_src[j], phi, gx, gy, gz);
-            else
-              for (int j = a; j < b; ++j) p2p_pair(x.x, x.y, x.z, s_src[j], phi, gx, gy, gz);
+            const int a = s_off[e], b = s_off[e + 1];  // b - a is a multiple of 4
+            if (self) {
+              for (int j = a; j < b; j += 4) {
+                const float4 y0 = s_src[j], y1 = s_src[j + 1], y2 = s_src[j + 2], y3 = s_src[j + 3];
+                p2p_pair_masked(x.x, x.y, x.z, y0, phi, gx, gy, gz);
+                p2p_pair_masked(x.x, x.y, x.z, y1, phi, gx, gy, gz);
+                p2p_pair_masked(x.x, x.y, x.z, y2, phi, gx, gy, gz);
+                p2p_pair_masked(x.x, x.y, x.z, y3, phi, gx, gy, gz);
+              }
+            } else {
+              for (int j = a; j < b; j += 4) {
+                const float4 y0 = s_src[j], y1 = s_src[j + 1], y2 = s_src[j + 2], y3 = s_src[j + 3];
+                p2p_pair(x.x, x.y, x.z, y0, phi, gx, gy, gz);
+                p2p_pair(x.x, x.y, x.z, y1, phi, gx, gy, gz);
+                p2p_pair(x.x, x.y, x.z, y2, phi, gx, gy, gz);
+                p2p_pair(x.x, x.y, x.z, y3, phi, gx, gy, gz);
+              }
+            }
           } else {
             const int slot = s_slot[e];
             if (slot >= 0) {
@@ -414,23 +568,33 @@ __global__ __launch_bounds__(256) void k_p2p(const float4* __restrict__ pts, con
         agz += gz;
       }
     }
-    const float phi = (float)aphi, gx = (float)agx, gy = (float)agy, gz = (float)agz;
     const int oi = order[ti];
-    if (pot) pot[oi] = phi;
+    if (pot) pot[oi] = (float)aphi;
     if (grad) {
-      grad[3 * (size_t)oi] = gx;
-      grad[3 * (size_t)oi + 1] = gy;
-      grad[3 * (size_t)oi + 2] = gz;
+      grad[3 * (size_t)oi] = (float)agx;
+      grad[3 * (size_t)oi + 1] = (float)agy;
+      grad[3 * (size_t)oi + 2] = (float)agz;
     }
   }
 }
 
-void launch_p2p(const float4* pts, const int* start, const int* blk, int ngroups, int group_slots,
+size_t p2p_lds_bytes(int cap, int n) { return (size_t)cap * 16 + (size_t)n * 16 + (size_t)8 * n * 4; }
+
+bool launch_p2p(const float4* pts, const int* start, const int* blk, int ngroups, int group_slots, int cap,
                 const float4* centers, const float* surf, int n, float alpha, const float* d, int ldd, int far,
                 const int* order, float* pot, float* grad, hipStream_t s) {
-  if (ngroups <= 0) return;
-  hipLaunchKernelGGL(k_p2p, dim3(ngroups), dim3(256), 0, s, pts, start, blk, group_slots, centers, surf, n, alpha, d,
-                     ldd, far, order, pot, grad);
+  if (ngroups <= 0) return true;
+  const size_t lds = p2p_lds_bytes(cap, n);
+  static size_t attr = 0;
+  if (lds > attr) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_p2p), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess)
+      return false;
+    attr = lds;
+  }
+  hipLaunchKernelGGL(k_p2p, dim3(ngroups), dim3(256), lds, s, pts, start, blk, group_slots, cap, centers, surf, n,
+                     alpha, d, ldd, far, order, pot, grad);
+  return true;
 }
 
 }  // namespace kifmm

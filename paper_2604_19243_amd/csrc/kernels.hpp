@@ -6,27 +6,31 @@
 
 namespace kifmm {
 
-// A block of up to 64 M2L targets of one level and one sibling position.
-struct M2LTile {
-  int octant;     // position among siblings, 0..7 (selects the 189 offsets)
-  int i0;         // first target index within its group
-  int count;      // targets in this tile (<= 64)
-  int stride;     // targets in the group: row stride of the group's source table
-  int tgt_base;   // group's first entry in the target list
-  long long vsrc_base;  // group's first entry in the source table [189][stride]
+// An M2L work item (see k_m2l in kernels.hip): one aligned 4x4x4 block of
+// parents at one level, target sibling position o and source position o'.
+struct M2LItem {
+  int pair;      // 8 o + o'
+  int noffs;     // number of V-list offsets of the pair (19 to 26)
+  int part;      // o': which partial sum this item writes
+  int tgt_base;  // 64 target slots (or -1) in block position order, x fastest
+  int src_base;  // 216 source slots (or -1): position o' children of the 6x6x6 parents around the block
 };
 
 void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int* xrow, float* Y, int ldy,
                     const int* yrow, int nbox, int nout, int K, float alpha, int beta, hipStream_t s);
-void launch_m2l(int rb, const float* cores, int core_rows, int ldk, int K, const int* offidx, const float* uhat,
-                float* chat, const float* zero_row, const M2LTile* tiles, int ntiles, const int* tgt,
-                const int* vsrc, hipStream_t s);
+// Returns false if no kernel instance fits (rb, ldk).
+bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int lds_ld, const M2LItem* items, int nitems,
+                const int* tgt_blk, const int* src_blk, const int* pair_offs, const float* uhat, float* chat_part,
+                long long part_stride, hipStream_t s);
+void launch_sum_parts(const float* part, float* chat, long long n, long long stride, hipStream_t s);
 void launch_permute(float4* pts, const float* charges, const int* order, int n, hipStream_t s);
 void launch_p2m(const float4* pts, const int* start, const int* leaves, const float4* centers, const float* surf, int n,
                 float alpha, float* q, int ldq, int nleaves, hipStream_t s);
 // centers: per leaf slot two float4, (c_hi, r) and (c_lo, 0) with c = c_hi + c_lo.
 // blk: per parent group, the 64 leaf slots of the 4x4x4 block around it (-1 = none).
-void launch_p2p(const float4* pts, const int* start, const int* blk, int ngroups, int group_slots,
+// cap: sources staged in LDS per block (each leaf padded to a multiple of 4).
+size_t p2p_lds_bytes(int cap, int n);
+bool launch_p2p(const float4* pts, const int* start, const int* blk, int ngroups, int group_slots, int cap,
                 const float4* centers, const float* surf, int n, float alpha, const float* d, int ldd, int far,
                 const int* order, float* pot, float* grad, hipStream_t s);
 

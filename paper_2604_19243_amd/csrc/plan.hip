@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -42,24 +43,6 @@ T* dev_upload(std::vector<void*>& owned, const T* host, size_t count, const char
   if (host && count) hip_check(hipMemcpy(p, host, count * sizeof(T), hipMemcpyHostToDevice), what);
   else hip_check(hipMemset(p, 0, bytes), what);
   return static_cast<T*>(p);
-}
-
-// The 189 V-list offsets t = target - source available to a box at sibling
-// position `oct`, as indices into the ops offset table (Table 1: children of the
-// parent's colleagues that are not adjacent).
-std::vector<int> offsets_of_octant(const Ops& ops, int oct) {
-  std::vector<int> out;
-  const int b[3] = {oct & 1, (oct >> 1) & 1, (oct >> 2) & 1};
-  for (int t = 0; t < kNumOffsets; ++t) {
-    bool ok = true;
-    for (int d = 0; d < 3; ++d) {
-      const int a = b[d] - ops.offsets[3 * t + d];  // source position relative to the target's parent corner
-      const int pa = a >= 0 ? a / 2 : -((1 - a) / 2);  // floor(a / 2)
-      ok = ok && pa >= -1 && pa <= 1;
-    }
-    if (ok) out.push_back(t);
-  }
-  return out;
 }
 
 }  // namespace
@@ -194,6 +177,21 @@ Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
           }
     }
     P->d_blk = dev_upload(own, blk.data(), blk.size(), "leaf blocks");
+    // LDS capacity of the leaf kernel: the largest block's padded source count
+    // (rounded up to 64), limited so that at least two workgroups fit on a CU.
+    {
+      int64_t most = 0;
+      for (int64_t g = 0; g < ngroups; ++g) {
+        int64_t tot = 0;
+        for (int e = 0; e < 64; ++e) {
+          const int sl = blk[64 * g + e];
+          if (sl >= 0) tot += (start[sl + 1] - start[sl] + 3) & ~3;
+        }
+        most = std::max(most, tot);
+      }
+      const int64_t budget = (72 * 1024 - (int64_t)O.n * 16 - 8 * (int64_t)O.n * 4) / 16;
+      P->p2p_cap = (int)std::max<int64_t>(64, std::min<int64_t>((most + 63) / 64 * 64, budget / 64 * 64));
+    }
     // U-list pair count (target, source), for throughput accounting.
     int64_t pairs = 0;
     for (int64_t i = 0; i < NBL; ++i) {
@@ -232,6 +230,8 @@ Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
       P->d_d = dev_upload<float>(own, nullptr, (size_t)total * nst, "d");
       P->d_uhat = dev_upload<float>(own, nullptr, (size_t)total * kst, "uhat");
       P->d_chat = dev_upload<float>(own, nullptr, (size_t)total * kst, "chat");
+      // M2L partial sums, one per source position among siblings: [8][total][kst].
+      P->d_chat_part = dev_upload<float>(own, nullptr, (size_t)8 * total * kst, "chat parts");
       P->d_zero = dev_upload<float>(own, nullptr, (size_t)kst + nst, "zero row");
 
       auto pad_rows = [](int rows) { return round_up(rows, 64); };
@@ -269,11 +269,9 @@ Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
           for (int c = 0; c < n; ++c)
             wl[((size_t)oc * nst + i) * nst + c] = (float)O.l2l[((size_t)oc * n + i) * n + c];
       P->d_l2l = dev_upload(own, wl.data(), wl.size(), "l2l");
-      // M2L cores: [316][core_rows][kst], row blocks of 16 split over two waves.
-      const int blocks = kst / 16 + (kst % 16 ? 1 : 0);
-      P->m2l_rb = (blocks + 1) / 2;
-      require(P->m2l_rb <= 10, "M2L rank too large for the M2L kernel (k <= 320)");
-      P->core_rows = 32 * P->m2l_rb;
+      // M2L cores: [316][core_rows][kst], rows padded to whole 16-row blocks (one wave each).
+      P->m2l_rb = kst / 16 + (kst % 16 ? 1 : 0);
+      P->core_rows = 16 * P->m2l_rb;
       std::vector<float> wc((size_t)kNumOffsets * P->core_rows * kst, 0.f);
       for (int t = 0; t < kNumOffsets; ++t)
         for (int a = 0; a < k; ++a)
@@ -286,62 +284,120 @@ Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
       for (int l = 2; l <= L; ++l)
         P->d_nbslot[l] = dev_upload(own, slot_of[l].data(), slot_of[l].size(), "box slots");
 
-      // V lists: per (level, sibling position) group, targets and a [189][T] source table.
-      std::vector<int> offidx(8 * kOffsetsPerOctant);
-      std::vector<std::vector<int>> oct_offs(8);
-      for (int oc = 0; oc < 8; ++oc) {
-        oct_offs[oc] = offsets_of_octant(O, oc);
-        require((int)oct_offs[oc].size() == kOffsetsPerOctant, "internal: V-list offsets per position != 189");
-        std::copy(oct_offs[oc].begin(), oct_offs[oc].end(), offidx.begin() + oc * kOffsetsPerOctant);
-      }
-      P->d_offidx = dev_upload(own, offidx.data(), offidx.size(), "offset index");
-      std::vector<int> tgt, vsrc;
-      std::vector<M2LTile> tiles;
-      std::vector<std::vector<M2LTile>> group_tiles;
-      int64_t vpairs = 0;
-      for (int l = L; l >= 2; --l) {
-        const int64_t ml = 1ll << l;
-        std::vector<std::vector<int>> by_oct(8);
-        for (size_t i = 0; i < T.keys[l].size(); ++i) by_oct[T.keys[l][i] & 7].push_back((int)i);
-        std::vector<std::vector<M2LTile>> lt(8);
-        size_t most = 0;
-        for (int oc = 0; oc < 8; ++oc) {
-          const auto& members = by_oct[oc];
-          const int cnt = (int)members.size();
-          if (!cnt) continue;
-          const int tgt_base = (int)tgt.size();
-          const long long vs_base = (long long)vsrc.size();
-          for (int i : members) tgt.push_back((int)(P->base[l] + slot_of[l][i]));
-          vsrc.resize(vsrc.size() + (size_t)kOffsetsPerOctant * cnt, -1);
-          for (int jj = 0; jj < kOffsetsPerOctant; ++jj) {
-            const int t = oct_offs[oc][jj];
-            for (int ii = 0; ii < cnt; ++ii) {
-              int32_t c[3];
-              morton_decode(T.keys[l][members[ii]], l, c);
-              const int64_t x = c[0] - O.offsets[3 * t], y = c[1] - O.offsets[3 * t + 1], z = c[2] - O.offsets[3 * t + 2];
-              if (x < 0 || y < 0 || z < 0 || x >= ml || y >= ml || z >= ml) continue;
-              const int64_t j = T.find(l, morton_encode((uint32_t)x, (uint32_t)y, (uint32_t)z, l));
-              if (j < 0) continue;
-              vsrc[vs_base + (size_t)jj * cnt + ii] = (int)(P->base[l] + slot_of[l][j]);
-              ++vpairs;
-            }
+      // VLI work items (see k_m2l).  For target position o and source position o'
+      // (x bit 0, y bit 1, z bit 2) the V-list offsets are the parent shifts d in
+      // {-1,0,1}^3 whose offset t = o - o' - 2 d (per axis) has max |t| >= 2
+      // (Table 1: children of the parent's colleagues, not adjacent).
+      std::vector<int> pair_offs(64 * 27, 0), pair_cnt(64, 0);
+      {
+        auto offset_index = [&](int tx, int ty, int tz) {
+          for (int t = 0; t < kNumOffsets; ++t)
+            if (O.offsets[3 * t] == tx && O.offsets[3 * t + 1] == ty && O.offsets[3 * t + 2] == tz) return t;
+          fail(KIFMM_E_INVALID, "internal: V-list offset not in the operator table");
+        };
+        int total_offs = 0;
+        for (int o = 0; o < 8; ++o)
+          for (int o2 = 0; o2 < 8; ++o2) {
+            const int pr = 8 * o + o2;
+            for (int dz = -1; dz <= 1; ++dz)
+              for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                  const int t[3] = {(o & 1) - (o2 & 1) - 2 * dx, ((o >> 1) & 1) - ((o2 >> 1) & 1) - 2 * dy,
+                                    ((o >> 2) & 1) - ((o2 >> 2) & 1) - 2 * dz};
+                  if (std::max({std::abs(t[0]), std::abs(t[1]), std::abs(t[2])}) < 2) continue;
+                  const int e = (dx + 1) + 6 * (dy + 1) + 36 * (dz + 1);
+                  pair_offs[27 * pr + pair_cnt[pr]++] = offset_index(t[0], t[1], t[2]) | (e << 9);
+                }
+            total_offs += pair_cnt[pr];
           }
-          for (int i0 = 0; i0 < cnt; i0 += 64)
-            lt[oc].push_back(M2LTile{oc, i0, std::min(64, cnt - i0), cnt, tgt_base, vs_base});
-          most = std::max(most, lt[oc].size());
-        }
-        // Interleave sibling positions so that consecutive workgroups (spread over
-        // the XCDs round-robin) use the same offset set per XCD when counts agree.
-        for (size_t ib = 0; ib < most; ++ib)
-          for (int oc = 0; oc < 8; ++oc)
-            if (ib < lt[oc].size()) tiles.push_back(lt[oc][ib]);
+        require(total_offs == 8 * kOffsetsPerOctant, "internal: V-list offsets per position != 189");
       }
+      P->d_pair_offs = dev_upload(own, pair_offs.data(), pair_offs.size(), "m2l pair offsets");
+      std::vector<int> tgt_blk, src_blk;
+      std::vector<std::vector<M2LItem>> per_xcd(8);
+      int64_t vpairs = 0, ntargets = 0;
+      for (int l = L; l >= 2; --l) {
+        const int64_t mp = 1ll << (l - 1);  // parents per axis
+        const int64_t ml = 1ll << l;
+        // aligned 4x4x4 blocks of parents that hold at least one non-empty parent
+        std::vector<uint64_t> blocks;
+        for (uint64_t pk : T.keys[l - 1]) {
+          const uint64_t bk = pk >> 6;
+          if (blocks.empty() || blocks.back() != bk) blocks.push_back(bk);
+        }
+        for (uint64_t bk : blocks) {
+          int32_t bc[3];
+          morton_decode(bk, std::max(l - 3, 0), bc);
+          const int64_t px0 = 4 * (int64_t)bc[0], py0 = 4 * (int64_t)bc[1], pz0 = 4 * (int64_t)bc[2];
+          auto box_slot = [&](int64_t x, int64_t y, int64_t z) -> int {
+            if (x < 0 || y < 0 || z < 0 || x >= ml || y >= ml || z >= ml) return -1;
+            const int64_t j = T.find(l, morton_encode((uint32_t)x, (uint32_t)y, (uint32_t)z, l));
+            return j < 0 ? -1 : (int)(P->base[l] + slot_of[l][j]);
+          };
+          int src_base[8];
+          for (int o2 = 0; o2 < 8; ++o2) {
+            src_base[o2] = (int)src_blk.size();
+            for (int ez = 0; ez < 6; ++ez)
+              for (int ey = 0; ey < 6; ++ey)
+                for (int ex = 0; ex < 6; ++ex) {
+                  const int64_t x = px0 - 1 + ex, y = py0 - 1 + ey, z = pz0 - 1 + ez;
+                  const bool inside = x >= 0 && y >= 0 && z >= 0 && x < mp && y < mp && z < mp;
+                  src_blk.push_back(inside ? box_slot(2 * x + (o2 & 1), 2 * y + ((o2 >> 1) & 1),
+                                                      2 * z + ((o2 >> 2) & 1))
+                                           : -1);
+                }
+          }
+          for (int o = 0; o < 8; ++o) {
+            const int tgt_base = (int)tgt_blk.size();
+            int count = 0;
+            for (int pi = 0; pi < 64; ++pi) {
+              const int64_t x = px0 + (pi & 3), y = py0 + ((pi >> 2) & 3), z = pz0 + (pi >> 4);
+              const bool inside = x < mp && y < mp && z < mp;
+              const int sl = inside ? box_slot(2 * x + (o & 1), 2 * y + ((o >> 1) & 1), 2 * z + ((o >> 2) & 1)) : -1;
+              tgt_blk.push_back(sl);
+              if (sl < 0) continue;
+              ++count;
+              // V-list pairs of this target, for accounting
+              for (int o2 = 0; o2 < 8; ++o2)
+                for (int j = 0; j < pair_cnt[8 * o + o2]; ++j) {
+                  const int e = pair_offs[27 * (8 * o + o2) + j] >> 9;
+                  const int ex = e % 6, ey = (e / 6) % 6, ez = e / 36;  // (d + 1) per axis, in 0..2
+                  const int r = ((pi & 3) + ex) + 6 * (((pi >> 2) & 3) + ey) + 36 * ((pi >> 4) + ez);
+                  vpairs += src_blk[src_base[o2] + r] >= 0;
+                }
+            }
+            if (!count) {
+              tgt_blk.resize(tgt_base);
+              continue;
+            }
+            ntargets += count;
+            // items of one (o, o') pair go to one XCD: source position o' -> XCD o'
+            for (int o2 = 0; o2 < 8; ++o2)
+              per_xcd[o2].push_back(M2LItem{8 * o + o2, pair_cnt[8 * o + o2], o2, tgt_base, src_base[o2]});
+          }
+        }
+      }
+      // Workgroups are dealt to the 8 XCDs round-robin: item b runs on XCD b % 8.
+      // Within an XCD's list, items are ordered by (o, o') pair, so that the XCD's
+      // L2 holds the ~24 translation cores of the pair its CUs are working on.
+      for (auto& v : per_xcd)
+        std::stable_sort(v.begin(), v.end(), [](const M2LItem& a, const M2LItem& b) { return a.pair < b.pair; });
+      std::vector<M2LItem> items;
+      size_t most = 0;
+      for (auto& v : per_xcd) most = std::max(most, v.size());
+      for (size_t i = 0; i < most; ++i)
+        for (int x = 0; x < 8; ++x)
+          if (i < per_xcd[x].size()) items.push_back(per_xcd[x][i]);
       P->m2l_pairs = vpairs;
-      P->m2l_targets = (int64_t)tgt.size();
-      P->n_tiles = (int)tiles.size();
-      P->d_tgt = dev_upload(own, tgt.data(), tgt.size(), "m2l targets");
-      P->d_vsrc = dev_upload(own, vsrc.data(), vsrc.size(), "m2l sources");
-      P->d_tiles = dev_upload(own, tiles.data(), tiles.size(), "m2l tiles");
+      P->m2l_targets = ntargets;
+      P->n_items = (int)items.size();
+      // LDS row stride of one 64-k slab of the staged sources: 68 floats, an odd
+      // number of 16-byte units, so 16 lanes reading 16 rows hit distinct banks.
+      P->m2l_lds_ld = 68;
+      require(P->m2l_rb <= 16, "M2L rank too large for the M2L kernel");
+      P->d_tgt_blk = dev_upload(own, tgt_blk.data(), tgt_blk.size(), "m2l block targets");
+      P->d_src_blk = dev_upload(own, src_blk.data(), src_blk.size(), "m2l block sources");
+      P->d_items = dev_upload(own, items.data(), items.size(), "m2l items");
       P->keys_per_level.assign(L + 1, 0);
       for (int l = 0; l <= L; ++l) P->keys_per_level[l] = (int64_t)T.keys[l].size();
       P->slot_of = slot_of;
@@ -441,8 +497,10 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
                    0, st);
     P->stage_end(KIFMM_STAGE_COMPRESS, st);
     P->stage_begin(KIFMM_STAGE_M2L, st);
-    launch_m2l(P->m2l_rb, P->d_cores, P->core_rows, kst, kst, P->d_offidx, P->d_uhat, P->d_chat, P->d_zero,
-               P->d_tiles, P->n_tiles, P->d_tgt, P->d_vsrc, st);
+    if (!launch_m2l(P->m2l_rb, P->d_cores, P->core_rows, kst, P->m2l_lds_ld, P->d_items, P->n_items, P->d_tgt_blk,
+                    P->d_src_blk, P->d_pair_offs, P->d_uhat, P->d_chat_part, (long long)P->total_slots * kst, st))
+      fail(KIFMM_E_DEVICE, "M2L kernel configuration not available");
+    launch_sum_parts(P->d_chat_part, P->d_chat, (long long)P->total_slots * kst, (long long)P->total_slots * kst, st);
     P->stage_end(KIFMM_STAGE_M2L, st);
     // (2c) post (DC2E U_k) and D2D, coarse to fine.
     P->stage_begin(KIFMM_STAGE_L2L, st);
@@ -459,9 +517,10 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
   }
   // (3b) D2T + (3c) ULI, written in input order.
   P->stage_begin(KIFMM_STAGE_P2P, st);
-  launch_p2p(P->d_pts, P->d_start, P->d_blk, (int)P->n_groups, P->group_slots, P->d_centers, P->d_surf, P->n,
-             (float)kAlphaOuter, P->far ? P->d_d + P->base[L] * P->nst : nullptr, P->nst, P->far ? 1 : 0,
-             P->d_order, pot, grad, st);
+  if (!launch_p2p(P->d_pts, P->d_start, P->d_blk, (int)P->n_groups, P->group_slots, P->p2p_cap, P->d_centers,
+                  P->d_surf, P->n, (float)kAlphaOuter, P->far ? P->d_d + P->base[L] * P->nst : nullptr, P->nst,
+                  P->far ? 1 : 0, P->d_order, pot, grad, st))
+    fail(KIFMM_E_DEVICE, "leaf kernel configuration not available");
   P->stage_end(KIFMM_STAGE_P2P, st);
   hip_check(hipGetLastError(), "kernel launch");
   if (prev != P->device) (void)hipSetDevice(prev);

@@ -23,7 +23,7 @@ struct Plan : Object {
   std::vector<std::vector<int>> slot_of;
   int64_t total_slots = 0, n_leaves = 0;
   int64_t p2p_pairs = 0, m2l_pairs = 0, m2l_targets = 0;
-  int m2l_rb = 0, core_rows = 0, n_tiles = 0;
+  int m2l_rb = 0, core_rows = 0, n_items = 0, m2l_lds_ld = 0;
 
   std::vector<void*> owned;  // device allocations
   float4* d_pts = nullptr;
@@ -33,6 +33,7 @@ struct Plan : Object {
   float4* d_centers = nullptr;
   int* d_blk = nullptr;
   int64_t n_groups = 0;
+  int p2p_cap = 0;
   int group_slots = 8;
   float* d_surf = nullptr;
   float *d_q = nullptr, *d_t = nullptr, *d_u = nullptr, *d_d = nullptr, *d_uhat = nullptr, *d_chat = nullptr;
@@ -40,10 +41,11 @@ struct Plan : Object {
   float *d_f1 = nullptr, *d_f2 = nullptr, *d_m2m = nullptr, *d_vt = nullptr, *d_post = nullptr, *d_l2l = nullptr;
   float* d_cores = nullptr;
   std::vector<int*> d_nbslot;
-  int* d_offidx = nullptr;
-  int* d_tgt = nullptr;
-  int* d_vsrc = nullptr;
-  M2LTile* d_tiles = nullptr;
+  float* d_chat_part = nullptr;
+  int* d_pair_offs = nullptr;
+  int* d_tgt_blk = nullptr;
+  int* d_src_blk = nullptr;
+  M2LItem* d_items = nullptr;
 
   // Stage timing: a ring of event pairs per call, read back only when full or
   // on request, so timed evaluates never wait on the host.

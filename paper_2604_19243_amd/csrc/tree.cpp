@@ -20,7 +20,8 @@ Tree* build_tree(const float* xyz, int64_t n, int depth, const double* cube) {
   require(xyz != nullptr, "xyz is null");
   require(n >= 1 && n < (1ll << 31), "n must be in [1, 2^31)");
   require(depth >= 0 && depth <= KIFMM_MAX_DEPTH, "depth must be in [0, " + std::to_string(KIFMM_MAX_DEPTH) + "]");
-  for (int64_t i = 0; i < 3 * n; ++i) require(std::isfinite(xyz[i]), "non-finite coordinate");
+  for (int64_t i = 0; i < 3 * n; ++i)
+    require(std::isfinite(xyz[i]) && std::fabs(xyz[i]) < 1e30f, "coordinates must be finite and below 1e30 in magnitude");
 
   Tree* t = new Tree();
   try {
