@@ -199,8 +199,8 @@ enum {
   KIFMM_STAGE_UC2E = 2,    /* upward-check field -> upward density, two factors */
   KIFMM_STAGE_M2M = 3,     /* U2U, all levels */
   KIFMM_STAGE_COMPRESS = 4,/* u -> V_k^T u, levels 2..L */
-  KIFMM_STAGE_M2L = 5,     /* compressed VLI over all levels */
-  KIFMM_STAGE_L2L = 6,     /* post (DC2E U_k) and D2D, levels 2..L */
+  KIFMM_STAGE_M2L = 5,     /* compressed VLI over all levels (one kernel) */
+  KIFMM_STAGE_L2L = 6,     /* sum of M2L partial sums, post (DC2E U_k) and D2D, levels 2..L */
   KIFMM_STAGE_P2P = 7,     /* fused D2T + ULI at the leaves, then un-permute */
   KIFMM_N_STAGES = 8
 };

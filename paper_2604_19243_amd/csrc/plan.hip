@@ -500,10 +500,10 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
     if (!launch_m2l(P->m2l_rb, P->d_cores, P->core_rows, kst, P->m2l_lds_ld, P->d_items, P->n_items, P->d_tgt_blk,
                     P->d_src_blk, P->d_pair_offs, P->d_uhat, P->d_chat_part, (long long)P->total_slots * kst, st))
       fail(KIFMM_E_DEVICE, "M2L kernel configuration not available");
-    launch_sum_parts(P->d_chat_part, P->d_chat, (long long)P->total_slots * kst, (long long)P->total_slots * kst, st);
     P->stage_end(KIFMM_STAGE_M2L, st);
-    // (2c) post (DC2E U_k) and D2D, coarse to fine.
+    // (2c) sum of the M2L partial sums, post (DC2E U_k) and D2D, coarse to fine.
     P->stage_begin(KIFMM_STAGE_L2L, st);
+    launch_sum_parts(P->d_chat_part, P->d_chat, (long long)P->total_slots * kst, (long long)P->total_slots * kst, st);
     for (int l = 2; l <= L; ++l) {
       launch_gemm_nt(P->d_post, kst, P->d_chat + P->base[l] * kst, kst, nullptr, P->d_d + P->base[l] * nst, nst,
                      nullptr, (int)P->slots[l], nst, kst, 1.0f, 0, st);
