@@ -116,3 +116,58 @@ def test_stream_and_outputs_subset():
     with pytest.raises(kifmm.KifmmError):
         f.evaluate(sd, None, None)
     f.close()
+
+
+@pytest.mark.parametrize("p,n,depth", [
+    (2, 3_000, 3),    # n = 8 surface points, rank < 16: plain 4-k M2L steps
+    (3, 5_000, 3),    # k = 26: one 16-k chunk and a 12-k tail
+    (7, 8_000, 3),    # k = 122 -> 124: two slabs, tail 12
+    (8, 8_000, 3),    # n = 296, k = 124
+])
+def test_expansion_orders(p, n, depth):
+    log(f"order p={p} n={n} depth={depth}")
+    x = workloads.points("cube", n, 700 + p)
+    s = workloads.charges("uniform11", n, 800 + p)
+    phi, g, f = gpu_evaluate(x, s, depth, p, UNIT)
+    k = kifmm.kifmm_ops_get_info(f.ops)["rank_m2l"]
+    f.close()
+    rphi, rg, _, ops = oracle_evaluate(x, s, depth, p, UNIT)
+    assert ops.compression(1.0)[0].shape[1] == k
+    e, eg = rel_l2(phi, rphi), rel_l2(g, rg)
+    log(f"  rel-L2 phi {e:.3e} grad {eg:.3e} (k={k})")
+    assert e < TOL and eg < TOL
+
+
+@pytest.mark.parametrize("depth", [8, 10])
+def test_deep_sparse_trees(depth):
+    # Maximum depth: almost every leaf holds one point and most boxes are empty.
+    log(f"deep depth={depth}")
+    n = 600
+    x = workloads.points("sphere", n, 900 + depth)
+    s = workloads.charges("uniform01", n, 901 + depth)
+    phi, g, f = gpu_evaluate(x, s, depth, 4, (0.0, 0.0, 0.0, 1.0))
+    f.close()
+    rphi, rg, _, _ = oracle_evaluate(x, s, depth, 4, (0.0, 0.0, 0.0, 1.0))
+    e, eg = rel_l2(phi, rphi), rel_l2(g, rg)
+    log(f"  rel-L2 phi {e:.3e} grad {eg:.3e}")
+    assert e < TOL and eg < TOL
+
+
+def test_gradient_only_and_auto_cube():
+    import torch
+    log("gradient only, automatic cube")
+    n = 6000
+    x = (workloads.points("cube", n, 31) * np.float32(3.0) - np.float32(1.0)).astype(np.float32)
+    s = workloads.charges("normal", n, 32)
+    f = kifmm.FMM(x, 3, 5, cube=None)
+    dev = torch.device("cuda:0")
+    grad = torch.zeros(n, 3, device=dev)
+    f.evaluate(torch.from_numpy(s).to(dev), None, grad)
+    torch.cuda.synchronize()
+    info = kifmm.kifmm_tree_get_info(f.tree)
+    f.close()
+    c, r = info["center"], info["half_width"]
+    _, rg, _, _ = oracle_evaluate(x, s, 3, 5, (c[0], c[1], c[2], r))
+    eg = rel_l2(grad.cpu().double().numpy(), rg)
+    log(f"  rel-L2 grad {eg:.3e}")
+    assert eg < TOL
