@@ -81,7 +81,7 @@ typedef struct {
  * the Morton key of their leaf (three bits per level, Section 2.1), ties kept
  * in input order.
  *
- *   xyz    host, [n][3] float, point coordinates (finite), read during the call.
+ *   xyz    host, [n][3] float, point coordinates (finite, |x| < 1e30), read during the call.
  *   n      number of points, 1 <= n < 2^31.
  *   depth  leaf level L, 0 <= L <= KIFMM_MAX_DEPTH.
  *   cube   host, {cx, cy, cz, half_width} in double, or NULL.  NULL encloses
@@ -161,9 +161,15 @@ kifmm_status kifmm_ops_destroy(kifmm_ops ops);
 
 /* ---------------------------------------------------------------- plan --- */
 
-/* Flags of kifmm_plan_create: which outputs evaluate may be asked for. */
+/* Flags of kifmm_plan_create.  KIFMM_POTENTIAL / KIFMM_GRADIENT: which outputs
+ * evaluate may be asked for.  By default the U-list sum (ULI), which does not
+ * depend on the far field (Section 2.2), runs on a stream owned by the plan,
+ * forked from and joined back into the caller's stream with events, so that it
+ * overlaps the upward pass and M2L; KIFMM_SERIAL keeps every kernel on the
+ * caller's stream (with the near and far leaf sums fused in one kernel). */
 #define KIFMM_POTENTIAL 1u
 #define KIFMM_GRADIENT 2u
+#define KIFMM_SERIAL 4u
 
 /*
  * Place a tree and its operators on HIP device `device`: uploads the sorted
@@ -201,8 +207,9 @@ enum {
   KIFMM_STAGE_COMPRESS = 4,/* u -> V_k^T u, levels 2..L */
   KIFMM_STAGE_M2L = 5,     /* compressed VLI over all levels (one kernel) */
   KIFMM_STAGE_L2L = 6,     /* sum of M2L partial sums, post (DC2E U_k) and D2D, levels 2..L */
-  KIFMM_STAGE_P2P = 7,     /* fused D2T + ULI at the leaves, then un-permute */
-  KIFMM_N_STAGES = 8
+  KIFMM_STAGE_P2P = 7,     /* ULI at the leaves (on the plan's stream), or fused D2T + ULI with KIFMM_SERIAL */
+  KIFMM_STAGE_L2P = 8,     /* D2T added to the ULI result, written in input order (not with KIFMM_SERIAL) */
+  KIFMM_N_STAGES = 9
 };
 
 /* When enabled, evaluate records HIP events around every stage on its stream

@@ -115,141 +115,142 @@ void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int*
 // of parent boxes, target position o, source position o').  Its targets are the
 // children at position o of the block's parents (up to 64); its sources are the
 // children at position o' of the 6 x 6 x 6 parents around the block (216 rows,
-// staged once in LDS, missing boxes as zero rows).  Every V-list offset between
-// such a target and source is a parent shift d in {-1,0,1}^3, i.e. a fixed row
-// shift in the staged block, and the item computes for each target
+// staged in LDS, missing boxes as zero rows).  Every V-list offset between such
+// a target and source is a parent shift d in {-1,0,1}^3, i.e. a fixed row shift
+// in the staged block, and the item computes for each target
 //   chat_part[o'][target] = sum_{d} C_{t(o, o', d)} uhat[child o' of (parent + d)].
 // The eight source positions' partial sums are added afterwards (k_sum_parts).
 //
-// One wave per 16 output rows (blockDim = 64 * ceil(k / 16)); each wave covers
-// all 64 targets as four 16-column blocks.  Operator rows are read from global
-// memory (L2: the items of one (o, o') pair are dealt to one XCD) exactly once
-// per workgroup, sources from LDS.  The k loop runs over "chunks" of 16 k (plus
-// a TAIL of 4, 8 or 12 k per offset) with the next chunk's operands loaded into
-// a second register set while the current one feeds the matrix cores.
-template <int TAIL>
+// Matrix-core mapping (v_mfma_f32_32x32x2_f32): one wave per 32 output rows,
+// covering the 64 targets as two 32-column blocks.  The k dimension (padded
+// with zeros to a multiple of 8) runs in "chunks" of 8: lane (i, h) = (l % 32,
+// l / 32) loads A[i][8c + 4h .. +3] and B^T[j][8c + 4h .. +3] as float4 and the
+// four MFMA steps contract k = 8c + 4h + r (the order of the sum over k is
+// free).  Sources are staged in LDS in slabs of 40 k; operator rows are read
+// from global memory (L2: the items of one (o, o') pair are dealt to one XCD);
+// each chunk's operands are fetched two chunks ahead of their use.
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ v16f mfma32(float a, float b, v16f c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
 struct M2LRegs {
   float4 a;
-  float4 b[4];
-  float at[TAIL / 4 > 0 ? TAIL / 4 : 1];
-  float bt[TAIL / 4 > 0 ? TAIL / 4 : 1][4];
+  float4 b[2];
 };
 
-extern __shared__ float4 s_m2l[];  // [217][ld4] float4: the current k-slab of the staged sources
+extern __shared__ float4 s_m2l[];  // [216][ld4] float4: the current k-slab of the staged sources
 
-constexpr int kM2LSlab = 64;  // k per LDS slab
+constexpr int kM2LSlab = 40;  // k per LDS slab: 5 chunks of 8; the row stride 44 is an odd number of float4
 
-// Operands of chunk c (16 k) of the current slab; `ka` is the slab's first k in
-// the operator row.  The tail of the last slab is fetched with every chunk (used
-// only with the last one), so no load is conditional and wait counts stay exact.
-template <int TAIL>
-__device__ __forceinline__ void m2l_load(M2LRegs<TAIL>& r, const float* __restrict__ arow_ptr, const int* brow,
-                                         int c, int nch, int ld4, int q) {
-  r.a = *reinterpret_cast<const float4*>(arow_ptr + 16 * c + 4 * q);
-#pragma unroll
-  for (int nb = 0; nb < 4; ++nb) r.b[nb] = s_m2l[brow[nb] * ld4 + 4 * c + q];
-#pragma unroll
-  for (int st = 0; st < TAIL / 4; ++st) {
-    r.at[st] = arow_ptr[16 * nch + 4 * st + q];
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb)
-      r.bt[st][nb] = reinterpret_cast<const float*>(s_m2l)[4 * (brow[nb] * ld4 + 4 * nch + st) + q];
-  }
-}
-
-template <int TAIL>
-__device__ __forceinline__ void m2l_compute(const M2LRegs<TAIL>& r, v4f* acc, bool tail) {
-#pragma unroll
-  for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16(r.a.x, r.b[nb].x, acc[nb]);
-#pragma unroll
-  for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16(r.a.y, r.b[nb].y, acc[nb]);
-#pragma unroll
-  for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16(r.a.z, r.b[nb].z, acc[nb]);
-#pragma unroll
-  for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16(r.a.w, r.b[nb].w, acc[nb]);
-  if (TAIL && tail) {
-#pragma unroll
-    for (int st = 0; st < TAIL / 4; ++st)
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16(r.at[st], r.bt[st][nb], acc[nb]);
-  }
-}
-
-// All offsets of the item over one k-slab: nch full chunks per offset (and the
-// TAIL after the last chunk when `with_tail`), prefetching one chunk ahead.
-template <int TAIL>
-__device__ __forceinline__ void m2l_slab(v4f* acc, const float* abase, size_t core_stride, int po_reg, int noffs,
-                                         const int* bbase, int nch, bool with_tail, int ld4, int q) {
-  const int nv = noffs * nch;
-  auto setup = [&](int j, const float*& ap, int* brow) {
+// Position (offset j, chunk c) in an item's sequence of 8-k chunks over one
+// slab, with the offset's wave-uniform address parts.  Stepping past the end
+// stays on the last chunk, so the loads it drives remain unconditional.
+struct M2LCursor {
+  int j, c, nch, noffs, ld4, po_reg;
+  size_t core_stride, aoff;
+  int sh;
+  __device__ __forceinline__ void set_offset() {
     const int e = __builtin_amdgcn_readlane(po_reg, j);
-    ap = abase + (e & 511) * core_stride;
+    aoff = (size_t)(e & 511) * core_stride;
+    sh = (e >> 9) * ld4;
+  }
+  __device__ __forceinline__ void next() {
+    if (++c == nch) {
+      if (j + 1 < noffs) {
+        c = 0;
+        ++j;
+        set_offset();
+      } else {
+        c = nch - 1;
+      }
+    }
+  }
+};
+
+// Operands of the cursor's chunk.  alane: this lane's operator row and k half at
+// the slab start; bq[nb]: the float4 index of its target's staged row plus h.
+__device__ __forceinline__ void m2l_load(M2LRegs& r, const float* __restrict__ alane, const int* bq,
+                                         const M2LCursor& cu) {
+  r.a = *reinterpret_cast<const float4*>(alane + cu.aoff + 8 * cu.c);
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) brow[nb] = bbase[nb] + (e >> 9);
-  };
-  M2LRegs<TAIL> r0, r1;
-  int j0 = 0, c0 = 0;
-  int brow0[4], brow1[4];
-  const float* ap0;
-  const float* ap1;
-  setup(0, ap0, brow0);
-  m2l_load(r0, ap0, brow0, 0, nch, ld4, q);
-  for (int v = 0; v < nv; v += 2) {
-    int j1 = c0 + 1 < nch ? j0 : j0 + 1;
-    int c1 = c0 + 1 < nch ? c0 + 1 : 0;
-    if (j1 >= noffs) {
-      j1 = noffs - 1;
-      c1 = nch - 1;
-    }
-    setup(j1, ap1, brow1);
-    m2l_load(r1, ap1, brow1, c1, nch, ld4, q);
+  for (int nb = 0; nb < 2; ++nb) r.b[nb] = s_m2l[bq[nb] + cu.sh + 2 * cu.c];
+}
+
+__device__ __forceinline__ void m2l_compute(const M2LRegs& r, v16f* acc) {
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) acc[nb] = mfma32(r.a.x, r.b[nb].x, acc[nb]);
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) acc[nb] = mfma32(r.a.y, r.b[nb].y, acc[nb]);
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) acc[nb] = mfma32(r.a.z, r.b[nb].z, acc[nb]);
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) acc[nb] = mfma32(r.a.w, r.b[nb].w, acc[nb]);
+}
+
+// All offsets of the item over one slab of nch chunks, with three register sets.
+__device__ __forceinline__ void m2l_slab(v16f* acc, const float* alane, size_t core_stride, int po_reg, int noffs,
+                                         const int* bq, int nch, int ld4) {
+  const int nv = noffs * nch;
+  M2LCursor cu{0, 0, nch, noffs, ld4, po_reg, core_stride, 0, 0};
+  cu.set_offset();
+  M2LRegs r0, r1, r2;
+  m2l_load(r0, alane, bq, cu);
+  cu.next();
+  m2l_load(r1, alane, bq, cu);
+  cu.next();
+  for (int v = 0; v < nv; v += 3) {
+    m2l_load(r2, alane, bq, cu);
+    cu.next();
     __builtin_amdgcn_sched_barrier(0);
-    m2l_compute(r0, acc, with_tail && c0 == nch - 1);
+    m2l_compute(r0, acc);
     __builtin_amdgcn_sched_barrier(0);
-    j0 = c1 + 1 < nch ? j1 : j1 + 1;
-    c0 = c1 + 1 < nch ? c1 + 1 : 0;
-    if (j0 >= noffs) {
-      j0 = noffs - 1;
-      c0 = nch - 1;
-    }
-    setup(j0, ap0, brow0);
-    m2l_load(r0, ap0, brow0, c0, nch, ld4, q);
+    m2l_load(r0, alane, bq, cu);
+    cu.next();
     __builtin_amdgcn_sched_barrier(0);
-    if (v + 1 < nv) m2l_compute(r1, acc, with_tail && c1 == nch - 1);
+    if (v + 1 < nv) m2l_compute(r1, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    m2l_load(r1, alane, bq, cu);
+    cu.next();
+    __builtin_amdgcn_sched_barrier(0);
+    if (v + 2 < nv) m2l_compute(r2, acc);
     __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-template <int TAIL>
-__global__ __launch_bounds__(1024) void k_m2l(const float* __restrict__ cores, int core_rows, int ldk, int ld4,
-                                              const M2LItem* __restrict__ items, const int* __restrict__ tgt_blk,
-                                              const int* __restrict__ src_blk, const int* __restrict__ pair_offs,
-                                              const float* __restrict__ uhat, float* __restrict__ chat_part,
-                                              long long part_stride) {
+__global__ __launch_bounds__(512) void k_m2l(const float* __restrict__ cores, int core_rows, int ldk, int ld4,
+                                             const M2LItem* __restrict__ items, const int* __restrict__ tgt_blk,
+                                             const int* __restrict__ src_blk, const int* __restrict__ pair_offs,
+                                             const float* __restrict__ uhat, float* __restrict__ chat_part,
+                                             long long part_stride) {
   const M2LItem it = items[blockIdx.x];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;  // 16-row block of the output
-  const int i16 = lane & 15, q = lane >> 4;
+  const int wave = tid >> 6;  // 32-row block of the output
+  const int i32 = lane & 31, h = lane >> 5;
 
-  int tslot[4], bbase[4];
+  int tslot[2], bq[2], bbase[2];
 #pragma unroll
-  for (int nb = 0; nb < 4; ++nb) {
-    const int pi = 16 * nb + i16;  // position in the 4x4x4 parent block, x fastest
+  for (int nb = 0; nb < 2; ++nb) {
+    const int pi = 32 * nb + i32;  // position in the 4x4x4 parent block, x fastest
     tslot[nb] = tgt_blk[it.tgt_base + pi];
     bbase[nb] = ((pi & 3) + 1) + 6 * (((pi >> 2) & 3) + 1) + 36 * ((pi >> 4) + 1) - 43;
+    bq[nb] = bbase[nb] * ld4 + h;
   }
-  v4f acc[4];
+  v16f acc[2];
 #pragma unroll
-  for (int nb = 0; nb < 4; ++nb) acc[nb] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[nb][e] = 0.f;
   // offset table of the item in one VGPR (lane j holds entry j), read with readlane
   const int po_reg = pair_offs[it.pair * 27 + min(lane, 26)];
-  const float* arow = cores + (size_t)(16 * wave + i16) * ldk;
+  const float* arow = cores + (size_t)(32 * wave + i32) * ldk + 4 * h;  // this lane's operator row, k half h
   const size_t core_stride = (size_t)core_rows * ldk;
   const int* srcs = src_blk + it.src_base;
 
   for (int k0 = 0; k0 < ldk; k0 += kM2LSlab) {
-    const int kw = min(kM2LSlab, ldk - k0);  // slab width, a multiple of 4
+    const int kw = min(kM2LSlab, ldk - k0);  // slab width, a multiple of 8
     const int w4 = kw >> 2;
     if (k0) __syncthreads();  // previous slab fully consumed
     for (int idx = tid; idx < 216 * w4; idx += blockDim.x) {
@@ -260,31 +261,19 @@ __global__ __launch_bounds__(1024) void k_m2l(const float* __restrict__ cores, i
       s_m2l[r * ld4 + c4] = v;
     }
     __syncthreads();
-    const int nch = kw / 16;
-    const bool last = k0 + kM2LSlab >= ldk;
-    if (nch > 0) {
-      m2l_slab<TAIL>(acc, arow + k0, core_stride, po_reg, it.noffs, bbase, nch, last, ld4, q);
-    } else {
-      // a slab narrower than 16 (small rank): plain 4-k steps
-      for (int j = 0; j < it.noffs; ++j) {
-        const int e = __builtin_amdgcn_readlane(po_reg, j);
-        const float* ap = arow + k0 + (e & 511) * core_stride;
-        for (int k = 0; k < kw; k += 4)
-#pragma unroll
-          for (int nb = 0; nb < 4; ++nb)
-            acc[nb] = mfma16(ap[k + q], reinterpret_cast<const float*>(s_m2l)[4 * ((bbase[nb] + (e >> 9)) * ld4) + k + q],
-                             acc[nb]);
-      }
-    }
+    m2l_slab(acc, arow + k0, core_stride, po_reg, it.noffs, bq, kw >> 3, ld4);
   }
+  // acc[nb][v]: row 32 wave + 8 (v / 4) + 4 h + v % 4, target column 32 nb + i32
   float* out = chat_part + (size_t)it.part * part_stride;
-  const int o = 16 * wave + 4 * q;
-  if (o < ldk) {
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-      if (tslot[nb] < 0) continue;
-      *reinterpret_cast<float4*>(out + (size_t)tslot[nb] * ldk + o) =
-          make_float4(acc[nb][0], acc[nb][1], acc[nb][2], acc[nb][3]);
+  for (int nb = 0; nb < 2; ++nb) {
+    if (tslot[nb] < 0) continue;
+#pragma unroll
+    for (int b4 = 0; b4 < 4; ++b4) {
+      const int o = 32 * wave + 8 * b4 + 4 * h;
+      if (o < ldk)
+        *reinterpret_cast<float4*>(out + (size_t)tslot[nb] * ldk + o) =
+            make_float4(acc[nb][4 * b4], acc[nb][4 * b4 + 1], acc[nb][4 * b4 + 2], acc[nb][4 * b4 + 3]);
     }
   }
 }
@@ -293,32 +282,18 @@ bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int 
                 int nitems, const int* tgt_blk, const int* src_blk, const int* pair_offs, const float* uhat,
                 float* chat_part, long long part_stride, hipStream_t s) {
   if (nitems <= 0) return true;
-  if (row_blocks < 1 || row_blocks > 16 || (lds_ld & 3)) return false;
-  const int last_w = ldk - kM2LSlab * ((ldk - 1) / kM2LSlab);
-  const int tail = last_w % 16;
-  // 216 staged rows plus one spare row: in slabs other than the last, the
-  // (unused) tail operands are read up to 12 floats past a row's 64 k.
-  const size_t lds = (size_t)217 * lds_ld * sizeof(float);
-  if (lds_ld < 68) return false;
-#define KIFMM_M2L_CASE(T)                                                                                          \
-  if (tail == T) {                                                                                                 \
-    static size_t attr = 0;                                                                                        \
-    if (lds > attr) {                                                                                              \
-      if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l<T>), hipFuncAttributeMaxDynamicSharedMemorySize, \
-                              (int)lds) != hipSuccess)                                                             \
-        return false;                                                                                              \
-      attr = lds;                                                                                                  \
-    }                                                                                                              \
-    hipLaunchKernelGGL((k_m2l<T>), dim3(nitems), dim3(64 * row_blocks), lds, s, cores, core_rows, ldk, lds_ld / 4, \
-                       items, tgt_blk, src_blk, pair_offs, uhat, chat_part, part_stride);                          \
-    return true;                                                                                                   \
+  if (row_blocks < 1 || row_blocks > 8 || (ldk & 7) || lds_ld < kM2LSlab || (lds_ld & 3)) return false;
+  const size_t lds = (size_t)216 * lds_ld * sizeof(float);
+  static size_t attr = 0;
+  if (lds > attr) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess)
+      return false;
+    attr = lds;
   }
-  KIFMM_M2L_CASE(0)
-  KIFMM_M2L_CASE(4)
-  KIFMM_M2L_CASE(8)
-  KIFMM_M2L_CASE(12)
-#undef KIFMM_M2L_CASE
-  return false;
+  hipLaunchKernelGGL(k_m2l, dim3(nitems), dim3(64 * row_blocks), lds, s, cores, core_rows, ldk, lds_ld / 4, items,
+                     tgt_blk, src_blk, pair_offs, uhat, chat_part, part_stride);
+  return true;
 }
 
 // Sum of the eight source positions' partial sums, in a fixed order:
@@ -440,12 +415,18 @@ __device__ __forceinline__ void p2p_pair_masked(float xx, float xy, float xz, fl
   gz -= qr3 * dz;
 }
 
+// MODE 0: fused near + far field; MODE 1: near field only, written in sorted
+// order to `near` (phi, grad) for a later MODE 2 launch; MODE 2: far field only,
+// added to `near` and written to input order.
+template <int MODE>
 __global__ __launch_bounds__(256) void k_p2p(const float4* __restrict__ pts, const int* __restrict__ start,
                                              const int* __restrict__ blk, int group_slots, int cap,
                                              const float4* __restrict__ centers, const float* __restrict__ surf,
                                              int n, float alpha, const float* __restrict__ d, int ldd, int far,
                                              const int* __restrict__ order, float* __restrict__ pot,
-                                             float* __restrict__ grad) {
+                                             float* __restrict__ grad, float4* __restrict__ near) {
+  constexpr bool kNear = MODE != 2;
+  constexpr bool kFar = MODE != 1;
   float4* s_src = s_p2p;
   float4* s_de = s_p2p + cap;
   float* s_d = reinterpret_cast<float*>(s_p2p + cap + n);
@@ -458,7 +439,7 @@ __global__ __launch_bounds__(256) void k_p2p(const float4* __restrict__ pts, con
   const int tid = threadIdx.x;
   const int c0 = group_slots * g;  // first leaf slot of this parent
 
-  if (tid < 64) {
+  if (kNear && tid < 64) {
     const int slot = blk[(size_t)g * 64 + tid];
     const int cnt = slot >= 0 ? start[slot + 1] - start[slot] : 0;
     int incl = (cnt + 3) & ~3;
@@ -474,9 +455,9 @@ __global__ __launch_bounds__(256) void k_p2p(const float4* __restrict__ pts, con
   }
   if (tid <= group_slots) s_cs[tid] = start[c0 + tid];
   __syncthreads();
-  const int total = s_off[64];
+  const int total = kNear ? s_off[64] : 0;
   const bool in_lds = total <= cap;
-  if (in_lds) {
+  if (kNear && in_lds) {
     const float big = 3.402823466e38f;
     for (int i = tid; i < total; i += 256) {
       int lo = 0, hi = 64;  // entry e with s_off[e] <= i < s_off[e + 1]
@@ -490,7 +471,7 @@ __global__ __launch_bounds__(256) void k_p2p(const float4* __restrict__ pts, con
     }
   }
   const float sc = alpha * centers[2 * c0].w;
-  if (far) {
+  if (kFar && far) {
     for (int m = tid; m < n; m += 256)
       s_de[m] = make_float4(sc * surf[3 * m], sc * surf[3 * m + 1], sc * surf[3 * m + 2], 0.f);
     for (int i = tid; i < group_slots * n; i += 256) {
@@ -511,47 +492,55 @@ __global__ __launch_bounds__(256) void k_p2p(const float4* __restrict__ pts, con
     // Two-level summation: FP32 partial sums per source leaf and per block of 8
     // surface points, accumulated in FP64 (the D2T sum cancels heavily).
     double aphi = 0.0, agx = 0.0, agy = 0.0, agz = 0.0;
-    for (int dz = -1; dz <= 1; ++dz)
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int e = (bx + dx) + 4 * (by + dy) + 16 * (bz + dz);
-          const bool self = (dx == 0) & (dy == 0) & (dz == 0);
-          float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
-          if (in_lds) {
-            const int a = s_off[e], b = s_off[e + 1];  // b - a is a multiple of 4
-            if (self) {
-              for (int j = a; j < b; j += 4) {
-                const float4 y0 = s_src[j], y1 = s_src[j + 1], y2 = s_src[j + 2], y3 = s_src[j + 3];
-                p2p_pair_masked(x.x, x.y, x.z, y0, phi, gx, gy, gz);
-                p2p_pair_masked(x.x, x.y, x.z, y1, phi, gx, gy, gz);
-                p2p_pair_masked(x.x, x.y, x.z, y2, phi, gx, gy, gz);
-                p2p_pair_masked(x.x, x.y, x.z, y3, phi, gx, gy, gz);
+    if (kNear) {
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int e = (bx + dx) + 4 * (by + dy) + 16 * (bz + dz);
+            const bool self = (dx == 0) & (dy == 0) & (dz == 0);
+            float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+            if (in_lds) {
+              const int a = s_off[e], b = s_off[e + 1];  // b - a is a multiple of 4
+              if (self) {
+                for (int j = a; j < b; j += 4) {
+                  const float4 y0 = s_src[j], y1 = s_src[j + 1], y2 = s_src[j + 2], y3 = s_src[j + 3];
+                  p2p_pair_masked(x.x, x.y, x.z, y0, phi, gx, gy, gz);
+                  p2p_pair_masked(x.x, x.y, x.z, y1, phi, gx, gy, gz);
+                  p2p_pair_masked(x.x, x.y, x.z, y2, phi, gx, gy, gz);
+                  p2p_pair_masked(x.x, x.y, x.z, y3, phi, gx, gy, gz);
+                }
+              } else {
+                for (int j = a; j < b; j += 4) {
+                  const float4 y0 = s_src[j], y1 = s_src[j + 1], y2 = s_src[j + 2], y3 = s_src[j + 3];
+                  p2p_pair(x.x, x.y, x.z, y0, phi, gx, gy, gz);
+                  p2p_pair(x.x, x.y, x.z, y1, phi, gx, gy, gz);
+                  p2p_pair(x.x, x.y, x.z, y2, phi, gx, gy, gz);
+                  p2p_pair(x.x, x.y, x.z, y3, phi, gx, gy, gz);
+                }
               }
             } else {
-              for (int j = a; j < b; j += 4) {
-                const float4 y0 = s_src[j], y1 = s_src[j + 1], y2 = s_src[j + 2], y3 = s_src[j + 3];
-                p2p_pair(x.x, x.y, x.z, y0, phi, gx, gy, gz);
-                p2p_pair(x.x, x.y, x.z, y1, phi, gx, gy, gz);
-                p2p_pair(x.x, x.y, x.z, y2, phi, gx, gy, gz);
-                p2p_pair(x.x, x.y, x.z, y3, phi, gx, gy, gz);
+              const int slot = s_slot[e];
+              if (slot >= 0) {
+                const int a = start[slot], b = start[slot + 1];
+                if (self)
+                  for (int j = a; j < b; ++j) p2p_pair_masked(x.x, x.y, x.z, pts[j], phi, gx, gy, gz);
+                else
+                  for (int j = a; j < b; ++j) p2p_pair(x.x, x.y, x.z, pts[j], phi, gx, gy, gz);
               }
             }
-          } else {
-            const int slot = s_slot[e];
-            if (slot >= 0) {
-              const int a = start[slot], b = start[slot + 1];
-              if (self)
-                for (int j = a; j < b; ++j) p2p_pair_masked(x.x, x.y, x.z, pts[j], phi, gx, gy, gz);
-              else
-                for (int j = a; j < b; ++j) p2p_pair(x.x, x.y, x.z, pts[j], phi, gx, gy, gz);
-            }
+            aphi += phi;
+            agx += gx;
+            agy += gy;
+            agz += gz;
           }
-          aphi += phi;
-          agx += gx;
-          agy += gy;
-          agz += gz;
-        }
-    if (far) {
+    } else {
+      const float4 v = near[ti];
+      aphi = v.x;
+      agx = v.y;
+      agy = v.z;
+      agz = v.w;
+    }
+    if (kFar && far) {
       const float4 ch = centers[2 * (c0 + o)], cl = centers[2 * (c0 + o) + 1];
       const float xx = (x.x - ch.x) - cl.x, xy = (x.y - ch.y) - cl.y, xz = (x.z - ch.z) - cl.z;
       const float* dl = s_d + o * n;
@@ -568,33 +557,44 @@ __global__ __launch_bounds__(256) void k_p2p(const float4* __restrict__ pts, con
         agz += gz;
       }
     }
-    const int oi = order[ti];
-    if (pot) pot[oi] = (float)aphi;
-    if (grad) {
-      grad[3 * (size_t)oi] = (float)agx;
-      grad[3 * (size_t)oi + 1] = (float)agy;
-      grad[3 * (size_t)oi + 2] = (float)agz;
+    if (MODE == 1) {
+      near[ti] = make_float4((float)aphi, (float)agx, (float)agy, (float)agz);
+    } else {
+      const int oi = order[ti];
+      if (pot) pot[oi] = (float)aphi;
+      if (grad) {
+        grad[3 * (size_t)oi] = (float)agx;
+        grad[3 * (size_t)oi + 1] = (float)agy;
+        grad[3 * (size_t)oi + 2] = (float)agz;
+      }
     }
   }
 }
 
 size_t p2p_lds_bytes(int cap, int n) { return (size_t)cap * 16 + (size_t)n * 16 + (size_t)8 * n * 4; }
 
-bool launch_p2p(const float4* pts, const int* start, const int* blk, int ngroups, int group_slots, int cap,
+bool launch_p2p(int mode, const float4* pts, const int* start, const int* blk, int ngroups, int group_slots, int cap,
                 const float4* centers, const float* surf, int n, float alpha, const float* d, int ldd, int far,
-                const int* order, float* pot, float* grad, hipStream_t s) {
+                const int* order, float* pot, float* grad, float4* near, hipStream_t s) {
   if (ngroups <= 0) return true;
-  const size_t lds = p2p_lds_bytes(cap, n);
-  static size_t attr = 0;
-  if (lds > attr) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_p2p), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds) != hipSuccess)
-      return false;
-    attr = lds;
-  }
-  hipLaunchKernelGGL(k_p2p, dim3(ngroups), dim3(256), lds, s, pts, start, blk, group_slots, cap, centers, surf, n,
-                     alpha, d, ldd, far, order, pot, grad);
-  return true;
+  const int c = mode == 2 ? 0 : cap;
+  const size_t lds = mode == 1 ? (size_t)cap * 16 : p2p_lds_bytes(c, n);  // near-only: sources alone
+  auto launch = [&](auto kernel, size_t& attr) {
+    if (lds > attr) {
+      if (hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds) != hipSuccess)
+        return false;
+      attr = lds;
+    }
+    hipLaunchKernelGGL(kernel, dim3(ngroups), dim3(256), lds, s, pts, start, blk, group_slots, c, centers, surf, n,
+                       alpha, d, ldd, far, order, pot, grad, near);
+    return true;
+  };
+  static size_t attr0 = 0, attr1 = 0, attr2 = 0;
+  if (mode == 0) return launch(&k_p2p<0>, attr0);
+  if (mode == 1) return launch(&k_p2p<1>, attr1);
+  if (mode == 2) return launch(&k_p2p<2>, attr2);
+  return false;
 }
 
 }  // namespace kifmm

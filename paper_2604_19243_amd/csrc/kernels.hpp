@@ -30,8 +30,11 @@ void launch_p2m(const float4* pts, const int* start, const int* leaves, const fl
 // blk: per parent group, the 64 leaf slots of the 4x4x4 block around it (-1 = none).
 // cap: sources staged in LDS per block (each leaf padded to a multiple of 4).
 size_t p2p_lds_bytes(int cap, int n);
-bool launch_p2p(const float4* pts, const int* start, const int* blk, int ngroups, int group_slots, int cap,
+// mode 0: near + far field fused, written to input order; mode 1: near field only,
+// written in sorted order to `near` (phi, grad); mode 2: far field added to `near`,
+// written to input order.
+bool launch_p2p(int mode, const float4* pts, const int* start, const int* blk, int ngroups, int group_slots, int cap,
                 const float4* centers, const float* surf, int n, float alpha, const float* d, int ldd, int far,
-                const int* order, float* pot, float* grad, hipStream_t s);
+                const int* order, float* pot, float* grad, float4* near, hipStream_t s);
 
 }  // namespace kifmm

@@ -52,6 +52,9 @@ Plan::~Plan() {
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(device);
   for (auto& e : ev) (void)hipEventDestroy(e);
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  if (side) (void)hipStreamDestroy(side);
   for (void* p : owned) (void)hipFree(p);
   (void)hipSetDevice(prev);
   release(tree);
@@ -60,7 +63,9 @@ Plan::~Plan() {
 
 Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
   require(tree && ops, "null tree or ops");
-  require((flags & ~(KIFMM_POTENTIAL | KIFMM_GRADIENT)) == 0 && flags != 0, "flags must be POTENTIAL and/or GRADIENT");
+  require((flags & ~(KIFMM_POTENTIAL | KIFMM_GRADIENT | KIFMM_SERIAL)) == 0 &&
+              (flags & (KIFMM_POTENTIAL | KIFMM_GRADIENT)) != 0,
+          "flags must hold POTENTIAL and/or GRADIENT, optionally SERIAL");
   int ndev = 0;
   hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
   require(device >= 0 && device < ndev, "device index out of range");
@@ -85,7 +90,7 @@ Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
     P->n = O.n;
     P->nst = round_up(O.n, 4);
     P->k = O.k;
-    P->kst = round_up(O.k, 4);
+    P->kst = round_up(O.k, 8);  // M2L runs k in chunks of 8 (zero padding)
     P->kc = O.kc;
     P->kcst = round_up(O.kc, 4);
     auto& own = P->owned;
@@ -269,9 +274,9 @@ Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
           for (int c = 0; c < n; ++c)
             wl[((size_t)oc * nst + i) * nst + c] = (float)O.l2l[((size_t)oc * n + i) * n + c];
       P->d_l2l = dev_upload(own, wl.data(), wl.size(), "l2l");
-      // M2L cores: [316][core_rows][kst], rows padded to whole 16-row blocks (one wave each).
-      P->m2l_rb = kst / 16 + (kst % 16 ? 1 : 0);
-      P->core_rows = 16 * P->m2l_rb;
+      // M2L cores: [316][core_rows][kst], rows padded to whole 32-row blocks (one wave each).
+      P->m2l_rb = (kst + 31) / 32;
+      P->core_rows = 32 * P->m2l_rb;
       std::vector<float> wc((size_t)kNumOffsets * P->core_rows * kst, 0.f);
       for (int t = 0; t < kNumOffsets; ++t)
         for (int a = 0; a < k; ++a)
@@ -391,16 +396,22 @@ Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
       P->m2l_pairs = vpairs;
       P->m2l_targets = ntargets;
       P->n_items = (int)items.size();
-      // LDS row stride of one 64-k slab of the staged sources: 68 floats, an odd
-      // number of 16-byte units, so 16 lanes reading 16 rows hit distinct banks.
-      P->m2l_lds_ld = 68;
-      require(P->m2l_rb <= 16, "M2L rank too large for the M2L kernel");
+      // LDS row stride of one 40-k slab of the staged sources: 44 floats, an odd
+      // number of 16-byte units, so lanes reading different rows spread over the banks.
+      P->m2l_lds_ld = 44;
+      require(P->m2l_rb <= 8, "M2L rank too large for the M2L kernel (k <= 256)");
       P->d_tgt_blk = dev_upload(own, tgt_blk.data(), tgt_blk.size(), "m2l block targets");
       P->d_src_blk = dev_upload(own, src_blk.data(), src_blk.size(), "m2l block sources");
       P->d_items = dev_upload(own, items.data(), items.size(), "m2l items");
       P->keys_per_level.assign(L + 1, 0);
       for (int l = 0; l <= L; ++l) P->keys_per_level[l] = (int64_t)T.keys[l].size();
       P->slot_of = slot_of;
+    }
+    if (P->far && !(flags & KIFMM_SERIAL)) {
+      hip_check(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking), "hipStreamCreate");
+      hip_check(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming), "hipEventCreate");
+      hip_check(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming), "hipEventCreate");
+      P->d_near = reinterpret_cast<float4*>(dev_upload<float>(own, nullptr, 4 * (size_t)T.n, "near field"));
     }
     hip_check(hipDeviceSynchronize(), "plan upload");
   } catch (...) {
@@ -466,6 +477,21 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
   P->stage_begin(KIFMM_STAGE_PERMUTE, st);
   launch_permute(P->d_pts, charges, P->d_order, N, st);
   P->stage_end(KIFMM_STAGE_PERMUTE, st);
+  const bool split = P->side != nullptr;
+  const float* d_leaf = P->far ? P->d_d + P->base[L] * P->nst : nullptr;
+  if (split) {
+    // (3c) ULI needs only the sorted charges: it runs on the plan's stream beside
+    // the upward pass and M2L, and is joined before D2T.
+    hip_check(hipEventRecord(P->ev_fork, st), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(P->side, P->ev_fork, 0), "hipStreamWaitEvent");
+    P->stage_begin(KIFMM_STAGE_P2P, P->side);
+    if (!launch_p2p(1, P->d_pts, P->d_start, P->d_blk, (int)P->n_groups, P->group_slots, P->p2p_cap, P->d_centers,
+                    P->d_surf, P->n, (float)kAlphaOuter, d_leaf, P->nst, 0, P->d_order, nullptr, nullptr, P->d_near,
+                    P->side))
+      fail(KIFMM_E_DEVICE, "leaf kernel configuration not available");
+    P->stage_end(KIFMM_STAGE_P2P, P->side);
+    hip_check(hipEventRecord(P->ev_join, P->side), "hipEventRecord");
+  }
 
   if (P->far) {
     const int n = P->n, nst = P->nst, kst = P->kst, kcst = P->kcst;
@@ -515,13 +541,23 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
     }
     P->stage_end(KIFMM_STAGE_L2L, st);
   }
-  // (3b) D2T + (3c) ULI, written in input order.
-  P->stage_begin(KIFMM_STAGE_P2P, st);
-  if (!launch_p2p(P->d_pts, P->d_start, P->d_blk, (int)P->n_groups, P->group_slots, P->p2p_cap, P->d_centers,
-                  P->d_surf, P->n, (float)kAlphaOuter, P->far ? P->d_d + P->base[L] * P->nst : nullptr, P->nst,
-                  P->far ? 1 : 0, P->d_order, pot, grad, st))
-    fail(KIFMM_E_DEVICE, "leaf kernel configuration not available");
-  P->stage_end(KIFMM_STAGE_P2P, st);
+  if (split) {
+    // (3b) D2T added to the ULI result, written in input order.
+    hip_check(hipStreamWaitEvent(st, P->ev_join, 0), "hipStreamWaitEvent");
+    P->stage_begin(KIFMM_STAGE_L2P, st);
+    if (!launch_p2p(2, P->d_pts, P->d_start, P->d_blk, (int)P->n_groups, P->group_slots, P->p2p_cap, P->d_centers,
+                    P->d_surf, P->n, (float)kAlphaOuter, d_leaf, P->nst, 1, P->d_order, pot, grad, P->d_near, st))
+      fail(KIFMM_E_DEVICE, "leaf kernel configuration not available");
+    P->stage_end(KIFMM_STAGE_L2P, st);
+  } else {
+    // (3b) D2T + (3c) ULI fused, written in input order.
+    P->stage_begin(KIFMM_STAGE_P2P, st);
+    if (!launch_p2p(0, P->d_pts, P->d_start, P->d_blk, (int)P->n_groups, P->group_slots, P->p2p_cap, P->d_centers,
+                    P->d_surf, P->n, (float)kAlphaOuter, d_leaf, P->nst, P->far ? 1 : 0, P->d_order, pot, grad,
+                    nullptr, st))
+      fail(KIFMM_E_DEVICE, "leaf kernel configuration not available");
+    P->stage_end(KIFMM_STAGE_P2P, st);
+  }
   hip_check(hipGetLastError(), "kernel launch");
   if (prev != P->device) (void)hipSetDevice(prev);
 }

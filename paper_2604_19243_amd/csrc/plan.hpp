@@ -50,6 +50,10 @@ struct Plan : Object {
   // Stage timing: a ring of event pairs per call, read back only when full or
   // on request, so timed evaluates never wait on the host.
   static constexpr int kRing = 128;
+  hipStream_t side = nullptr;            // ULI stream (default priority)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  float4* d_near = nullptr;              // ULI result in sorted order (phi, grad)
+
   bool timing = false;
   std::vector<hipEvent_t> ev;            // [kRing][KIFMM_N_STAGES][2]
   std::vector<unsigned char> recorded;   // [kRing][KIFMM_N_STAGES]

@@ -34,18 +34,19 @@ def test_shallow_tree_equals_direct_sum(depth, n):
     assert rel_l2(g, gref) < TOL
 
 
-@pytest.mark.parametrize("name,n,depth,p,dist", [
-    ("cube20k_p6_d3", 20_000, 3, 6, "cube"),   # the FP64 validation workload, full size
-    ("ragged", 7_777, 4, 5, "cube"),           # ragged leaves and tiles, many boundary boxes
-    ("sphere", 30_000, 4, 6, "sphere"),        # strongly non-uniform: most boxes empty
-    ("sparse_deep", 2_000, 5, 4, "cube"),      # ~0.06 points per leaf
+@pytest.mark.parametrize("name,n,depth,p,dist,serial", [
+    ("cube20k_p6_d3", 20_000, 3, 6, "cube", False),   # the FP64 validation workload, full size
+    ("cube20k_p6_d3", 20_000, 3, 6, "cube", True),    # same, every kernel on the caller's stream
+    ("ragged", 7_777, 4, 5, "cube", False),           # ragged leaves and tiles, many boundary boxes
+    ("sphere", 30_000, 4, 6, "sphere", False),        # strongly non-uniform: most boxes empty
+    ("sparse_deep", 2_000, 5, 4, "cube", True),       # ~0.06 points per leaf
 ])
-def test_parity_with_oracle(name, n, depth, p, dist):
-    log(f"parity {name} n={n} depth={depth} p={p}")
+def test_parity_with_oracle(name, n, depth, p, dist, serial):
+    log(f"parity {name} n={n} depth={depth} p={p} serial={serial}")
     x = workloads.points(dist, n, 1001 if name.startswith("cube20k") else 500 + n)
     s = workloads.charges("uniform01", n, 2001 if name.startswith("cube20k") else 600 + n)
     cube = UNIT if dist == "cube" else (0.0, 0.0, 0.0, 1.0)
-    phi, g, f = gpu_evaluate(x, s, depth, p, cube)
+    phi, g, f = gpu_evaluate(x, s, depth, p, cube, serial=serial)
     k = kifmm.kifmm_ops_get_info(f.ops)["rank_m2l"]
     f.close()
     rphi, rg, _, ops = oracle_evaluate(x, s, depth, p, cube)
@@ -75,13 +76,17 @@ def test_linearity_and_determinism():
 
 def test_full_size_hot_path_sampled():
     # 1,000,000 points, depth 5, p = 6: the benchmarked workload in the benchmarked launch
-    # configuration, checked against the oracle on the points of 24 sampled leaves.
+    # configuration, checked against the oracle on the points of 24 sampled leaves; the
+    # single-stream configuration must give the same numbers to FP32 summation order.
     w = workloads.WORKLOADS["cube1m_p6_d5"]
     log("full size cube1m_p6_d5")
     x, s = workloads.make(w)
     c = w.cube[0] + (w.cube[1],)
     phi, g, f = gpu_evaluate(x, s, w.depth, w.p, c)
     f.close()
+    phi_s, g_s, f = gpu_evaluate(x, s, w.depth, w.p, c, serial=True)
+    f.close()
+    assert rel_l2(phi_s, phi) < 1e-7 and rel_l2(g_s, g) < 1e-7
     assert np.isfinite(phi).all() and np.isfinite(g).all()
     rng = np.random.default_rng(4002)
     m = 2 ** w.depth
