@@ -10,6 +10,11 @@ Prints one JSON line: metric/value (Mpoints/s = N / time per evaluate), the
 roofline of the dominant kernel (M2L, FP32 matrix cores) measured with HIP
 events on the evaluate stream, the P2P kernel's FLOP rate, and the FP64 oracle
 timed on a bounded sample on the host CPU.
+
+`--m2l bf16x3` runs M2L as three bfloat16 matrix-core passes with FP32
+accumulation (roofline against the BF16 peak, three passes counted);
+`--compare-fp32` then also times the plain FP32 form on the same tree and
+operators and reports both forms' accuracy against the direct sum.
 """
 
 import argparse
@@ -26,6 +31,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 (vector and matrix), dense
+PEAK_BF16_TFLOPS = 2500.0  # MI355X BF16 matrix, dense (no sparsity)
 P2P_FLOPS_PER_PAIR = 20    # potential + gradient: 3 sub, 5 for r^2, 1 rsqrt, 2 potential, 1 + 8 gradient
 METRIC = "Mpoints/s per kiFMM evaluate at rel-L2<=1e-5; P2P/M2L % roofline"
 
@@ -58,6 +64,20 @@ def cpu_baseline_worker(args):
     w = workloads.WORKLOADS[args.workload]
     x32, s32 = workloads.make(w)
     x, s = x32.astype(np.float64), s32.astype(np.float64)
+
+    # accuracy of the GPU run(s): oracle direct sum at sampled targets, in blocks of sources
+    gpu = np.load(args.gpu_sample)
+    idx = gpu["idx"]
+    ref = np.zeros(len(idx))
+    for a in range(0, len(x), 250_000):
+        ref += direct.potential(x[idx], x[a:a + 250_000], s[a:a + 250_000])
+    acc = {"rel_l2_vs_direct_sampled": direct.rel_l2(gpu["phi"], ref), "direct_sample_targets": int(len(idx))}
+    if "phi_fp32" in gpu:
+        acc["fp32_rel_l2_vs_direct_sampled"] = direct.rel_l2(gpu["phi_fp32"], ref)
+    if args.accuracy_only:
+        print(json.dumps(acc), flush=True)
+        return
+
     c, r = w.cube
     t = tree.Tree(x, w.depth, c, r)
     ops = operators.Operators(w.p, eps_pinv=1e-7, m2l="compressed", eps_svd=1e-6)
@@ -86,10 +106,6 @@ def cpu_baseline_worker(args):
     boxes_sampled = sum(len(needed[l]) for l in range(2, L + 1))
     t_full = (t1 - t0) + (t2 - t1) * boxes_all / boxes_sampled + (t3 - t2) * len(all_leaves) / len(leaves)
 
-    # accuracy of the GPU run: oracle direct sum at sampled targets
-    gpu = np.load(args.gpu_sample)
-    idx, gphi = gpu["idx"], gpu["phi"]
-    ref = direct.potential(x[idx], x, s)
     out = {
         "value": w.n / t_full / 1e6, "unit": "Mpoints/s", "cores": 1, "kind": "oracle",
         "sample": (f"FP64 NumPy oracle, single thread: full upward pass ({t1 - t0:.2f} s) timed; downward pass "
@@ -97,8 +113,8 @@ def cpu_baseline_worker(args):
                    f"leaf pass on those leaves ({t3 - t2:.2f} s), each scaled by box/leaf counts to the full "
                    f"workload; extrapolated evaluate {t_full:.1f} s"),
         "seconds_measured": t3 - t0, "seconds_extrapolated": t_full,
-        "rel_l2_vs_direct_sampled": direct.rel_l2(gphi, ref), "direct_sample_targets": int(len(idx)),
     }
+    out.update(acc)
     print(json.dumps(out), flush=True)
 
 
@@ -111,11 +127,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serial", action="store_true",
                     help="run every kernel on one stream (no ULI overlap with the far field)")
+    ap.add_argument("--m2l", choices=["fp32", "bf16x3", "bf16x6"], default="fp32",
+                    help="M2L arithmetic: plain FP32, or split bfloat16 (3 or 6 matrix-core passes, FP32 accumulation)")
+    ap.add_argument("--compare-fp32", action="store_true",
+                    help="with a split-bfloat16 --m2l: also time the plain FP32 form on the same tree and operators")
     ap.add_argument("--sample-leaves", type=int, default=24)
     ap.add_argument("--sample-seed", type=int, default=2)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (calibrates HBM byte counters) and exit")
     ap.add_argument("--cpu-baseline-worker", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--accuracy-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--gpu-sample", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
 
@@ -146,8 +167,11 @@ def main():
     x, s = workloads.make(w)
     cube = w.cube[0] + (w.cube[1],)
     t_setup = time.perf_counter()
+    passes = {"fp32": 0, "bf16x3": 3, "bf16x6": 6}[args.m2l]
+    bf16 = passes > 0
+    m2l_flag = {"fp32": 0, "bf16x3": kifmm.KIFMM_M2L_BF16X3, "bf16x6": kifmm.KIFMM_M2L_BF16X6}[args.m2l]
     flags = kifmm.KIFMM_POTENTIAL | kifmm.KIFMM_GRADIENT | (kifmm.KIFMM_SERIAL if args.serial else 0)
-    f = kifmm.FMM(x, w.depth, w.p, cube=cube, eps_pinv=1e-7, eps_svd=1e-6, flags=flags)
+    f = kifmm.FMM(x, w.depth, w.p, cube=cube, eps_pinv=1e-7, eps_svd=1e-6, flags=flags | m2l_flag)
     t_setup = time.perf_counter() - t_setup
     info = kifmm.kifmm_ops_get_info(f.ops)
     stats = kifmm.kifmm_plan_get_stats(f.plan)
@@ -159,39 +183,65 @@ def main():
     pot = torch.empty(w.n, device=dev)
     grad = torch.empty(w.n, 3, device=dev) if w.gradient else None
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        f.evaluate(charges, pot, grad, stream=stream.cuda_stream)
-    torch.cuda.synchronize()
 
-    kifmm.kifmm_plan_set_timing(f.plan, True)
-    kifmm.kifmm_plan_get_stage_times(f.plan, reset=True)
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    for _ in range(args.steps):
-        f.evaluate(charges, pot, grad, stream=stream.cuda_stream)
-    end.record(stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end) / args.steps
-    stages = kifmm.kifmm_plan_get_stage_times(f.plan, reset=True)
-    kifmm.kifmm_plan_set_timing(f.plan, False)
-    print(f"# {ms:.3f} ms/evaluate; stages (ms/call): "
-          + ", ".join(f"{k_}={v[0] / max(v[1], 1):.3f}" for k_, v in stages.items()), file=sys.stderr, flush=True)
+    def timed(plan, label):
+        """Warm-up, then exactly args.steps evaluates between two events on the evaluate stream."""
+        for _ in range(args.warmup):
+            kifmm.kifmm_evaluate(plan, charges, pot, grad, stream.cuda_stream)
+        torch.cuda.synchronize()
+        kifmm.kifmm_plan_set_timing(plan, True)
+        kifmm.kifmm_plan_get_stage_times(plan, reset=True)
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(args.steps):
+            kifmm.kifmm_evaluate(plan, charges, pot, grad, stream.cuda_stream)
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms_ = start.elapsed_time(end) / args.steps
+        st = kifmm.kifmm_plan_get_stage_times(plan, reset=True)
+        kifmm.kifmm_plan_set_timing(plan, False)
+        print(f"# {label}: {ms_:.3f} ms/evaluate; stages (ms/call): "
+              + ", ".join(f"{k_}={v[0] / max(v[1], 1):.3f}" for k_, v in st.items()), file=sys.stderr, flush=True)
+        return ms_, {k_: v[0] / max(v[1], 1) for k_, v in st.items()}
 
-    # M2L (dominant kernel): 2 k^2 FLOP per (target, source) V-list pair.
-    m2l_ms = stages["m2l"][0] / max(stages["m2l"][1], 1)
+    idx = np.sort(np.random.default_rng(4002).choice(w.n, size=min(256, w.n), replace=False))
+    ms, stages = timed(f.plan, "m2l " + args.m2l)
+    phi_sample = pot.cpu().numpy()[idx].astype(np.float64)
+    fp32_form = None
+    if bf16 and args.compare_fp32:
+        plan32 = kifmm.kifmm_plan_create(f.tree, f.ops, flags)
+        ms32, stages32 = timed(plan32, "m2l fp32")
+        phi32_sample = pot.cpu().numpy()[idx].astype(np.float64)
+        kifmm.kifmm_plan_destroy(plan32)
+        fp32_form = {"ms_per_step": ms32, "m2l_ms": stages32["m2l"], "stages_ms": stages32,
+                     "speedup_evaluate": ms32 / ms, "speedup_m2l": stages32["m2l"] / stages["m2l"]}
+
+    # M2L (dominant kernel): 2 k^2 FLOP per (target, source) V-list pair; the split-bfloat16
+    # forms execute each product as 3 or 6 bfloat16 products, counted against the BF16 peak.
+    m2l_ms = stages["m2l"]
     m2l_flop = 2.0 * k * k * stats["m2l_pairs"]
     m2l_tflops = m2l_flop / (m2l_ms * 1e-3) / 1e12
-    traffic = load_traffic(w.name, "k_m2l")
+    m2l_kernel = f"k_m2l_bf16<{passes // 3 + 1}>" if bf16 else "k_m2l"
+    traffic = load_traffic(w.name, m2l_kernel)
     # Leaf kernels: 20 FLOP per U-list pair (ULI) and per (target, downward-equivalent point) pair (D2T).
     # By default ULI runs on the plan's own stream beside the far field and D2T is a separate
     # kernel; with --serial one fused kernel does both.
-    p2p_ms = stages["p2p"][0] / max(stages["p2p"][1], 1)
+    p2p_ms = stages["p2p"]
     d2t_pairs = w.n * n * (1 if w.depth >= 2 else 0)
     p2p_pairs = stats["p2p_pairs"] + (d2t_pairs if args.serial else 0)
     p2p_tflops = P2P_FLOPS_PER_PAIR * p2p_pairs / (p2p_ms * 1e-3) / 1e12
-    l2p_ms = stages["l2p"][0] / max(stages["l2p"][1], 1)
+    l2p_ms = stages["l2p"]
+    if bf16:
+        roofline = {"kernel": m2l_kernel, "bound": "mfma", "achieved": passes * m2l_tflops,
+                    "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": passes * m2l_tflops / PEAK_BF16_TFLOPS,
+                    "traffic": traffic, "passes": passes, "fp32_equivalent_tflops": m2l_tflops}
+    else:
+        roofline = {"kernel": m2l_kernel, "bound": "mfma", "achieved": m2l_tflops, "peak": PEAK_FP32_TFLOPS,
+                    "unit": "TFLOP/s", "frac": m2l_tflops / PEAK_FP32_TFLOPS, "traffic": traffic}
+    roofline.update({"ms_per_launch": m2l_ms, "algorithmic_flop_per_launch": m2l_flop,
+                     "v_list_pairs": stats["m2l_pairs"]})
 
     result = {
         "metric": METRIC,
@@ -199,44 +249,46 @@ def main():
         "unit": "Mpoints/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": f"f32, M2L {args.m2l} (f32 accumulation)" if bf16 else "f32", "data": "synthetic",
         "config": {"workload": w.name, "n_points": w.n, "distribution": w.distribution, "charges": w.charges,
                    "p": w.p, "n_surface": n, "m2l_rank": k, "depth": w.depth, "nrhs": w.nrhs,
                    "outputs": "potential+gradient" if w.gradient else "potential", "parallelism": "single-gpu",
-                   "uli_overlap": not args.serial},
-        "roofline": {"kernel": "k_m2l", "bound": "mfma", "achieved": m2l_tflops, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": m2l_tflops / PEAK_FP32_TFLOPS, "traffic": traffic,
-                     "ms_per_launch": m2l_ms, "algorithmic_flop_per_launch": m2l_flop,
-                     "v_list_pairs": stats["m2l_pairs"]},
+                   "uli_overlap": not args.serial, "m2l": args.m2l},
+        "roofline": roofline,
         "p2p": {"kernel": "k_p2p<0>" if args.serial else "k_p2p<1> (ULI, overlapped with the far field)",
                 "bound": "alu", "achieved": p2p_tflops, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": p2p_tflops / PEAK_FP32_TFLOPS, "ms_per_launch": p2p_ms,
                 "pairs_per_launch": p2p_pairs, "flop_per_pair": P2P_FLOPS_PER_PAIR,
                 "d2t_ms_per_launch": None if args.serial else l2p_ms, "d2t_pairs_per_launch": d2t_pairs},
-        "stages_ms": {k_: v[0] / max(v[1], 1) for k_, v in stages.items()},
+        "stages_ms": stages,
         "setup_s": t_setup,
         "cpu_baseline": None,
     }
+    if fp32_form is not None:
+        result["fp32_form"] = fp32_form
 
-    if not args.no_cpu_baseline:
-        idx = np.sort(np.random.default_rng(4002).choice(w.n, size=min(256, w.n), replace=False))
-        phi = pot.cpu().numpy()[idx].astype(np.float64)
-        with tempfile.TemporaryDirectory() as tmp:
-            path = os.path.join(tmp, "gpu_sample.npz")
-            np.savez(path, idx=idx, phi=phi)
-            env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-            print("# cpu baseline (oracle, 1 thread)...", file=sys.stderr, flush=True)
-            r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker",
-                                "--workload", w.name, "--sample-leaves", str(args.sample_leaves),
-                                "--sample-seed", str(args.sample_seed), "--gpu-sample", path],
-                               capture_output=True, text=True, env=env, timeout=900)
-            if r.returncode == 0:
-                cb = json.loads(r.stdout.strip().splitlines()[-1])
-                result["rel_l2_vs_direct_sampled"] = cb.pop("rel_l2_vs_direct_sampled")
-                result["direct_sample_targets"] = cb.pop("direct_sample_targets")
+    # The oracle leg (a child process with single-threaded BLAS): the direct sum at the sampled
+    # targets for the accuracy figures and, unless skipped, the oracle timed on a bounded sample.
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "gpu_sample.npz")
+        extra = {"phi_fp32": phi32_sample} if fp32_form is not None else {}
+        np.savez(path, idx=idx, phi=phi_sample, **extra)
+        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+        print("# oracle leg (1 thread)...", file=sys.stderr, flush=True)
+        cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker", "--workload", w.name,
+               "--sample-leaves", str(args.sample_leaves), "--sample-seed", str(args.sample_seed),
+               "--gpu-sample", path] + (["--accuracy-only"] if args.no_cpu_baseline else [])
+        r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=900)
+        if r.returncode == 0:
+            cb = json.loads(r.stdout.strip().splitlines()[-1])
+            result["rel_l2_vs_direct_sampled"] = cb.pop("rel_l2_vs_direct_sampled")
+            result["direct_sample_targets"] = cb.pop("direct_sample_targets")
+            if "fp32_rel_l2_vs_direct_sampled" in cb:
+                result["fp32_form"]["rel_l2_vs_direct_sampled"] = cb.pop("fp32_rel_l2_vs_direct_sampled")
+            if not args.no_cpu_baseline:
                 result["cpu_baseline"] = cb
-            else:
-                print(r.stderr[-2000:], file=sys.stderr, flush=True)
+        else:
+            print(r.stderr[-2000:], file=sys.stderr, flush=True)
     f.close()
     print(json.dumps(result), flush=True)
 

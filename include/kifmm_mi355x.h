@@ -166,10 +166,19 @@ kifmm_status kifmm_ops_destroy(kifmm_ops ops);
  * depend on the far field (Section 2.2), runs on a stream owned by the plan,
  * forked from and joined back into the caller's stream with events, so that it
  * overlaps the upward pass and M2L; KIFMM_SERIAL keeps every kernel on the
- * caller's stream (with the near and far leaf sums fused in one kernel). */
+ * caller's stream (with the near and far leaf sums fused in one kernel).
+ * KIFMM_M2L_BF16X3 and KIFMM_M2L_BF16X6 (at most one of them) run the
+ * compressed M2L translations (Section 2.2, BLAS M2L) on bfloat16 matrix cores
+ * with FP32 accumulation, each operand split into bfloat16 pieces (split
+ * bfloat16): two pieces and three products (a0 b0 + a0 b1 + a1 b0, each
+ * product to about 3 * 2^-16 relative), or three pieces and six products (to
+ * about 2^-24, the accuracy of the plain FP32 path).  Everything else stays
+ * FP32 and the operators are still computed in FP64. */
 #define KIFMM_POTENTIAL 1u
 #define KIFMM_GRADIENT 2u
 #define KIFMM_SERIAL 4u
+#define KIFMM_M2L_BF16X3 8u
+#define KIFMM_M2L_BF16X6 16u
 
 /*
  * Place a tree and its operators on HIP device `device`: uploads the sorted

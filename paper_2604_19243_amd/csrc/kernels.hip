@@ -126,9 +126,11 @@ void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int*
 // with zeros to a multiple of 8) runs in "chunks" of 8: lane (i, h) = (l % 32,
 // l / 32) loads A[i][8c + 4h .. +3] and B^T[j][8c + 4h .. +3] as float4 and the
 // four MFMA steps contract k = 8c + 4h + r (the order of the sum over k is
-// free).  Sources are staged in LDS in slabs of 40 k; operator rows are read
-// from global memory (L2: the items of one (o, o') pair are dealt to one XCD);
-// each chunk's operands are fetched two chunks ahead of their use.
+// free).  Sources are staged in LDS in slabs of 40 k.  The operators are read
+// from global memory (L2: the items of one (o, o') pair are dealt to one XCD),
+// stored in lane order so that a wave's float4 loads of one chunk cover 1 KiB
+// of contiguous memory; each chunk's operands are fetched two chunks ahead of
+// their use.
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ v16f mfma32(float a, float b, v16f c) {
@@ -169,11 +171,12 @@ struct M2LCursor {
   }
 };
 
-// Operands of the cursor's chunk.  alane: this lane's operator row and k half at
-// the slab start; bq[nb]: the float4 index of its target's staged row plus h.
+// Operands of the cursor's chunk.  alane: this lane's float4 of the wave's row
+// block in the slab's first chunk; bq[nb]: the float4 index of its target's
+// staged row plus h.
 __device__ __forceinline__ void m2l_load(M2LRegs& r, const float* __restrict__ alane, const int* bq,
                                          const M2LCursor& cu) {
-  r.a = *reinterpret_cast<const float4*>(alane + cu.aoff + 8 * cu.c);
+  r.a = *reinterpret_cast<const float4*>(alane + cu.aoff + 256 * cu.c);
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) r.b[nb] = s_m2l[bq[nb] + cu.sh + 2 * cu.c];
 }
@@ -245,7 +248,8 @@ __global__ __launch_bounds__(512) void k_m2l(const float* __restrict__ cores, in
     for (int e = 0; e < 16; ++e) acc[nb][e] = 0.f;
   // offset table of the item in one VGPR (lane j holds entry j), read with readlane
   const int po_reg = pair_offs[it.pair * 27 + min(lane, 26)];
-  const float* arow = cores + (size_t)(32 * wave + i32) * ldk + 4 * h;  // this lane's operator row, k half h
+  // this lane's float4 in the wave's row block of the lane-ordered operators
+  const float* ablk = cores + (size_t)wave * 32 * ldk + 4 * lane;
   const size_t core_stride = (size_t)core_rows * ldk;
   const int* srcs = src_blk + it.src_base;
 
@@ -261,7 +265,7 @@ __global__ __launch_bounds__(512) void k_m2l(const float* __restrict__ cores, in
       s_m2l[r * ld4 + c4] = v;
     }
     __syncthreads();
-    m2l_slab(acc, arow + k0, core_stride, po_reg, it.noffs, bq, kw >> 3, ld4);
+    m2l_slab(acc, ablk + 32 * k0, core_stride, po_reg, it.noffs, bq, kw >> 3, ld4);
   }
   // acc[nb][v]: row 32 wave + 8 (v / 4) + 4 h + v % 4, target column 32 nb + i32
   float* out = chat_part + (size_t)it.part * part_stride;
@@ -294,6 +298,205 @@ bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int 
   hipLaunchKernelGGL(k_m2l, dim3(nitems), dim3(64 * row_blocks), lds, s, cores, core_rows, ldk, lds_ld / 4, items,
                      tgt_blk, src_blk, pair_offs, uhat, chat_part, part_stride);
   return true;
+}
+
+// ------------------------------------------------- M2L, split bfloat16 ---
+// The same work items and staging as k_m2l, with every product of the
+// translation computed from bfloat16 pieces on the matrix cores with FP32
+// accumulation.  A value x is split into NP bfloat16 pieces, x_0 the bfloat16
+// rounding of x and x_p that of x - x_0 - ... - x_{p-1}, so that the pieces hold
+// 8 NP significant bits.  The products kept are those of pieces p of the
+// operator and q of the source with p + q < NP, of order 2^-8 (p + q):
+//   NP = 2: a0 b0 + a0 b1 + a1 b0                        (three passes, ~3 * 2^-16)
+//   NP = 3: a0 b0 + a0 b1 + a1 b0 + a0 b2 + a1 b1 + a2 b0 (six passes,  ~2^-24)
+// Operators are split once at plan creation; sources are split while they are
+// staged in LDS.
+//
+// Matrix-core mapping (v_mfma_f32_32x32x16_bf16): one wave per 32 output rows,
+// two 32-column target blocks, k in chunks of 16 (k padded with zeros to a
+// multiple of 16).  Lane (i, h) holds A[i][16c + 8h .. +7] and
+// B^T[j][16c + 8h .. +7] as 8 bfloat16 per piece; the accumulator layout is
+// that of the FP32 kernel.  Per chunk a lane loads the NP operator pieces (16
+// bytes each, global, in lane order) and the NP source pieces of both column
+// blocks (LDS).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ v16f mfma_bf16(const uint4& a, const uint4& b, v16f c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                 0, 0);
+}
+
+template <int NP>
+struct M2LRegsB {
+  uint4 a[NP];
+  uint4 b[2][NP];
+};
+
+// Staged sources, 16-byte units: a row holds, per group g of 8 k values of the
+// slab, the NP pieces of those 8 values in units NP g .. NP g + NP - 1.
+extern __shared__ uint4 s_m2lb[];
+
+constexpr int kM2LSlabB = 32;  // k per LDS slab (two chunks); row stride 8 NP / 2 + 1 units, odd
+
+template <int NP>
+__device__ __forceinline__ void m2lb_load(M2LRegsB<NP>& r, const uint4* __restrict__ alane, const int* bq,
+                                          const M2LCursor& cu) {
+  const uint4* a = alane + cu.aoff + 64 * NP * cu.c;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) r.a[p] = a[64 * p];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+    for (int p = 0; p < NP; ++p) r.b[nb][p] = s_m2lb[bq[nb] + cu.sh + 2 * NP * cu.c + p];
+}
+
+template <int NP>
+__device__ __forceinline__ void m2lb_compute(const M2LRegsB<NP>& r, v16f* acc) {
+  // (operator piece, source piece), largest terms first
+  constexpr int kTerms = NP == 2 ? 3 : 6;
+  constexpr int kPa[6] = {0, 0, 1, 0, 1, 2};
+  constexpr int kPb[6] = {0, 1, 0, 2, 1, 0};
+#pragma unroll
+  for (int t = 0; t < kTerms; ++t)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) acc[nb] = mfma_bf16(r.a[kPa[t]], r.b[nb][kPb[t]], acc[nb]);
+}
+
+// All offsets of the item over one slab of nch chunks, with two register sets.
+template <int NP>
+__device__ __forceinline__ void m2lb_slab(v16f* acc, const uint4* alane, size_t core_stride, int po_reg, int noffs,
+                                          const int* bq, int nch, int ld16) {
+  const int nv = noffs * nch;
+  M2LCursor cu{0, 0, nch, noffs, ld16, po_reg, core_stride, 0, 0};
+  cu.set_offset();
+  M2LRegsB<NP> r0, r1;
+  m2lb_load<NP>(r0, alane, bq, cu);
+  cu.next();
+  for (int v = 0; v < nv; v += 2) {
+    m2lb_load<NP>(r1, alane, bq, cu);
+    cu.next();
+    __builtin_amdgcn_sched_barrier(0);
+    m2lb_compute<NP>(r0, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    m2lb_load<NP>(r0, alane, bq, cu);
+    cu.next();
+    __builtin_amdgcn_sched_barrier(0);
+    if (v + 1 < nv) m2lb_compute<NP>(r1, acc);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+__device__ __forceinline__ uint32_t bf16_bits(__bf16 x) { return __builtin_bit_cast(uint16_t, x); }
+
+// Eight FP32 values split into NP bfloat16 pieces each (piece p of value e in
+// the low (e even) or high (e odd) half of word e / 2 of out[p]).  Each
+// remainder x - x_0 - ... is exact in FP32.
+template <int NP>
+__device__ __forceinline__ void split8(const float4& u, const float4& v, uint4* out) {
+  float x[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    uint32_t w[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const __bf16 h0 = (__bf16)x[2 * e], h1 = (__bf16)x[2 * e + 1];
+      w[e] = bf16_bits(h0) | (bf16_bits(h1) << 16);
+      x[2 * e] -= (float)h0;
+      x[2 * e + 1] -= (float)h1;
+    }
+    out[p] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+template <int NP>
+__global__ __launch_bounds__(512) void k_m2l_bf16(const uint4* __restrict__ cores, size_t core_stride, int ldk,
+                                                  int ld16, const M2LItem* __restrict__ items,
+                                                  const int* __restrict__ tgt_blk, const int* __restrict__ src_blk,
+                                                  const int* __restrict__ pair_offs, const float* __restrict__ uhat,
+                                                  float* __restrict__ chat_part, long long part_stride) {
+  const M2LItem it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;  // 32-row block of the output
+  const int i32 = lane & 31, h = lane >> 5;
+  const int nchunk = ldk >> 4;
+
+  int tslot[2], bq[2];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const int pi = 32 * nb + i32;  // position in the 4x4x4 parent block, x fastest
+    tslot[nb] = tgt_blk[it.tgt_base + pi];
+    const int bbase = ((pi & 3) + 1) + 6 * (((pi >> 2) & 3) + 1) + 36 * ((pi >> 4) + 1) - 43;
+    bq[nb] = bbase * ld16 + NP * h;
+  }
+  v16f acc[2];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[nb][e] = 0.f;
+  const int po_reg = pair_offs[it.pair * 27 + min(lane, 26)];
+  // this lane's piece-0 unit in the wave's row block of the lane-ordered operators
+  const uint4* ablk = cores + (size_t)wave * nchunk * 64 * NP + lane;
+  const int* srcs = src_blk + it.src_base;
+
+  for (int k0 = 0; k0 < ldk; k0 += kM2LSlabB) {
+    const int kw = min(kM2LSlabB, ldk - k0);  // a multiple of 16
+    const int ng = kw >> 3;                    // groups of 8 k
+    if (k0) __syncthreads();
+    for (int idx = tid; idx < 216 * ng; idx += blockDim.x) {
+      const int r = idx / ng, g = idx - r * ng;
+      const int slot = srcs[r];
+      float4 u = make_float4(0.f, 0.f, 0.f, 0.f), v = u;
+      if (slot >= 0) {
+        const float4* src = reinterpret_cast<const float4*>(uhat + (size_t)slot * ldk + k0 + 8 * g);
+        u = src[0];
+        v = src[1];
+      }
+      uint4 pcs[NP];
+      split8<NP>(u, v, pcs);
+#pragma unroll
+      for (int p = 0; p < NP; ++p) s_m2lb[r * ld16 + NP * g + p] = pcs[p];
+    }
+    __syncthreads();
+    m2lb_slab<NP>(acc, ablk + (size_t)(k0 >> 4) * 64 * NP, core_stride, po_reg, it.noffs, bq, kw >> 4, ld16);
+  }
+  float* out = chat_part + (size_t)it.part * part_stride;
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    if (tslot[nb] < 0) continue;
+#pragma unroll
+    for (int b4 = 0; b4 < 4; ++b4) {
+      const int o = 32 * wave + 8 * b4 + 4 * h;
+      if (o < ldk)
+        *reinterpret_cast<float4*>(out + (size_t)tslot[nb] * ldk + o) =
+            make_float4(acc[nb][4 * b4], acc[nb][4 * b4 + 1], acc[nb][4 * b4 + 2], acc[nb][4 * b4 + 3]);
+    }
+  }
+}
+
+int m2l_bf16_lds_ld16(int pieces) { return 4 * pieces + 1; }
+
+bool launch_m2l_bf16(int pieces, int row_blocks, const uint16_t* cores, size_t core_stride16, int ldk, int lds_ld16,
+                     const M2LItem* items, int nitems, const int* tgt_blk, const int* src_blk, const int* pair_offs,
+                     const float* uhat, float* chat_part, long long part_stride, hipStream_t s) {
+  if (nitems <= 0) return true;
+  if (row_blocks < 1 || row_blocks > 8 || (ldk & 15) || (pieces != 2 && pieces != 3) ||
+      lds_ld16 < m2l_bf16_lds_ld16(pieces))
+    return false;
+  const size_t lds = (size_t)216 * lds_ld16 * 16;
+  auto launch = [&](auto kernel, size_t& attr) {
+    if (lds > attr) {
+      if (hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds) != hipSuccess)
+        return false;
+      attr = lds;
+    }
+    hipLaunchKernelGGL(kernel, dim3(nitems), dim3(64 * row_blocks), lds, s, reinterpret_cast<const uint4*>(cores),
+                       core_stride16, ldk, lds_ld16, items, tgt_blk, src_blk, pair_offs, uhat, chat_part, part_stride);
+    return true;
+  };
+  static size_t attr2 = 0, attr3 = 0;
+  return pieces == 2 ? launch(&k_m2l_bf16<2>, attr2) : launch(&k_m2l_bf16<3>, attr3);
 }
 
 // Sum of the eight source positions' partial sums, in a fixed order:

@@ -22,6 +22,14 @@ void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int*
 bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int lds_ld, const M2LItem* items, int nitems,
                 const int* tgt_blk, const int* src_blk, const int* pair_offs, const float* uhat, float* chat_part,
                 long long part_stride, hipStream_t s);
+// The same translation from split-bfloat16 pieces (2 pieces: three matrix-core
+// passes; 3 pieces: six): cores are [316][row block][16-k chunk][piece][64
+// lanes][8] bfloat16 bit patterns; core_stride16 is the size of one offset's
+// operator in 16-byte units; lds_ld16 >= m2l_bf16_lds_ld16(pieces).
+int m2l_bf16_lds_ld16(int pieces);
+bool launch_m2l_bf16(int pieces, int row_blocks, const uint16_t* cores, size_t core_stride16, int ldk, int lds_ld16,
+                     const M2LItem* items, int nitems, const int* tgt_blk, const int* src_blk, const int* pair_offs,
+                     const float* uhat, float* chat_part, long long part_stride, hipStream_t s);
 void launch_sum_parts(const float* part, float* chat, long long n, long long stride, hipStream_t s);
 void launch_permute(float4* pts, const float* charges, const int* order, int n, hipStream_t s);
 void launch_p2m(const float4* pts, const int* start, const int* leaves, const float4* centers, const float* surf, int n,

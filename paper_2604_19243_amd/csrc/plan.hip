@@ -27,6 +27,23 @@ namespace {
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// bfloat16 bit pattern of x: x rounded to FP32, then to its top 16 bits, to
+// nearest with ties to even (finite values).
+uint16_t bf16_round(double x) {
+  const float f = (float)x;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+double bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
 void hip_check(hipError_t e, const char* what) {
   if (e == hipSuccess) return;
   (void)hipGetLastError();
@@ -63,9 +80,10 @@ Plan::~Plan() {
 
 Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
   require(tree && ops, "null tree or ops");
-  require((flags & ~(KIFMM_POTENTIAL | KIFMM_GRADIENT | KIFMM_SERIAL)) == 0 &&
+  require((flags & ~(KIFMM_POTENTIAL | KIFMM_GRADIENT | KIFMM_SERIAL | KIFMM_M2L_BF16X3 | KIFMM_M2L_BF16X6)) == 0 &&
               (flags & (KIFMM_POTENTIAL | KIFMM_GRADIENT)) != 0,
-          "flags must hold POTENTIAL and/or GRADIENT, optionally SERIAL");
+          "flags must hold POTENTIAL and/or GRADIENT, optionally SERIAL and one of M2L_BF16X3, M2L_BF16X6");
+  require(!((flags & KIFMM_M2L_BF16X3) && (flags & KIFMM_M2L_BF16X6)), "M2L_BF16X3 and M2L_BF16X6 exclude each other");
   int ndev = 0;
   hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
   require(device >= 0 && device < ndev, "device index out of range");
@@ -90,7 +108,9 @@ Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
     P->n = O.n;
     P->nst = round_up(O.n, 4);
     P->k = O.k;
-    P->kst = round_up(O.k, 8);  // M2L runs k in chunks of 8 (zero padding)
+    P->m2l_pieces = (flags & KIFMM_M2L_BF16X3) ? 2 : (flags & KIFMM_M2L_BF16X6) ? 3 : 0;
+    // M2L runs k in chunks of 8 (FP32) or 16 (bfloat16), with zero padding
+    P->kst = round_up(O.k, P->m2l_pieces ? 16 : 8);
     P->kc = O.kc;
     P->kcst = round_up(O.kc, 4);
     auto& own = P->owned;
@@ -274,15 +294,47 @@ Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
           for (int c = 0; c < n; ++c)
             wl[((size_t)oc * nst + i) * nst + c] = (float)O.l2l[((size_t)oc * n + i) * n + c];
       P->d_l2l = dev_upload(own, wl.data(), wl.size(), "l2l");
-      // M2L cores: [316][core_rows][kst], rows padded to whole 32-row blocks (one wave each).
+      // M2L cores, rows padded to whole 32-row blocks (one wave each) and stored in
+      // the matrix-core lane order of k_m2l: [316][row block][k chunk of 8][lane][4],
+      // where lane (i, h) = (l % 32, l / 32) holds C[32 rb + i][8 c + 4 h .. + 3].
+      // One wave's operand load for a chunk is then 1 KiB of contiguous memory.
       P->m2l_rb = (kst + 31) / 32;
       P->core_rows = 32 * P->m2l_rb;
-      std::vector<float> wc((size_t)kNumOffsets * P->core_rows * kst, 0.f);
-      for (int t = 0; t < kNumOffsets; ++t)
-        for (int a = 0; a < k; ++a)
-          for (int b = 0; b < k; ++b)
-            wc[((size_t)t * P->core_rows + a) * kst + b] = (float)O.cores[((size_t)t * k + a) * k + b];
-      P->d_cores = dev_upload(own, wc.data(), wc.size(), "m2l cores");
+      if (!P->m2l_pieces) {
+        const int nchunk = kst / 8;
+        std::vector<float> wc((size_t)kNumOffsets * P->core_rows * kst, 0.f);
+        for (int t = 0; t < kNumOffsets; ++t)
+          for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) {
+              const size_t chunk = ((size_t)t * P->m2l_rb + a / 32) * nchunk + b / 8;
+              const int lane = (a % 32) + 32 * ((b % 8) / 4);
+              wc[(chunk * 64 + lane) * 4 + b % 4] = (float)O.cores[((size_t)t * k + a) * k + b];
+            }
+        P->d_cores = dev_upload(own, wc.data(), wc.size(), "m2l cores");
+      } else {
+        // Split-bfloat16 cores: C = C_0 + C_1 (+ C_2), C_0 the bfloat16 rounding
+        // of C (to nearest, ties to even) and each further piece that of the
+        // FP64 remainder.  Layout [316][row block][16-k chunk][piece][64 lanes][8],
+        // lane (i, h) holding C[32 rb + i][16 c + 8 h .. + 7], so that one wave's
+        // load of a piece of a chunk is 1 KiB of contiguous memory.
+        const int np = P->m2l_pieces;
+        const int nchunk = kst / 16;
+        P->core_stride16 = (size_t)P->m2l_rb * nchunk * 64 * np;
+        std::vector<uint16_t> wb((size_t)kNumOffsets * P->core_stride16 * 8, 0);
+        for (int t = 0; t < kNumOffsets; ++t)
+          for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) {
+              double rem = O.cores[((size_t)t * k + a) * k + b];
+              const size_t chunk = ((size_t)t * P->m2l_rb + a / 32) * nchunk + b / 16;
+              const int lane = (a % 32) + 32 * ((b % 16) / 8);
+              for (int q = 0; q < np; ++q) {
+                const uint16_t piece = bf16_round(rem);
+                rem -= bf16_value(piece);
+                wb[((chunk * np + q) * 64 + lane) * 8 + b % 8] = piece;
+              }
+            }
+        P->d_cores_b = dev_upload(own, wb.data(), wb.size(), "m2l split cores");
+      }
 
       // Per-level lists of non-empty boxes' slots (U2U scatter, D2D gather).
       P->d_nbslot.assign(L + 1, nullptr);
@@ -384,9 +436,13 @@ Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
       }
       // Workgroups are dealt to the 8 XCDs round-robin: item b runs on XCD b % 8.
       // Within an XCD's list, items are ordered by (o, o') pair, so that the XCD's
-      // L2 holds the ~24 translation cores of the pair its CUs are working on.
+      // L2 holds the ~24 translation cores of the pair its CUs are working on, and
+      // pairs with more offsets (longer items) come first, so the end of the grid
+      // is made of short items.
       for (auto& v : per_xcd)
-        std::stable_sort(v.begin(), v.end(), [](const M2LItem& a, const M2LItem& b) { return a.pair < b.pair; });
+        std::stable_sort(v.begin(), v.end(), [](const M2LItem& a, const M2LItem& b) {
+          return a.noffs != b.noffs ? a.noffs > b.noffs : a.pair < b.pair;
+        });
       std::vector<M2LItem> items;
       size_t most = 0;
       for (auto& v : per_xcd) most = std::max(most, v.size());
@@ -523,9 +579,15 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
                    0, st);
     P->stage_end(KIFMM_STAGE_COMPRESS, st);
     P->stage_begin(KIFMM_STAGE_M2L, st);
-    if (!launch_m2l(P->m2l_rb, P->d_cores, P->core_rows, kst, P->m2l_lds_ld, P->d_items, P->n_items, P->d_tgt_blk,
-                    P->d_src_blk, P->d_pair_offs, P->d_uhat, P->d_chat_part, (long long)P->total_slots * kst, st))
-      fail(KIFMM_E_DEVICE, "M2L kernel configuration not available");
+    const bool m2l_ok =
+        P->m2l_pieces
+            ? launch_m2l_bf16(P->m2l_pieces, P->m2l_rb, P->d_cores_b, P->core_stride16, kst,
+                              m2l_bf16_lds_ld16(P->m2l_pieces), P->d_items, P->n_items, P->d_tgt_blk, P->d_src_blk,
+                              P->d_pair_offs, P->d_uhat, P->d_chat_part, (long long)P->total_slots * kst, st)
+            : launch_m2l(P->m2l_rb, P->d_cores, P->core_rows, kst, P->m2l_lds_ld, P->d_items, P->n_items,
+                         P->d_tgt_blk, P->d_src_blk, P->d_pair_offs, P->d_uhat, P->d_chat_part,
+                         (long long)P->total_slots * kst, st);
+    if (!m2l_ok) fail(KIFMM_E_DEVICE, "M2L kernel configuration not available");
     P->stage_end(KIFMM_STAGE_M2L, st);
     // (2c) sum of the M2L partial sums, post (DC2E U_k) and D2D, coarse to fine.
     P->stage_begin(KIFMM_STAGE_L2L, st);

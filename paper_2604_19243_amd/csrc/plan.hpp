@@ -40,6 +40,9 @@ struct Plan : Object {
   float* d_zero = nullptr;
   float *d_f1 = nullptr, *d_f2 = nullptr, *d_m2m = nullptr, *d_vt = nullptr, *d_post = nullptr, *d_l2l = nullptr;
   float* d_cores = nullptr;
+  int m2l_pieces = 0;                    // bfloat16 pieces per M2L operand (0: plain FP32)
+  uint16_t* d_cores_b = nullptr;         // split-bfloat16 cores (lane order, all pieces)
+  size_t core_stride16 = 0;              // one offset's split cores, 16-byte units
   std::vector<int*> d_nbslot;
   float* d_chat_part = nullptr;
   int* d_pair_offs = nullptr;

@@ -26,6 +26,8 @@ KIFMM_MAX_DEPTH = 10
 KIFMM_POTENTIAL = 1
 KIFMM_GRADIENT = 2
 KIFMM_SERIAL = 4
+KIFMM_M2L_BF16X3 = 8
+KIFMM_M2L_BF16X6 = 16
 
 (KIFMM_OP_SURFACE, KIFMM_OP_UC2E, KIFMM_OP_DC2E, KIFMM_OP_M2M, KIFMM_OP_L2L, KIFMM_OP_M2L_U, KIFMM_OP_M2L_V,
  KIFMM_OP_M2L_CORE, KIFMM_OP_M2L_OFFSET, KIFMM_OP_M2L_POST) = range(10)

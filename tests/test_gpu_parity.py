@@ -124,10 +124,10 @@ def test_stream_and_outputs_subset():
 
 
 @pytest.mark.parametrize("p,n,depth", [
-    (2, 3_000, 3),    # n = 8 surface points, rank < 16: plain 4-k M2L steps
-    (3, 5_000, 3),    # k = 26: one 16-k chunk and a 12-k tail
-    (7, 8_000, 3),    # k = 122 -> 124: two slabs, tail 12
-    (8, 8_000, 3),    # n = 296, k = 124
+    (2, 3_000, 3),    # n = 8 surface points, k = 8: one 8-k chunk, one 32-row block
+    (3, 5_000, 3),    # k = 26 -> 32 (zero-padded k)
+    (7, 8_000, 3),    # k = 122 -> 128: four 40-k slabs, the last one 8 wide
+    (8, 8_000, 3),    # n = 296, k = 124 -> 128
 ])
 def test_expansion_orders(p, n, depth):
     log(f"order p={p} n={n} depth={depth}")
