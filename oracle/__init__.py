@@ -21,7 +21,8 @@ single-threaded:
                    operators S2U, U2U, U2D, D2D of Table 1, plus the
                    SVD compression of the U2D (M2L) operators.
 * ``fmm``       -- Algorithm 1 steps (1a) S2U, (1b) U2U, (2a) VLI, (2c) D2D,
-                   (3b) D2T and (3c) ULI.
+                   (3b) D2T and (3c) ULI; and the derivative of the evaluate
+                   for a weighted sum of the potentials (``fmm.vjp``).
 
 Readings of points the paper leaves open (kernel normalisation, coincident
 points, surface geometry, pseudo-inverse cutoff, compression scheme) are

@@ -167,6 +167,27 @@ def evaluate(tree, ops, charges, gradient=True, target_leaves=None, return_state
     return phi, grad
 
 
+def vjp(tree, ops, charges, weights, target_leaves=None):
+    """Derivative of the evaluate for the loss L = sum_i w_i f_i, f the potentials
+    of densities s at the tree's points (the tree held fixed).
+
+    dL/ds_j = sum_i w_i K(x_i, x_j): since K is symmetric and the sources are the
+    targets, this is the evaluate applied to the weights (the adjoint FMM, with
+    sources and targets exchanged, is the same operator).
+
+    dL/dx_k = w_k grad f_s(x_k) + s_k grad f_w(x_k): the derivative of f_k through
+    its own position plus that of every other f_i through the source at x_k,
+    using grad_y K(x, y) = -grad_x K(x, y).
+
+    Returns (grad_charges [N], grad_points [N, 3]) in input order (NaN outside
+    `target_leaves` when given).
+    """
+    s = np.asarray(charges, dtype=np.float64)
+    w = np.asarray(weights, dtype=np.float64)
+    phi, grad = evaluate(tree, ops, np.stack([s, w], axis=1), gradient=True, target_leaves=target_leaves)
+    return phi[:, 1], w[:, None] * grad[:, 0, :] + s[:, None] * grad[:, 1, :]
+
+
 def local_field(tree, ops, charges, state, leaf, x):
     """Potential at arbitrary points x inside `leaf` from the leaf's local density and its U list.
 
