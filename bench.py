@@ -131,6 +131,9 @@ def main():
                     help="M2L arithmetic: plain FP32, or split bfloat16 (3 or 6 matrix-core passes, FP32 accumulation)")
     ap.add_argument("--compare-fp32", action="store_true",
                     help="with a split-bfloat16 --m2l: also time the plain FP32 form on the same tree and operators")
+    ap.add_argument("--backward", action="store_true",
+                    help="time forward + backward: evaluate (potentials and field) then the vector-Jacobian "
+                         "product of L = sum w_i f_i (adjoint evaluate + combination)")
     ap.add_argument("--sample-leaves", type=int, default=24)
     ap.add_argument("--sample-seed", type=int, default=2)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -171,6 +174,7 @@ def main():
     bf16 = passes > 0
     m2l_flag = {"fp32": 0, "bf16x3": kifmm.KIFMM_M2L_BF16X3, "bf16x6": kifmm.KIFMM_M2L_BF16X6}[args.m2l]
     flags = kifmm.KIFMM_POTENTIAL | kifmm.KIFMM_GRADIENT | (kifmm.KIFMM_SERIAL if args.serial else 0)
+    flags |= kifmm.KIFMM_VJP if args.backward else 0
     f = kifmm.FMM(x, w.depth, w.p, cube=cube, eps_pinv=1e-7, eps_svd=1e-6, flags=flags | m2l_flag)
     t_setup = time.perf_counter() - t_setup
     info = kifmm.kifmm_ops_get_info(f.ops)
@@ -181,13 +185,22 @@ def main():
     dev = torch.device("cuda:0")
     charges = torch.from_numpy(s).to(dev)
     pot = torch.empty(w.n, device=dev)
-    grad = torch.empty(w.n, 3, device=dev) if w.gradient else None
+    grad = torch.empty(w.n, 3, device=dev) if (w.gradient or args.backward) else None
     stream = torch.cuda.current_stream()
+    if args.backward:
+        weights = torch.from_numpy(workloads.charges("normal", w.n, w.seed + 2000)).to(dev)
+        grad_charges = torch.empty(w.n, device=dev)
+        grad_points = torch.empty(w.n, 3, device=dev)
+
+    def step(plan):
+        kifmm.kifmm_evaluate(plan, charges, pot, grad, stream.cuda_stream)
+        if args.backward:
+            kifmm.kifmm_evaluate_vjp(plan, charges, weights, grad, grad_charges, grad_points, stream.cuda_stream)
 
     def timed(plan, label):
-        """Warm-up, then exactly args.steps evaluates between two events on the evaluate stream."""
+        """Warm-up, then exactly args.steps steps between two events on the evaluate stream."""
         for _ in range(args.warmup):
-            kifmm.kifmm_evaluate(plan, charges, pot, grad, stream.cuda_stream)
+            step(plan)
         torch.cuda.synchronize()
         kifmm.kifmm_plan_set_timing(plan, True)
         kifmm.kifmm_plan_get_stage_times(plan, reset=True)
@@ -196,7 +209,7 @@ def main():
         torch.cuda.synchronize()
         start.record(stream)
         for _ in range(args.steps):
-            kifmm.kifmm_evaluate(plan, charges, pot, grad, stream.cuda_stream)
+            step(plan)
         end.record(stream)
         torch.cuda.synchronize()
         ms_ = start.elapsed_time(end) / args.steps
@@ -253,7 +266,9 @@ def main():
         "config": {"workload": w.name, "n_points": w.n, "distribution": w.distribution, "charges": w.charges,
                    "p": w.p, "n_surface": n, "m2l_rank": k, "depth": w.depth, "nrhs": w.nrhs,
                    "outputs": "potential+gradient" if w.gradient else "potential", "parallelism": "single-gpu",
-                   "uli_overlap": not args.serial, "m2l": args.m2l},
+                   "uli_overlap": not args.serial, "m2l": args.m2l,
+                   "step": ("forward (potentials and field) + backward (vector-Jacobian product of "
+                            "sum w_i f_i, w ~ N(0,1))") if args.backward else "evaluate"},
         "roofline": roofline,
         "p2p": {"kernel": "k_p2p<0>" if args.serial else "k_p2p<1> (ULI, overlapped with the far field)",
                 "bound": "alu", "achieved": p2p_tflops, "peak": PEAK_FP32_TFLOPS,

@@ -179,6 +179,9 @@ kifmm_status kifmm_ops_destroy(kifmm_ops ops);
 #define KIFMM_SERIAL 4u
 #define KIFMM_M2L_BF16X3 8u
 #define KIFMM_M2L_BF16X6 16u
+/* KIFMM_VJP: allocate the workspace of kifmm_evaluate_vjp (two [n][3] float
+ * fields on the device). */
+#define KIFMM_VJP 32u
 
 /*
  * Place a tree and its operators on HIP device `device`: uploads the sorted
@@ -203,6 +206,35 @@ kifmm_status kifmm_plan_create(kifmm_tree tree, kifmm_ops ops, unsigned flags, i
  */
 kifmm_status kifmm_evaluate(kifmm_plan plan, const float* charges, float* potential, float* gradient,
                             void* stream);
+
+/*
+ * Vector-Jacobian product of the evaluate, for a loss L = sum_i w_i f_i with f
+ * the potentials of densities s at the points (the differentiation of the
+ * evaluate; the plan needs KIFMM_VJP):
+ *
+ *   grad_charges[j]   = dL/ds_j = sum_i w_i K(x_i, x_j): the evaluate applied
+ *                       to the weights, i.e. the adjoint FMM with sources and
+ *                       targets exchanged, which for this symmetric kernel and
+ *                       equal source and target sets is the same operator;
+ *   grad_points[k][:] = dL/dx_k = w_k grad f_s(x_k) + s_k grad f_w(x_k), the
+ *                       field of s weighted by w plus the field of w weighted
+ *                       by s (requires KIFMM_GRADIENT).
+ *
+ *   charges      device, [n] float, s in input order.
+ *   weights      device, [n] float, w in input order.
+ *   field        device, [n][3] float, grad f_s from an earlier evaluate of the
+ *                same charges (saves one evaluate); or NULL, and it is computed.
+ *   grad_charges device, [n] float, or NULL.
+ *   grad_points  device, [n][3] float, or NULL.
+ *
+ * At least one output must be non-NULL.  Runs one evaluate of w (and one of s
+ * when grad_points is wanted and field is NULL) and an elementwise kernel on
+ * `stream`; the same buffer and stream rules as kifmm_evaluate apply.  The
+ * tree is fixed: the derivative is that of the evaluate for points that stay
+ * in their leaves.
+ */
+kifmm_status kifmm_evaluate_vjp(kifmm_plan plan, const float* charges, const float* weights, const float* field,
+                                float* grad_charges, float* grad_points, void* stream);
 kifmm_status kifmm_plan_destroy(kifmm_plan plan);
 
 /* ------------------------------------------------- inspection, timing --- */

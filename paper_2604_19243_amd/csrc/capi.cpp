@@ -183,6 +183,13 @@ kifmm_status kifmm_evaluate(kifmm_plan plan, const float* charges, float* potent
   return guarded([&] { evaluate_plan(as_plan(plan), charges, potential, gradient, (hipStream_t)stream); });
 }
 
+kifmm_status kifmm_evaluate_vjp(kifmm_plan plan, const float* charges, const float* weights, const float* field,
+                                float* grad_charges, float* grad_points, void* stream) {
+  return guarded([&] {
+    evaluate_vjp(as_plan(plan), charges, weights, field, grad_charges, grad_points, (hipStream_t)stream);
+  });
+}
+
 kifmm_status kifmm_plan_destroy(kifmm_plan plan) {
   return guarded([&] { release(as_plan(plan)); });
 }

@@ -140,11 +140,20 @@ __device__ __forceinline__ v16f mfma32(float a, float b, v16f c) {
 struct M2LRegs {
   float4 a;
   float4 b[2];
+  bool first;  // first chunk of a group of offsets in this slab
 };
 
 extern __shared__ float4 s_m2l[];  // [216][ld4] float4: the current k-slab of the staged sources
 
 constexpr int kM2LSlab = 40;  // k per LDS slab: 5 chunks of 8; the row stride 44 is an odd number of float4
+
+// The contribution of each group of kM2LFlush offsets over a slab is
+// accumulated from zero and added into the running total when the next group
+// starts: FP32 rounding then grows with the length of these short chains
+// rather than with that of the whole sum (about 23 offsets x k terms, of both
+// signs for signed charges).  Groups of 4 keep almost all of the gain of
+// single offsets at a quarter of the vector-ALU cost.
+constexpr int kM2LFlush = 4;
 
 // Position (offset j, chunk c) in an item's sequence of 8-k chunks over one
 // slab, with the offset's wave-uniform address parts.  Stepping past the end
@@ -179,9 +188,21 @@ __device__ __forceinline__ void m2l_load(M2LRegs& r, const float* __restrict__ a
   r.a = *reinterpret_cast<const float4*>(alane + cu.aoff + 256 * cu.c);
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) r.b[nb] = s_m2l[bq[nb] + cu.sh + 2 * cu.c];
+  r.first = cu.c == 0 && cu.j % kM2LFlush == 0;
 }
 
-__device__ __forceinline__ void m2l_compute(const M2LRegs& r, v16f* acc) {
+// Adds the group's accumulator into the running total and restarts it.
+__device__ __forceinline__ void m2l_flush(v16f* acc, v16f* tot) {
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    tot[nb] += acc[nb];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[nb][e] = 0.f;
+  }
+}
+
+__device__ __forceinline__ void m2l_compute(const M2LRegs& r, v16f* acc, v16f* tot) {
+  if (r.first) m2l_flush(acc, tot);
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) acc[nb] = mfma32(r.a.x, r.b[nb].x, acc[nb]);
 #pragma unroll
@@ -192,32 +213,25 @@ __device__ __forceinline__ void m2l_compute(const M2LRegs& r, v16f* acc) {
   for (int nb = 0; nb < 2; ++nb) acc[nb] = mfma32(r.a.w, r.b[nb].w, acc[nb]);
 }
 
-// All offsets of the item over one slab of nch chunks, with three register sets.
-__device__ __forceinline__ void m2l_slab(v16f* acc, const float* alane, size_t core_stride, int po_reg, int noffs,
-                                         const int* bq, int nch, int ld4) {
+// All offsets of the item over one slab of nch chunks, with two register sets.
+__device__ __forceinline__ void m2l_slab(v16f* acc, v16f* tot, const float* alane, size_t core_stride, int po_reg,
+                                         int noffs, const int* bq, int nch, int ld4) {
   const int nv = noffs * nch;
   M2LCursor cu{0, 0, nch, noffs, ld4, po_reg, core_stride, 0, 0};
   cu.set_offset();
-  M2LRegs r0, r1, r2;
+  M2LRegs r0, r1;
   m2l_load(r0, alane, bq, cu);
   cu.next();
-  m2l_load(r1, alane, bq, cu);
-  cu.next();
-  for (int v = 0; v < nv; v += 3) {
-    m2l_load(r2, alane, bq, cu);
+  for (int v = 0; v < nv; v += 2) {
+    m2l_load(r1, alane, bq, cu);
     cu.next();
     __builtin_amdgcn_sched_barrier(0);
-    m2l_compute(r0, acc);
+    m2l_compute(r0, acc, tot);
     __builtin_amdgcn_sched_barrier(0);
     m2l_load(r0, alane, bq, cu);
     cu.next();
     __builtin_amdgcn_sched_barrier(0);
-    if (v + 1 < nv) m2l_compute(r1, acc);
-    __builtin_amdgcn_sched_barrier(0);
-    m2l_load(r1, alane, bq, cu);
-    cu.next();
-    __builtin_amdgcn_sched_barrier(0);
-    if (v + 2 < nv) m2l_compute(r2, acc);
+    if (v + 1 < nv) m2l_compute(r1, acc, tot);
     __builtin_amdgcn_sched_barrier(0);
   }
 }
@@ -241,11 +255,11 @@ __global__ __launch_bounds__(512) void k_m2l(const float* __restrict__ cores, in
     bbase[nb] = ((pi & 3) + 1) + 6 * (((pi >> 2) & 3) + 1) + 36 * ((pi >> 4) + 1) - 43;
     bq[nb] = bbase[nb] * ld4 + h;
   }
-  v16f acc[2];
+  v16f acc[2], tot[2];
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[nb][e] = 0.f;
+    for (int e = 0; e < 16; ++e) acc[nb][e] = tot[nb][e] = 0.f;
   // offset table of the item in one VGPR (lane j holds entry j), read with readlane
   const int po_reg = pair_offs[it.pair * 27 + min(lane, 26)];
   // this lane's float4 in the wave's row block of the lane-ordered operators
@@ -265,9 +279,10 @@ __global__ __launch_bounds__(512) void k_m2l(const float* __restrict__ cores, in
       s_m2l[r * ld4 + c4] = v;
     }
     __syncthreads();
-    m2l_slab(acc, ablk + 32 * k0, core_stride, po_reg, it.noffs, bq, kw >> 3, ld4);
+    m2l_slab(acc, tot, ablk + 32 * k0, core_stride, po_reg, it.noffs, bq, kw >> 3, ld4);
   }
-  // acc[nb][v]: row 32 wave + 8 (v / 4) + 4 h + v % 4, target column 32 nb + i32
+  m2l_flush(acc, tot);
+  // tot[nb][v]: row 32 wave + 8 (v / 4) + 4 h + v % 4, target column 32 nb + i32
   float* out = chat_part + (size_t)it.part * part_stride;
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
@@ -277,7 +292,7 @@ __global__ __launch_bounds__(512) void k_m2l(const float* __restrict__ cores, in
       const int o = 32 * wave + 8 * b4 + 4 * h;
       if (o < ldk)
         *reinterpret_cast<float4*>(out + (size_t)tslot[nb] * ldk + o) =
-            make_float4(acc[nb][4 * b4], acc[nb][4 * b4 + 1], acc[nb][4 * b4 + 2], acc[nb][4 * b4 + 3]);
+            make_float4(tot[nb][4 * b4], tot[nb][4 * b4 + 1], tot[nb][4 * b4 + 2], tot[nb][4 * b4 + 3]);
     }
   }
 }
@@ -330,6 +345,7 @@ template <int NP>
 struct M2LRegsB {
   uint4 a[NP];
   uint4 b[2][NP];
+  bool first;  // first chunk of a group of offsets in this slab
 };
 
 // Staged sources, 16-byte units: a row holds, per group g of 8 k values of the
@@ -348,14 +364,16 @@ __device__ __forceinline__ void m2lb_load(M2LRegsB<NP>& r, const uint4* __restri
   for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
     for (int p = 0; p < NP; ++p) r.b[nb][p] = s_m2lb[bq[nb] + cu.sh + 2 * NP * cu.c + p];
+  r.first = cu.c == 0 && cu.j % kM2LFlush == 0;
 }
 
 template <int NP>
-__device__ __forceinline__ void m2lb_compute(const M2LRegsB<NP>& r, v16f* acc) {
+__device__ __forceinline__ void m2lb_compute(const M2LRegsB<NP>& r, v16f* acc, v16f* tot) {
   // (operator piece, source piece), largest terms first
   constexpr int kTerms = NP == 2 ? 3 : 6;
   constexpr int kPa[6] = {0, 0, 1, 0, 1, 2};
   constexpr int kPb[6] = {0, 1, 0, 2, 1, 0};
+  if (r.first) m2l_flush(acc, tot);  // short FP32 chains, as in k_m2l
 #pragma unroll
   for (int t = 0; t < kTerms; ++t)
 #pragma unroll
@@ -364,8 +382,8 @@ __device__ __forceinline__ void m2lb_compute(const M2LRegsB<NP>& r, v16f* acc) {
 
 // All offsets of the item over one slab of nch chunks, with two register sets.
 template <int NP>
-__device__ __forceinline__ void m2lb_slab(v16f* acc, const uint4* alane, size_t core_stride, int po_reg, int noffs,
-                                          const int* bq, int nch, int ld16) {
+__device__ __forceinline__ void m2lb_slab(v16f* acc, v16f* tot, const uint4* alane, size_t core_stride, int po_reg,
+                                          int noffs, const int* bq, int nch, int ld16) {
   const int nv = noffs * nch;
   M2LCursor cu{0, 0, nch, noffs, ld16, po_reg, core_stride, 0, 0};
   cu.set_offset();
@@ -376,12 +394,12 @@ __device__ __forceinline__ void m2lb_slab(v16f* acc, const uint4* alane, size_t 
     m2lb_load<NP>(r1, alane, bq, cu);
     cu.next();
     __builtin_amdgcn_sched_barrier(0);
-    m2lb_compute<NP>(r0, acc);
+    m2lb_compute<NP>(r0, acc, tot);
     __builtin_amdgcn_sched_barrier(0);
     m2lb_load<NP>(r0, alane, bq, cu);
     cu.next();
     __builtin_amdgcn_sched_barrier(0);
-    if (v + 1 < nv) m2lb_compute<NP>(r1, acc);
+    if (v + 1 < nv) m2lb_compute<NP>(r1, acc, tot);
     __builtin_amdgcn_sched_barrier(0);
   }
 }
@@ -429,11 +447,11 @@ __global__ __launch_bounds__(512) void k_m2l_bf16(const uint4* __restrict__ core
     const int bbase = ((pi & 3) + 1) + 6 * (((pi >> 2) & 3) + 1) + 36 * ((pi >> 4) + 1) - 43;
     bq[nb] = bbase * ld16 + NP * h;
   }
-  v16f acc[2];
+  v16f acc[2], tot[2];
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[nb][e] = 0.f;
+    for (int e = 0; e < 16; ++e) acc[nb][e] = tot[nb][e] = 0.f;
   const int po_reg = pair_offs[it.pair * 27 + min(lane, 26)];
   // this lane's piece-0 unit in the wave's row block of the lane-ordered operators
   const uint4* ablk = cores + (size_t)wave * nchunk * 64 * NP + lane;
@@ -458,8 +476,9 @@ __global__ __launch_bounds__(512) void k_m2l_bf16(const uint4* __restrict__ core
       for (int p = 0; p < NP; ++p) s_m2lb[r * ld16 + NP * g + p] = pcs[p];
     }
     __syncthreads();
-    m2lb_slab<NP>(acc, ablk + (size_t)(k0 >> 4) * 64 * NP, core_stride, po_reg, it.noffs, bq, kw >> 4, ld16);
+    m2lb_slab<NP>(acc, tot, ablk + (size_t)(k0 >> 4) * 64 * NP, core_stride, po_reg, it.noffs, bq, kw >> 4, ld16);
   }
+  m2l_flush(acc, tot);
   float* out = chat_part + (size_t)it.part * part_stride;
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
@@ -469,7 +488,7 @@ __global__ __launch_bounds__(512) void k_m2l_bf16(const uint4* __restrict__ core
       const int o = 32 * wave + 8 * b4 + 4 * h;
       if (o < ldk)
         *reinterpret_cast<float4*>(out + (size_t)tslot[nb] * ldk + o) =
-            make_float4(acc[nb][4 * b4], acc[nb][4 * b4 + 1], acc[nb][4 * b4 + 2], acc[nb][4 * b4 + 3]);
+            make_float4(tot[nb][4 * b4], tot[nb][4 * b4 + 1], tot[nb][4 * b4 + 2], tot[nb][4 * b4 + 3]);
     }
   }
 }
@@ -522,6 +541,22 @@ void launch_sum_parts(const float* part, float* chat, long long n, long long str
   if (n4 <= 0) return;
   hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s,
                      reinterpret_cast<const float4*>(part), reinterpret_cast<float4*>(chat), n4, stride / 4);
+}
+
+// ----------------------------------------------------------------- VJP ---
+// dL/dx_k = w_k grad f_s(x_k) + s_k grad f_w(x_k), elementwise over [n][3].
+__global__ void k_vjp_combine(const float* __restrict__ s, const float* __restrict__ w, const float* __restrict__ fs,
+                              const float* __restrict__ fw, float* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * n) return;
+  const int k = i / 3;
+  out[i] = w[k] * fs[i] + s[k] * fw[i];
+}
+
+void launch_vjp_combine(const float* s, const float* w, const float* fs, const float* fw, float* out, int n,
+                        hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_vjp_combine, dim3((3 * n + 255) / 256), dim3(256), 0, st, s, w, fs, fw, out, n);
 }
 
 // ------------------------------------------------------------- permute ---

@@ -31,6 +31,9 @@ bool launch_m2l_bf16(int pieces, int row_blocks, const uint16_t* cores, size_t c
                      const M2LItem* items, int nitems, const int* tgt_blk, const int* src_blk, const int* pair_offs,
                      const float* uhat, float* chat_part, long long part_stride, hipStream_t s);
 void launch_sum_parts(const float* part, float* chat, long long n, long long stride, hipStream_t s);
+// out[k][c] = w[k] fs[k][c] + s[k] fw[k][c] for k < n, c < 3.
+void launch_vjp_combine(const float* s, const float* w, const float* fs, const float* fw, float* out, int n,
+                        hipStream_t st);
 void launch_permute(float4* pts, const float* charges, const int* order, int n, hipStream_t s);
 void launch_p2m(const float4* pts, const int* start, const int* leaves, const float4* centers, const float* surf, int n,
                 float alpha, float* q, int ldq, int nleaves, hipStream_t s);

@@ -80,9 +80,10 @@ Plan::~Plan() {
 
 Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
   require(tree && ops, "null tree or ops");
-  require((flags & ~(KIFMM_POTENTIAL | KIFMM_GRADIENT | KIFMM_SERIAL | KIFMM_M2L_BF16X3 | KIFMM_M2L_BF16X6)) == 0 &&
+  require((flags & ~(KIFMM_POTENTIAL | KIFMM_GRADIENT | KIFMM_SERIAL | KIFMM_M2L_BF16X3 | KIFMM_M2L_BF16X6 |
+                     KIFMM_VJP)) == 0 &&
               (flags & (KIFMM_POTENTIAL | KIFMM_GRADIENT)) != 0,
-          "flags must hold POTENTIAL and/or GRADIENT, optionally SERIAL and one of M2L_BF16X3, M2L_BF16X6");
+          "flags must hold POTENTIAL and/or GRADIENT, optionally SERIAL, VJP and one of M2L_BF16X3, M2L_BF16X6");
   require(!((flags & KIFMM_M2L_BF16X3) && (flags & KIFMM_M2L_BF16X6)), "M2L_BF16X3 and M2L_BF16X6 exclude each other");
   int ndev = 0;
   hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
@@ -469,6 +470,10 @@ Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
       hip_check(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming), "hipEventCreate");
       P->d_near = reinterpret_cast<float4*>(dev_upload<float>(own, nullptr, 4 * (size_t)T.n, "near field"));
     }
+    if (flags & KIFMM_VJP) {
+      P->d_vjp_fs = dev_upload<float>(own, nullptr, 3 * (size_t)T.n, "vjp field");
+      P->d_vjp_fw = dev_upload<float>(own, nullptr, 3 * (size_t)T.n, "vjp field");
+    }
     hip_check(hipDeviceSynchronize(), "plan upload");
   } catch (...) {
     delete P;
@@ -622,6 +627,29 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
   }
   hip_check(hipGetLastError(), "kernel launch");
   if (prev != P->device) (void)hipSetDevice(prev);
+}
+
+void evaluate_vjp(Plan* P, const float* charges, const float* weights, const float* field, float* grad_charges,
+                  float* grad_points, hipStream_t st) {
+  require(P->flags & KIFMM_VJP, "plan was created without KIFMM_VJP");
+  require(charges != nullptr && weights != nullptr, "charges or weights is null");
+  require(grad_charges || grad_points, "at least one of grad_charges / grad_points must be given");
+  require(!grad_points || (P->flags & KIFMM_GRADIENT), "grad_points needs a plan with KIFMM_GRADIENT");
+  // dL/ds = evaluate(w); dL/dx = w grad f_s + s grad f_w.
+  const float* fs = field;
+  if (grad_points && !fs) {
+    evaluate_plan(P, charges, nullptr, P->d_vjp_fs, st);
+    fs = P->d_vjp_fs;
+  }
+  evaluate_plan(P, weights, grad_charges, grad_points ? P->d_vjp_fw : nullptr, st);
+  if (grad_points) {
+    int prev = 0;
+    hip_check(hipGetDevice(&prev), "hipGetDevice");
+    if (prev != P->device) hip_check(hipSetDevice(P->device), "hipSetDevice");
+    launch_vjp_combine(charges, weights, fs, P->d_vjp_fw, grad_points, (int)P->N, st);
+    hip_check(hipGetLastError(), "kernel launch");
+    if (prev != P->device) (void)hipSetDevice(prev);
+  }
 }
 
 void read_density(Plan* P, int kind, int level, float* out, int64_t capacity) {

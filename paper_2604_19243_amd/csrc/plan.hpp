@@ -56,6 +56,8 @@ struct Plan : Object {
   hipStream_t side = nullptr;            // ULI stream (default priority)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   float4* d_near = nullptr;              // ULI result in sorted order (phi, grad)
+  float* d_vjp_fs = nullptr;             // KIFMM_VJP: grad f of the charges, [n][3], input order
+  float* d_vjp_fw = nullptr;             // KIFMM_VJP: grad f of the weights, [n][3], input order
 
   bool timing = false;
   std::vector<hipEvent_t> ev;            // [kRing][KIFMM_N_STAGES][2]
@@ -73,6 +75,8 @@ struct Plan : Object {
 
 Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device);
 void evaluate_plan(Plan* plan, const float* charges, float* pot, float* grad, hipStream_t st);
+void evaluate_vjp(Plan* plan, const float* charges, const float* weights, const float* field, float* grad_charges,
+                  float* grad_points, hipStream_t st);
 void read_density(Plan* plan, int kind, int level, float* out, int64_t capacity);
 
 }  // namespace kifmm

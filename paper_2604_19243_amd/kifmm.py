@@ -28,6 +28,7 @@ KIFMM_GRADIENT = 2
 KIFMM_SERIAL = 4
 KIFMM_M2L_BF16X3 = 8
 KIFMM_M2L_BF16X6 = 16
+KIFMM_VJP = 32
 
 (KIFMM_OP_SURFACE, KIFMM_OP_UC2E, KIFMM_OP_DC2E, KIFMM_OP_M2M, KIFMM_OP_L2L, KIFMM_OP_M2L_U, KIFMM_OP_M2L_V,
  KIFMM_OP_M2L_CORE, KIFMM_OP_M2L_OFFSET, KIFMM_OP_M2L_POST) = range(10)
@@ -82,6 +83,7 @@ def library():
         "kifmm_ops_destroy": (ctypes.c_int, [_VP]),
         "kifmm_plan_create": (ctypes.c_int, [_VP, _VP, ctypes.c_uint, ctypes.c_int, ctypes.POINTER(_VP)]),
         "kifmm_evaluate": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+        "kifmm_evaluate_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
         "kifmm_plan_destroy": (ctypes.c_int, [_VP]),
         "kifmm_plan_set_timing": (ctypes.c_int, [_VP, ctypes.c_int]),
         "kifmm_plan_get_stage_times": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int]),
@@ -194,6 +196,13 @@ def kifmm_evaluate(plan, charges, potential=None, gradient=None, stream=None):
     _check(library().kifmm_evaluate(plan, _dev_ptr(charges), _dev_ptr(potential), _dev_ptr(gradient), s))
 
 
+def kifmm_evaluate_vjp(plan, charges, weights, field=None, grad_charges=None, grad_points=None, stream=None):
+    """Vector-Jacobian product of the evaluate for L = sum_i w_i f_i (device arrays; see the header)."""
+    s = None if stream is None else ctypes.c_void_p(int(stream))
+    _check(library().kifmm_evaluate_vjp(plan, _dev_ptr(charges), _dev_ptr(weights), _dev_ptr(field),
+                                        _dev_ptr(grad_charges), _dev_ptr(grad_points), s))
+
+
 def kifmm_plan_destroy(plan):
     _check(library().kifmm_plan_destroy(plan))
 
@@ -236,6 +245,9 @@ class FMM:
 
     def evaluate(self, charges, potential=None, gradient=None, stream=None):
         kifmm_evaluate(self.plan, charges, potential, gradient, stream)
+
+    def vjp(self, charges, weights, field=None, grad_charges=None, grad_points=None, stream=None):
+        kifmm_evaluate_vjp(self.plan, charges, weights, field, grad_charges, grad_points, stream)
 
     def close(self):
         for attr, fn in (("plan", kifmm_plan_destroy), ("ops", kifmm_ops_destroy), ("tree", kifmm_tree_destroy)):
