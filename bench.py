@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--backward", action="store_true",
                     help="time forward + backward: evaluate (potentials and field) then the vector-Jacobian "
                          "product of L = sum w_i f_i (adjoint evaluate + combination)")
+    ap.add_argument("--compare-single", action="store_true",
+                    help="with a multi-RHS workload: also time a one-RHS plan on the same tree and operators")
     ap.add_argument("--sample-leaves", type=int, default=24)
     ap.add_argument("--sample-seed", type=int, default=2)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -173,9 +175,16 @@ def main():
     passes = {"fp32": 0, "bf16x3": 3, "bf16x6": 6}[args.m2l]
     bf16 = passes > 0
     m2l_flag = {"fp32": 0, "bf16x3": kifmm.KIFMM_M2L_BF16X3, "bf16x6": kifmm.KIFMM_M2L_BF16X6}[args.m2l]
-    flags = kifmm.KIFMM_POTENTIAL | kifmm.KIFMM_GRADIENT | (kifmm.KIFMM_SERIAL if args.serial else 0)
-    flags |= kifmm.KIFMM_VJP if args.backward else 0
-    f = kifmm.FMM(x, w.depth, w.p, cube=cube, eps_pinv=1e-7, eps_svd=1e-6, flags=flags | m2l_flag)
+    R = w.nrhs
+    if R > 1:
+        # several right-hand sides: potentials, one stream
+        if args.backward:
+            raise SystemExit("--backward needs a one-RHS workload")
+        flags = kifmm.KIFMM_POTENTIAL
+    else:
+        flags = kifmm.KIFMM_POTENTIAL | kifmm.KIFMM_GRADIENT | (kifmm.KIFMM_SERIAL if args.serial else 0)
+        flags |= kifmm.KIFMM_VJP if args.backward else 0
+    f = kifmm.FMM(x, w.depth, w.p, cube=cube, eps_pinv=1e-7, eps_svd=1e-6, flags=flags | m2l_flag, nrhs=R)
     t_setup = time.perf_counter() - t_setup
     info = kifmm.kifmm_ops_get_info(f.ops)
     stats = kifmm.kifmm_plan_get_stats(f.plan)
@@ -184,16 +193,18 @@ def main():
 
     dev = torch.device("cuda:0")
     charges = torch.from_numpy(s).to(dev)
-    pot = torch.empty(w.n, device=dev)
-    grad = torch.empty(w.n, 3, device=dev) if (w.gradient or args.backward) else None
+    pot = torch.empty(w.n, device=dev) if R == 1 else torch.empty(w.n, R, device=dev)
+    grad = torch.empty(w.n, 3, device=dev) if (R == 1 and (w.gradient or args.backward)) else None
     stream = torch.cuda.current_stream()
     if args.backward:
         weights = torch.from_numpy(workloads.charges("normal", w.n, w.seed + 2000)).to(dev)
         grad_charges = torch.empty(w.n, device=dev)
         grad_points = torch.empty(w.n, 3, device=dev)
 
+    io = {"charges": charges, "pot": pot}
+
     def step(plan):
-        kifmm.kifmm_evaluate(plan, charges, pot, grad, stream.cuda_stream)
+        kifmm.kifmm_evaluate(plan, io["charges"], io["pot"], grad, stream.cuda_stream)
         if args.backward:
             kifmm.kifmm_evaluate_vjp(plan, charges, weights, grad, grad_charges, grad_points, stream.cuda_stream)
 
@@ -223,8 +234,16 @@ def main():
     ms, stages = timed(f.plan, "m2l " + args.m2l)
     phi_sample = pot.cpu().numpy()[idx].astype(np.float64)
     fp32_form = None
+    single = None
+    if R > 1 and args.compare_single:
+        plan1 = kifmm.kifmm_plan_create(f.tree, f.ops, 1, kifmm.KIFMM_POTENTIAL | m2l_flag)
+        io.update(charges=charges[:, 0].contiguous(), pot=torch.empty(w.n, device=dev))
+        ms1, stages1 = timed(plan1, "one right-hand side")
+        kifmm.kifmm_plan_destroy(plan1)
+        io.update(charges=charges, pot=pot)
+        single = {"ms_per_evaluate": ms1, "stages_ms": stages1, "batching_speedup": R * ms1 / ms}
     if bf16 and args.compare_fp32:
-        plan32 = kifmm.kifmm_plan_create(f.tree, f.ops, flags)
+        plan32 = kifmm.kifmm_plan_create(f.tree, f.ops, R, flags)
         ms32, stages32 = timed(plan32, "m2l fp32")
         phi32_sample = pot.cpu().numpy()[idx].astype(np.float64)
         kifmm.kifmm_plan_destroy(plan32)
@@ -234,17 +253,20 @@ def main():
     # M2L (dominant kernel): 2 k^2 FLOP per (target, source) V-list pair; the split-bfloat16
     # forms execute each product as 3 or 6 bfloat16 products, counted against the BF16 peak.
     m2l_ms = stages["m2l"]
-    m2l_flop = 2.0 * k * k * stats["m2l_pairs"]
+    m2l_flop = 2.0 * k * k * stats["m2l_pairs"] * R
     m2l_tflops = m2l_flop / (m2l_ms * 1e-3) / 1e12
     m2l_kernel = f"k_m2l_bf16<{passes // 3 + 1}>" if bf16 else "k_m2l"
     traffic = load_traffic(w.name, m2l_kernel)
     # Leaf kernels: 20 FLOP per U-list pair (ULI) and per (target, downward-equivalent point) pair (D2T).
     # By default ULI runs on the plan's own stream beside the far field and D2T is a separate
     # kernel; with --serial one fused kernel does both.
+    # Potentials only: 9 + 2R FLOP per pair (the geometry once, 2 per right-hand side).
     p2p_ms = stages["p2p"]
+    fused = args.serial or R > 1
+    flop_pair = P2P_FLOPS_PER_PAIR if grad is not None else 9 + 2 * R
     d2t_pairs = w.n * n * (1 if w.depth >= 2 else 0)
-    p2p_pairs = stats["p2p_pairs"] + (d2t_pairs if args.serial else 0)
-    p2p_tflops = P2P_FLOPS_PER_PAIR * p2p_pairs / (p2p_ms * 1e-3) / 1e12
+    p2p_pairs = stats["p2p_pairs"] + (d2t_pairs if fused else 0)
+    p2p_tflops = flop_pair * p2p_pairs / (p2p_ms * 1e-3) / 1e12
     l2p_ms = stages["l2p"]
     if bf16:
         roofline = {"kernel": m2l_kernel, "bound": "mfma", "achieved": passes * m2l_tflops,
@@ -270,17 +292,22 @@ def main():
                    "step": ("forward (potentials and field) + backward (vector-Jacobian product of "
                             "sum w_i f_i, w ~ N(0,1))") if args.backward else "evaluate"},
         "roofline": roofline,
-        "p2p": {"kernel": "k_p2p<0>" if args.serial else "k_p2p<1> (ULI, overlapped with the far field)",
+        "p2p": {"kernel": (f"k_leaf_multi<{R}> (fused D2T + ULI)" if R > 1 else
+                           "k_p2p<0>" if args.serial else "k_p2p<1> (ULI, overlapped with the far field)"),
                 "bound": "alu", "achieved": p2p_tflops, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": p2p_tflops / PEAK_FP32_TFLOPS, "ms_per_launch": p2p_ms,
-                "pairs_per_launch": p2p_pairs, "flop_per_pair": P2P_FLOPS_PER_PAIR,
-                "d2t_ms_per_launch": None if args.serial else l2p_ms, "d2t_pairs_per_launch": d2t_pairs},
+                "pairs_per_launch": p2p_pairs, "flop_per_pair": flop_pair,
+                "d2t_ms_per_launch": None if fused else l2p_ms, "d2t_pairs_per_launch": d2t_pairs},
         "stages_ms": stages,
         "setup_s": t_setup,
         "cpu_baseline": None,
     }
     if fp32_form is not None:
         result["fp32_form"] = fp32_form
+    if R > 1:
+        result["point_rhs_per_s"] = w.n * R / (ms * 1e-3)
+    if single is not None:
+        result["single_rhs"] = single
 
     # The oracle leg (a child process with single-threaded BLAS): the direct sum at the sampled
     # targets for the accuracy figures and, unless skipped, the oracle timed on a bounded sample.

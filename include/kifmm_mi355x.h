@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define KIFMM_ABI_VERSION 1
+#define KIFMM_ABI_VERSION 2
 #define KIFMM_MAX_DEPTH 10
 
 typedef enum {
@@ -188,17 +188,25 @@ kifmm_status kifmm_ops_destroy(kifmm_ops ops);
  * points, interaction tables and FP32 operators, and allocates all workspace,
  * so that kifmm_evaluate allocates nothing and never synchronises the host.
  * Blocks until the uploads are complete.
+ *
+ * nrhs: right-hand sides per evaluate (charge vectors sharing the points), 1,
+ * 2, 4, 8, 16 or 32.  With nrhs > 1 the translations of all right-hand sides
+ * run as one batch and the leaf kernels compute each pair's geometry once for
+ * all of them; such plans give potentials only (no KIFMM_GRADIENT, no
+ * KIFMM_VJP) and run on the caller's stream alone.
  */
-kifmm_status kifmm_plan_create(kifmm_tree tree, kifmm_ops ops, unsigned flags, int device, kifmm_plan* out);
+kifmm_status kifmm_plan_create(kifmm_tree tree, kifmm_ops ops, int nrhs, unsigned flags, int device,
+                               kifmm_plan* out);
 
 /*
  * One FMM evaluate (Algorithm 1) on `stream` (a hipStream_t; NULL = the null
  * stream), asynchronous with respect to the host:
  *
- *   charges    device, [n] float, densities s in input order.
- *   potential  device, [n] float, receives f in input order; or NULL.
+ *   charges    device, [n][nrhs] float, densities s in input order (the nrhs
+ *              right-hand sides of a point contiguous).
+ *   potential  device, [n][nrhs] float, receives f in input order; or NULL.
  *   gradient   device, [n][3] float, receives grad f in input order; or NULL
- *              (requires KIFMM_GRADIENT at plan creation).
+ *              (requires KIFMM_GRADIENT at plan creation, hence nrhs = 1).
  *
  * At least one output must be non-NULL.  The buffers must stay valid until
  * the stream has passed this call's last kernel; the plan may not be used on
@@ -262,7 +270,8 @@ kifmm_status kifmm_plan_get_stage_times(kifmm_plan plan, double* ms, int64_t* co
 /* Plan shape: box counts and work counts used for roofline accounting.
  *   stats[0] = leaf-level pairs (target point, source point) of the U-list sum
  *   stats[1] = V-list (target box, source box) pairs over levels 2..L
- *   stats[2] = leaf slots, stats[3] = M2L target boxes, stats[4] = k, stats[5] = n */
+ *   stats[2] = leaf slots, stats[3] = M2L target boxes, stats[4] = k, stats[5] = n,
+ *   stats[6] = right-hand sides per evaluate */
 kifmm_status kifmm_plan_get_stats(kifmm_plan plan, int64_t* stats, int count);
 
 /* Copy a level's densities to the host after the stream is idle, as float in

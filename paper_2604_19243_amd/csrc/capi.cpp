@@ -171,11 +171,12 @@ kifmm_status kifmm_ops_destroy(kifmm_ops ops) {
   return guarded([&] { release(as_ops(ops)); });
 }
 
-kifmm_status kifmm_plan_create(kifmm_tree tree, kifmm_ops ops, unsigned flags, int device, kifmm_plan* out) {
+kifmm_status kifmm_plan_create(kifmm_tree tree, kifmm_ops ops, int nrhs, unsigned flags, int device,
+                               kifmm_plan* out) {
   return guarded([&] {
     require(out != nullptr, "out is null");
     *out = nullptr;
-    *out = reinterpret_cast<kifmm_plan>(create_plan(as_tree(tree), as_ops(ops), flags, device));
+    *out = reinterpret_cast<kifmm_plan>(create_plan(as_tree(tree), as_ops(ops), nrhs, flags, device));
   });
 }
 
@@ -222,8 +223,9 @@ kifmm_status kifmm_plan_get_stats(kifmm_plan plan, int64_t* stats, int count) {
   return guarded([&] {
     const Plan* p = as_plan(plan);
     require(stats != nullptr && count >= 0, "output is null");
-    const int64_t v[6] = {p->p2p_pairs, p->m2l_pairs, p->far ? p->slots[p->L] : 0, p->m2l_targets, p->k, p->n};
-    for (int i = 0; i < count && i < 6; ++i) stats[i] = v[i];
+    const int64_t v[7] = {p->p2p_pairs, p->m2l_pairs, p->far ? p->slots[p->L] : 0, p->m2l_targets, p->k, p->n,
+                          p->nrhs};
+    for (int i = 0; i < count && i < 7; ++i) stats[i] = v[i];
   });
 }
 

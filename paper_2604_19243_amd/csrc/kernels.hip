@@ -39,7 +39,9 @@ __device__ __forceinline__ v4f mfma16x4(const float4 a, const float4 b, v4f c) {
 __global__ __launch_bounds__(256) void k_gemm_nt(const float* __restrict__ W, int ldw, const float* __restrict__ X,
                                                  int ldx, const int* __restrict__ xrow, float* __restrict__ Y, int ldy,
                                                  const int* __restrict__ yrow, int nbox, int nout, int K, float alpha,
-                                                 int beta) {
+                                                 int beta, long long xbs, long long ybs) {
+  X += blockIdx.z * xbs;  // batch (right-hand side) blockIdx.z
+  Y += blockIdx.z * ybs;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int i16 = lane & 15, q = lane >> 4;
@@ -104,10 +106,12 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const float* __restrict__ W, in
 }
 
 void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int* xrow, float* Y, int ldy,
-                    const int* yrow, int nbox, int nout, int K, float alpha, int beta, hipStream_t s) {
-  if (nbox <= 0) return;
-  dim3 grid((nbox + 63) / 64, (nout + 63) / 64);
-  hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, s, W, ldw, X, ldx, xrow, Y, ldy, yrow, nbox, nout, K, alpha, beta);
+                    const int* yrow, int nbox, int nout, int K, float alpha, int beta, hipStream_t s, int batch,
+                    long long xbs, long long ybs) {
+  if (nbox <= 0 || batch <= 0) return;
+  dim3 grid((nbox + 63) / 64, (nout + 63) / 64, batch);
+  hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, s, W, ldw, X, ldx, xrow, Y, ldy, yrow, nbox, nout, K, alpha, beta,
+                     xbs, ybs);
 }
 
 // ----------------------------------------------------------------- M2L ---
@@ -240,8 +244,10 @@ __global__ __launch_bounds__(512) void k_m2l(const float* __restrict__ cores, in
                                              const M2LItem* __restrict__ items, const int* __restrict__ tgt_blk,
                                              const int* __restrict__ src_blk, const int* __restrict__ pair_offs,
                                              const float* __restrict__ uhat, float* __restrict__ chat_part,
-                                             long long part_stride) {
+                                             long long part_stride, long long rhs_stride) {
   const M2LItem it = items[blockIdx.x];
+  uhat += blockIdx.y * rhs_stride;  // right-hand side blockIdx.y
+  chat_part += blockIdx.y * rhs_stride;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;  // 32-row block of the output
@@ -299,8 +305,8 @@ __global__ __launch_bounds__(512) void k_m2l(const float* __restrict__ cores, in
 
 bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int lds_ld, const M2LItem* items,
                 int nitems, const int* tgt_blk, const int* src_blk, const int* pair_offs, const float* uhat,
-                float* chat_part, long long part_stride, hipStream_t s) {
-  if (nitems <= 0) return true;
+                float* chat_part, long long part_stride, int nrhs, long long rhs_stride, hipStream_t s) {
+  if (nitems <= 0 || nrhs <= 0) return true;
   if (row_blocks < 1 || row_blocks > 8 || (ldk & 7) || lds_ld < kM2LSlab || (lds_ld & 3)) return false;
   const size_t lds = (size_t)216 * lds_ld * sizeof(float);
   static size_t attr = 0;
@@ -310,8 +316,8 @@ bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int 
       return false;
     attr = lds;
   }
-  hipLaunchKernelGGL(k_m2l, dim3(nitems), dim3(64 * row_blocks), lds, s, cores, core_rows, ldk, lds_ld / 4, items,
-                     tgt_blk, src_blk, pair_offs, uhat, chat_part, part_stride);
+  hipLaunchKernelGGL(k_m2l, dim3(nitems, nrhs), dim3(64 * row_blocks), lds, s, cores, core_rows, ldk, lds_ld / 4,
+                     items, tgt_blk, src_blk, pair_offs, uhat, chat_part, part_stride, rhs_stride);
   return true;
 }
 
@@ -431,8 +437,11 @@ __global__ __launch_bounds__(512) void k_m2l_bf16(const uint4* __restrict__ core
                                                   int ld16, const M2LItem* __restrict__ items,
                                                   const int* __restrict__ tgt_blk, const int* __restrict__ src_blk,
                                                   const int* __restrict__ pair_offs, const float* __restrict__ uhat,
-                                                  float* __restrict__ chat_part, long long part_stride) {
+                                                  float* __restrict__ chat_part, long long part_stride,
+                                                  long long rhs_stride) {
   const M2LItem it = items[blockIdx.x];
+  uhat += blockIdx.y * rhs_stride;  // right-hand side blockIdx.y
+  chat_part += blockIdx.y * rhs_stride;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;  // 32-row block of the output
@@ -497,8 +506,9 @@ int m2l_bf16_lds_ld16(int pieces) { return 4 * pieces + 1; }
 
 bool launch_m2l_bf16(int pieces, int row_blocks, const uint16_t* cores, size_t core_stride16, int ldk, int lds_ld16,
                      const M2LItem* items, int nitems, const int* tgt_blk, const int* src_blk, const int* pair_offs,
-                     const float* uhat, float* chat_part, long long part_stride, hipStream_t s) {
-  if (nitems <= 0) return true;
+                     const float* uhat, float* chat_part, long long part_stride, int nrhs, long long rhs_stride,
+                     hipStream_t s) {
+  if (nitems <= 0 || nrhs <= 0) return true;
   if (row_blocks < 1 || row_blocks > 8 || (ldk & 15) || (pieces != 2 && pieces != 3) ||
       lds_ld16 < m2l_bf16_lds_ld16(pieces))
     return false;
@@ -510,8 +520,9 @@ bool launch_m2l_bf16(int pieces, int row_blocks, const uint16_t* cores, size_t c
         return false;
       attr = lds;
     }
-    hipLaunchKernelGGL(kernel, dim3(nitems), dim3(64 * row_blocks), lds, s, reinterpret_cast<const uint4*>(cores),
-                       core_stride16, ldk, lds_ld16, items, tgt_blk, src_blk, pair_offs, uhat, chat_part, part_stride);
+    hipLaunchKernelGGL(kernel, dim3(nitems, nrhs), dim3(64 * row_blocks), lds, s,
+                       reinterpret_cast<const uint4*>(cores), core_stride16, ldk, lds_ld16, items, tgt_blk, src_blk,
+                       pair_offs, uhat, chat_part, part_stride, rhs_stride);
     return true;
   };
   static size_t attr2 = 0, attr3 = 0;
@@ -833,6 +844,197 @@ bool launch_p2p(int mode, const float4* pts, const int* start, const int* blk, i
   if (mode == 1) return launch(&k_p2p<1>, attr1);
   if (mode == 2) return launch(&k_p2p<2>, attr2);
   return false;
+}
+
+// ---------------------------------------------------- multi-RHS leaves ---
+// R right-hand sides (R = 2, 4, ..., 32), potentials only.  Sorted charges are
+// [N][R] (a point's R charges contiguous) and every leaf kernel runs one wave
+// per leaf (or per 64 of its points) with the sources of a step common to the
+// whole wave, so that a source's position and charges are wave-uniform loads
+// and the geometry and reciprocal distance of a pair serve all R sums.
+
+// qs[i][r] = charges[order[i]][r].
+__global__ void k_permute_multi(float* __restrict__ qs, const float* __restrict__ charges,
+                                const int* __restrict__ order, int n, int R) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)n * R) return;
+  const long long p = i / R;
+  qs[i] = charges[(long long)order[p] * R + (i - p * R)];
+}
+
+void launch_permute_multi(float* qs, const float* charges, const int* order, int n, int R, hipStream_t s) {
+  const long long total = (long long)n * R;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_permute_multi, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, qs, charges, order, n,
+                     R);
+}
+
+// S2U first half for R right-hand sides: q[r][slot][m] for the check points m
+// (lanes) of one leaf per wave; sources in the leaf's order, centre-relative.
+template <int R>
+__global__ __launch_bounds__(256) void k_p2m_multi(const float4* __restrict__ pts, const float* __restrict__ qs,
+                                                   const int* __restrict__ start, const int* __restrict__ leaves,
+                                                   const float4* __restrict__ centers, const float* __restrict__ surf,
+                                                   int n, float alpha, float* __restrict__ q, int ldq, long long qrs,
+                                                   int nleaves) {
+  const int leaf = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (leaf >= nleaves) return;
+  const int lane = threadIdx.x & 63;
+  const int slot = leaves[leaf];
+  const float4 ch = centers[2 * slot], cl = centers[2 * slot + 1];
+  const float sc = alpha * ch.w;
+  const int s0 = start[slot], s1 = start[slot + 1];
+  for (int m0 = 0; m0 < n; m0 += 64) {
+    const int m = m0 + lane;
+    const int mc = min(m, n - 1);  // lanes past n repeat the last point and store nothing
+    const float px = sc * surf[3 * mc], py = sc * surf[3 * mc + 1], pz = sc * surf[3 * mc + 2];
+    float acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.f;
+#pragma unroll 1
+    for (int j = s0; j < s1; ++j) {
+      const float4 y = pts[j];
+      const float dx = px - ((y.x - ch.x) - cl.x);
+      const float dy = py - ((y.y - ch.y) - cl.y);
+      const float dz = pz - ((y.z - ch.z) - cl.z);
+      const float rinv = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+      const float* qj = qs + (size_t)j * R;
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += qj[r] * rinv;
+    }
+    if (m < n) {
+      float* out = q + (size_t)slot * ldq + m;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        *out = acc[r];
+        out += qrs;
+      }
+    }
+  }
+}
+
+bool launch_p2m_multi(int R, const float4* pts, const float* qs, const int* start, const int* leaves,
+                      const float4* centers, const float* surf, int n, float alpha, float* q, int ldq, long long qrs,
+                      int nleaves, hipStream_t s) {
+  if (nleaves <= 0) return true;
+  const dim3 grid((nleaves + 3) / 4), block(256);
+  switch (R) {
+    case 2: hipLaunchKernelGGL(k_p2m_multi<2>, grid, block, 0, s, pts, qs, start, leaves, centers, surf, n, alpha, q, ldq, qrs, nleaves); return true;
+    case 4: hipLaunchKernelGGL(k_p2m_multi<4>, grid, block, 0, s, pts, qs, start, leaves, centers, surf, n, alpha, q, ldq, qrs, nleaves); return true;
+    case 8: hipLaunchKernelGGL(k_p2m_multi<8>, grid, block, 0, s, pts, qs, start, leaves, centers, surf, n, alpha, q, ldq, qrs, nleaves); return true;
+    case 16: hipLaunchKernelGGL(k_p2m_multi<16>, grid, block, 0, s, pts, qs, start, leaves, centers, surf, n, alpha, q, ldq, qrs, nleaves); return true;
+    case 32: hipLaunchKernelGGL(k_p2m_multi<32>, grid, block, 0, s, pts, qs, start, leaves, centers, surf, n, alpha, q, ldq, qrs, nleaves); return true;
+    default: return false;
+  }
+}
+
+// D2T + ULI for R right-hand sides, potentials, written to input order
+// (pot[i][r]).  A task is up to 64 consecutive points of one leaf, one wave
+// each; lanes are targets.  The leaf's 27 neighbours come from the 4 x 4 x 4
+// leaf block of its parent group (as in k_p2p); the far field treats the n
+// downward-equivalent points (centre-relative) as sources with densities
+// d[r][slot][m], 4 consecutive m per load.  FP32 partial sums per source leaf
+// and per 8 surface points are accumulated in FP64.
+template <int R>
+__global__ __launch_bounds__(256) void k_leaf_multi(const float4* __restrict__ pts, const float* __restrict__ qs,
+                                                    const int* __restrict__ start, const int4* __restrict__ tasks,
+                                                    int ntasks, const int* __restrict__ blk, int group_slots,
+                                                    const float4* __restrict__ centers,
+                                                    const float* __restrict__ surf, int n, float alpha,
+                                                    const float* __restrict__ d, int ldd, long long drs, int far,
+                                                    const int* __restrict__ order, float* __restrict__ pot) {
+  const int t = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (t >= ntasks) return;
+  const int lane = threadIdx.x & 63;
+  const int4 task = tasks[t];
+  const int slot = task.x, cnt = task.z;
+  const int ti = start[slot] + task.y + min(lane, cnt - 1);
+  const float4 x = pts[ti];
+  const int g = slot / group_slots, o = slot - g * group_slots;
+  const int bx = 1 + (o & 1), by = 1 + ((o >> 1) & 1), bz = 1 + ((o >> 2) & 1);
+  double acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int ns = blk[(size_t)g * 64 + (bx + dx) + 4 * (by + dy) + 16 * (bz + dz)];
+        if (ns < 0) continue;
+        const int a = start[ns], b = start[ns + 1];
+        const bool self = ns == slot;
+        float part[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) part[r] = 0.f;
+        for (int j = a; j < b; ++j) {
+          const float4 y = pts[j];
+          const float ex = x.x - y.x, ey = x.y - y.y, ez = x.z - y.z;
+          const float r2 = ex * ex + ey * ey + ez * ez;
+          float rinv = __builtin_amdgcn_rsqf(r2);
+          if (self) rinv = r2 > 0.f ? rinv : 0.f;  // the target itself
+          const float* qj = qs + (size_t)j * R;
+#pragma unroll
+          for (int r = 0; r < R; ++r) part[r] += qj[r] * rinv;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] += part[r];
+      }
+  if (far) {
+    const float4 ch = centers[2 * slot], cl = centers[2 * slot + 1];
+    const float xx = (x.x - ch.x) - cl.x, xy = (x.y - ch.y) - cl.y, xz = (x.z - ch.z) - cl.z;
+    const float sc = alpha * ch.w;
+    const float* dl = d + (size_t)slot * ldd;
+    for (int m0 = 0; m0 < n; m0 += 8) {
+      float part[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) part[r] = 0.f;
+#pragma unroll
+      for (int h = 0; h < 8; h += 4) {
+        // d rows are zero beyond n (padded to a multiple of 4); surface indices are clamped
+        if (m0 + h >= n) break;
+        float rinv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int mc = min(m0 + h + e, n - 1);
+          const float fx = xx - sc * surf[3 * mc], fy = xy - sc * surf[3 * mc + 1], fz = xz - sc * surf[3 * mc + 2];
+          rinv[e] = __builtin_amdgcn_rsqf(fx * fx + fy * fy + fz * fz);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float4 dv = *reinterpret_cast<const float4*>(dl + r * drs + m0 + h);
+          part[r] += dv.x * rinv[0];
+          part[r] += dv.y * rinv[1];
+          part[r] += dv.z * rinv[2];
+          part[r] += dv.w * rinv[3];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += part[r];
+    }
+  }
+  if (lane < cnt) {
+    float* out = pot + (size_t)order[ti] * R;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[r] = (float)acc[r];
+  }
+}
+
+bool launch_leaf_multi(int R, const float4* pts, const float* qs, const int* start, const int4* tasks, int ntasks,
+                       const int* blk, int group_slots, const float4* centers, const float* surf, int n, float alpha,
+                       const float* d, int ldd, long long drs, int far, const int* order, float* pot, hipStream_t s) {
+  if (ntasks <= 0) return true;
+  const dim3 grid((ntasks + 3) / 4), block(256);
+#define KIFMM_LEAF_MULTI(RR)                                                                                        \
+  hipLaunchKernelGGL(k_leaf_multi<RR>, grid, block, 0, s, pts, qs, start, tasks, ntasks, blk, group_slots, centers, \
+                     surf, n, alpha, d, ldd, drs, far, order, pot)
+  switch (R) {
+    case 2: KIFMM_LEAF_MULTI(2); return true;
+    case 4: KIFMM_LEAF_MULTI(4); return true;
+    case 8: KIFMM_LEAF_MULTI(8); return true;
+    case 16: KIFMM_LEAF_MULTI(16); return true;
+    case 32: KIFMM_LEAF_MULTI(32); return true;
+    default: return false;
+  }
+#undef KIFMM_LEAF_MULTI
 }
 
 }  // namespace kifmm

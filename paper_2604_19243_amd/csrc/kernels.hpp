@@ -16,12 +16,16 @@ struct M2LItem {
   int src_base;  // 216 source slots (or -1): position o' children of the 6x6x6 parents around the block
 };
 
+// batch > 1: the same product for `batch` right-hand sides, X and Y advanced by
+// xbs and ybs floats per right-hand side.
 void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int* xrow, float* Y, int ldy,
-                    const int* yrow, int nbox, int nout, int K, float alpha, int beta, hipStream_t s);
+                    const int* yrow, int nbox, int nout, int K, float alpha, int beta, hipStream_t s, int batch = 1,
+                    long long xbs = 0, long long ybs = 0);
 // Returns false if no kernel instance fits (rb, ldk).
+// nrhs right-hand sides: uhat and each partial sum advance by rhs_stride floats per right-hand side.
 bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int lds_ld, const M2LItem* items, int nitems,
                 const int* tgt_blk, const int* src_blk, const int* pair_offs, const float* uhat, float* chat_part,
-                long long part_stride, hipStream_t s);
+                long long part_stride, int nrhs, long long rhs_stride, hipStream_t s);
 // The same translation from split-bfloat16 pieces (2 pieces: three matrix-core
 // passes; 3 pieces: six): cores are [316][row block][16-k chunk][piece][64
 // lanes][8] bfloat16 bit patterns; core_stride16 is the size of one offset's
@@ -29,7 +33,8 @@ bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int 
 int m2l_bf16_lds_ld16(int pieces);
 bool launch_m2l_bf16(int pieces, int row_blocks, const uint16_t* cores, size_t core_stride16, int ldk, int lds_ld16,
                      const M2LItem* items, int nitems, const int* tgt_blk, const int* src_blk, const int* pair_offs,
-                     const float* uhat, float* chat_part, long long part_stride, hipStream_t s);
+                     const float* uhat, float* chat_part, long long part_stride, int nrhs, long long rhs_stride,
+                     hipStream_t s);
 void launch_sum_parts(const float* part, float* chat, long long n, long long stride, hipStream_t s);
 // out[k][c] = w[k] fs[k][c] + s[k] fw[k][c] for k < n, c < 3.
 void launch_vjp_combine(const float* s, const float* w, const float* fs, const float* fw, float* out, int n,
@@ -47,5 +52,19 @@ size_t p2p_lds_bytes(int cap, int n);
 bool launch_p2p(int mode, const float4* pts, const int* start, const int* blk, int ngroups, int group_slots, int cap,
                 const float4* centers, const float* surf, int n, float alpha, const float* d, int ldd, int far,
                 const int* order, float* pot, float* grad, float4* near, hipStream_t s);
+
+
+// Multi-RHS leaf kernels (R = 2, 4, 8, 16, 32; potentials only).  qs: sorted
+// charges [N][R].  q: check fields [R][leaf slots][ldq], qrs = leaf slots * ldq.
+// tasks: (leaf slot, first point offset in the leaf, point count <= 64, 0).
+// d: leaf-level downward densities, slot row `slot` at d + slot * ldd, right-hand
+// side r at + r * drs.  Return false for an unsupported R.
+void launch_permute_multi(float* qs, const float* charges, const int* order, int n, int R, hipStream_t s);
+bool launch_p2m_multi(int R, const float4* pts, const float* qs, const int* start, const int* leaves,
+                      const float4* centers, const float* surf, int n, float alpha, float* q, int ldq, long long qrs,
+                      int nleaves, hipStream_t s);
+bool launch_leaf_multi(int R, const float4* pts, const float* qs, const int* start, const int4* tasks, int ntasks,
+                       const int* blk, int group_slots, const float4* centers, const float* surf, int n, float alpha,
+                       const float* d, int ldd, long long drs, int far, const int* order, float* pot, hipStream_t s);
 
 }  // namespace kifmm

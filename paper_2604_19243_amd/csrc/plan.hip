@@ -78,13 +78,17 @@ Plan::~Plan() {
   release(ops);
 }
 
-Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
+Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
   require(tree && ops, "null tree or ops");
   require((flags & ~(KIFMM_POTENTIAL | KIFMM_GRADIENT | KIFMM_SERIAL | KIFMM_M2L_BF16X3 | KIFMM_M2L_BF16X6 |
                      KIFMM_VJP)) == 0 &&
               (flags & (KIFMM_POTENTIAL | KIFMM_GRADIENT)) != 0,
           "flags must hold POTENTIAL and/or GRADIENT, optionally SERIAL, VJP and one of M2L_BF16X3, M2L_BF16X6");
   require(!((flags & KIFMM_M2L_BF16X3) && (flags & KIFMM_M2L_BF16X6)), "M2L_BF16X3 and M2L_BF16X6 exclude each other");
+  require(nrhs == 1 || nrhs == 2 || nrhs == 4 || nrhs == 8 || nrhs == 16 || nrhs == 32,
+          "nrhs must be 1, 2, 4, 8, 16 or 32");
+  require(nrhs == 1 || !(flags & (KIFMM_GRADIENT | KIFMM_VJP)),
+          "gradients and KIFMM_VJP need nrhs = 1 (plans with more right-hand sides give potentials)");
   int ndev = 0;
   hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
   require(device >= 0 && device < ndev, "device index out of range");
@@ -103,6 +107,7 @@ Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
     const Ops& O = *ops;
     const int L = T.depth;
     P->flags = flags;
+    P->nrhs = nrhs;
     P->L = L;
     P->N = T.n;
     P->far = L >= 2;
@@ -250,14 +255,16 @@ Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
         total += P->slots[l];
       }
       P->total_slots = total;
-      P->d_q = dev_upload<float>(own, nullptr, (size_t)SL * nst, "check field");
-      P->d_t = dev_upload<float>(own, nullptr, (size_t)SL * kcst, "check coefficients");
-      P->d_u = dev_upload<float>(own, nullptr, (size_t)total * nst, "u");
-      P->d_d = dev_upload<float>(own, nullptr, (size_t)total * nst, "d");
-      P->d_uhat = dev_upload<float>(own, nullptr, (size_t)total * kst, "uhat");
-      P->d_chat = dev_upload<float>(own, nullptr, (size_t)total * kst, "chat");
-      // M2L partial sums, one per source position among siblings: [8][total][kst].
-      P->d_chat_part = dev_upload<float>(own, nullptr, (size_t)8 * total * kst, "chat parts");
+      // Per-box arrays hold the nrhs right-hand sides one after the other: [nrhs][slots][row].
+      const size_t R = (size_t)nrhs;
+      P->d_q = dev_upload<float>(own, nullptr, R * SL * nst, "check field");
+      P->d_t = dev_upload<float>(own, nullptr, R * SL * kcst, "check coefficients");
+      P->d_u = dev_upload<float>(own, nullptr, R * total * nst, "u");
+      P->d_d = dev_upload<float>(own, nullptr, R * total * nst, "d");
+      P->d_uhat = dev_upload<float>(own, nullptr, R * total * kst, "uhat");
+      P->d_chat = dev_upload<float>(own, nullptr, R * total * kst, "chat");
+      // M2L partial sums, one per source position among siblings: [8][nrhs][total][kst].
+      P->d_chat_part = dev_upload<float>(own, nullptr, 8 * R * total * kst, "chat parts");
       P->d_zero = dev_upload<float>(own, nullptr, (size_t)kst + nst, "zero row");
 
       auto pad_rows = [](int rows) { return round_up(rows, 64); };
@@ -464,7 +471,24 @@ Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device) {
       for (int l = 0; l <= L; ++l) P->keys_per_level[l] = (int64_t)T.keys[l].size();
       P->slot_of = slot_of;
     }
-    if (P->far && !(flags & KIFMM_SERIAL)) {
+    if (nrhs > 1) {
+      // Multi-RHS leaf tasks: up to 64 consecutive points of one non-empty leaf each.
+      P->d_qs = dev_upload<float>(own, nullptr, (size_t)nrhs * T.n, "sorted charges");
+      std::vector<int> tk;
+      for (int64_t i = 0; i < NBL; ++i) {
+        const int s = leaves[i];
+        const int c = start[s + 1] - start[s];
+        for (int t0 = 0; t0 < c; t0 += 64) {
+          tk.push_back(s);
+          tk.push_back(t0);
+          tk.push_back(std::min(64, c - t0));
+          tk.push_back(0);
+        }
+      }
+      P->n_tasks = (int)(tk.size() / 4);
+      if (P->n_tasks) P->d_tasks = reinterpret_cast<int4*>(dev_upload(own, tk.data(), tk.size(), "leaf tasks"));
+    }
+    if (P->far && !(flags & KIFMM_SERIAL) && nrhs == 1) {
       hip_check(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking), "hipStreamCreate");
       hip_check(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming), "hipEventCreate");
       hip_check(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming), "hipEventCreate");
@@ -535,8 +559,13 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
 
   const int N = (int)P->N;
   const int L = P->L;
+  const int R = P->nrhs;
+  require(R == 1 || pot != nullptr, "plans with nrhs > 1 give potentials: potential must be given");
   P->stage_begin(KIFMM_STAGE_PERMUTE, st);
-  launch_permute(P->d_pts, charges, P->d_order, N, st);
+  if (R == 1)
+    launch_permute(P->d_pts, charges, P->d_order, N, st);
+  else
+    launch_permute_multi(P->d_qs, charges, P->d_order, N, R, st);
   P->stage_end(KIFMM_STAGE_PERMUTE, st);
   const bool split = P->side != nullptr;
   const float* d_leaf = P->far ? P->d_d + P->base[L] * P->nst : nullptr;
@@ -558,52 +587,60 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
     const int n = P->n, nst = P->nst, kst = P->kst, kcst = P->kcst;
     const int SL = (int)P->slots[L];
     const int nleaves = (int)P->n_leaves;
+    const long long TS = P->total_slots;
     float* uL = P->d_u + P->base[L] * nst;
     // (1a) S2U: check field, then the two pseudo-inverse factors (scaled by r_L).
+    // With nrhs > 1 every per-box array holds the right-hand sides one after
+    // the other, and each product runs as one batch over them.
     P->stage_begin(KIFMM_STAGE_P2M, st);
-    launch_p2m(P->d_pts, P->d_start, P->d_leaves, P->d_centers, P->d_surf, n, (float)kAlphaOuter, P->d_q, nst,
-               nleaves, st);
+    if (R == 1)
+      launch_p2m(P->d_pts, P->d_start, P->d_leaves, P->d_centers, P->d_surf, n, (float)kAlphaOuter, P->d_q, nst,
+                 nleaves, st);
+    else if (!launch_p2m_multi(R, P->d_pts, P->d_qs, P->d_start, P->d_leaves, P->d_centers, P->d_surf, n,
+                               (float)kAlphaOuter, P->d_q, nst, (long long)SL * nst, nleaves, st))
+      fail(KIFMM_E_DEVICE, "multi-RHS leaf kernel configuration not available");
     P->stage_end(KIFMM_STAGE_P2M, st);
     P->stage_begin(KIFMM_STAGE_UC2E, st);
-    launch_gemm_nt(P->d_f1, nst, P->d_q, nst, P->d_leaves, P->d_t, kcst, P->d_leaves, nleaves, kcst, nst, 1.0f, 0, st);
+    launch_gemm_nt(P->d_f1, nst, P->d_q, nst, P->d_leaves, P->d_t, kcst, P->d_leaves, nleaves, kcst, nst, 1.0f, 0, st,
+                   R, (long long)SL * nst, (long long)SL * kcst);
     launch_gemm_nt(P->d_f2, kcst, P->d_t, kcst, P->d_leaves, uL, nst, P->d_leaves, nleaves, nst, kcst,
-                   (float)P->tree->radius(L), 0, st);
+                   (float)P->tree->radius(L), 0, st, R, (long long)SL * kcst, TS * nst);
     P->stage_end(KIFMM_STAGE_UC2E, st);
-    (void)SL;
     // (1b) U2U, child level l -> parent level l - 1, down to level 2.
     P->stage_begin(KIFMM_STAGE_M2M, st);
     for (int l = L; l >= 3; --l) {
       const int parents = (int)P->keys_per_level[l - 1];
       launch_gemm_nt(P->d_m2m, 8 * nst, P->d_u + P->base[l] * nst, 8 * nst, nullptr, P->d_u + P->base[l - 1] * nst,
-                     nst, P->d_nbslot[l - 1], parents, nst, 8 * nst, 1.0f, 0, st);
+                     nst, P->d_nbslot[l - 1], parents, nst, 8 * nst, 1.0f, 0, st, R, TS * nst, TS * nst);
     }
     P->stage_end(KIFMM_STAGE_M2M, st);
     // (2a) VLI: compress, translate with the shared cores, all levels at once.
     P->stage_begin(KIFMM_STAGE_COMPRESS, st);
     launch_gemm_nt(P->d_vt, nst, P->d_u, nst, nullptr, P->d_uhat, kst, nullptr, (int)P->total_slots, kst, nst, 1.0f,
-                   0, st);
+                   0, st, R, TS * nst, TS * kst);
     P->stage_end(KIFMM_STAGE_COMPRESS, st);
     P->stage_begin(KIFMM_STAGE_M2L, st);
     const bool m2l_ok =
         P->m2l_pieces
             ? launch_m2l_bf16(P->m2l_pieces, P->m2l_rb, P->d_cores_b, P->core_stride16, kst,
                               m2l_bf16_lds_ld16(P->m2l_pieces), P->d_items, P->n_items, P->d_tgt_blk, P->d_src_blk,
-                              P->d_pair_offs, P->d_uhat, P->d_chat_part, (long long)P->total_slots * kst, st)
+                              P->d_pair_offs, P->d_uhat, P->d_chat_part, R * TS * kst, R, TS * kst, st)
             : launch_m2l(P->m2l_rb, P->d_cores, P->core_rows, kst, P->m2l_lds_ld, P->d_items, P->n_items,
-                         P->d_tgt_blk, P->d_src_blk, P->d_pair_offs, P->d_uhat, P->d_chat_part,
-                         (long long)P->total_slots * kst, st);
+                         P->d_tgt_blk, P->d_src_blk, P->d_pair_offs, P->d_uhat, P->d_chat_part, R * TS * kst, R,
+                         TS * kst, st);
     if (!m2l_ok) fail(KIFMM_E_DEVICE, "M2L kernel configuration not available");
     P->stage_end(KIFMM_STAGE_M2L, st);
     // (2c) sum of the M2L partial sums, post (DC2E U_k) and D2D, coarse to fine.
     P->stage_begin(KIFMM_STAGE_L2L, st);
-    launch_sum_parts(P->d_chat_part, P->d_chat, (long long)P->total_slots * kst, (long long)P->total_slots * kst, st);
+    launch_sum_parts(P->d_chat_part, P->d_chat, R * TS * kst, R * TS * kst, st);
     for (int l = 2; l <= L; ++l) {
       launch_gemm_nt(P->d_post, kst, P->d_chat + P->base[l] * kst, kst, nullptr, P->d_d + P->base[l] * nst, nst,
-                     nullptr, (int)P->slots[l], nst, kst, 1.0f, 0, st);
+                     nullptr, (int)P->slots[l], nst, kst, 1.0f, 0, st, R, TS * kst, TS * nst);
       if (l > 2) {
         const int parents = (int)P->keys_per_level[l - 1];
         launch_gemm_nt(P->d_l2l, nst, P->d_d + P->base[l - 1] * nst, nst, P->d_nbslot[l - 1],
-                       P->d_d + P->base[l] * nst, 8 * nst, nullptr, parents, 8 * nst, nst, 1.0f, 1, st);
+                       P->d_d + P->base[l] * nst, 8 * nst, nullptr, parents, 8 * nst, nst, 1.0f, 1, st, R, TS * nst,
+                       TS * nst);
       }
     }
     P->stage_end(KIFMM_STAGE_L2L, st);
@@ -616,6 +653,14 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
                     P->d_surf, P->n, (float)kAlphaOuter, d_leaf, P->nst, 1, P->d_order, pot, grad, P->d_near, st))
       fail(KIFMM_E_DEVICE, "leaf kernel configuration not available");
     P->stage_end(KIFMM_STAGE_L2P, st);
+  } else if (R > 1) {
+    // (3b) D2T + (3c) ULI for all right-hand sides, potentials in input order.
+    P->stage_begin(KIFMM_STAGE_P2P, st);
+    if (!launch_leaf_multi(R, P->d_pts, P->d_qs, P->d_start, P->d_tasks, P->n_tasks, P->d_blk, P->group_slots,
+                           P->d_centers, P->d_surf, P->n, (float)kAlphaOuter, d_leaf, P->nst,
+                           P->far ? (long long)P->total_slots * P->nst : 0, P->far ? 1 : 0, P->d_order, pot, st))
+      fail(KIFMM_E_DEVICE, "multi-RHS leaf kernel configuration not available");
+    P->stage_end(KIFMM_STAGE_P2P, st);
   } else {
     // (3b) D2T + (3c) ULI fused, written in input order.
     P->stage_begin(KIFMM_STAGE_P2P, st);

@@ -14,6 +14,7 @@ struct Plan : Object {
   Tree* tree = nullptr;
   Ops* ops = nullptr;
   unsigned flags = 0;
+  int nrhs = 1;                          // right-hand sides per evaluate
   int device = 0;
   int L = 0;
   int64_t N = 0;
@@ -56,6 +57,9 @@ struct Plan : Object {
   hipStream_t side = nullptr;            // ULI stream (default priority)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   float4* d_near = nullptr;              // ULI result in sorted order (phi, grad)
+  float* d_qs = nullptr;                 // nrhs > 1: sorted charges [N][nrhs]
+  int4* d_tasks = nullptr;               // nrhs > 1: leaf tasks (slot, first point, count <= 64, 0)
+  int n_tasks = 0;
   float* d_vjp_fs = nullptr;             // KIFMM_VJP: grad f of the charges, [n][3], input order
   float* d_vjp_fw = nullptr;             // KIFMM_VJP: grad f of the weights, [n][3], input order
 
@@ -73,7 +77,7 @@ struct Plan : Object {
   void collect_times();
 };
 
-Plan* create_plan(Tree* tree, Ops* ops, unsigned flags, int device);
+Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device);
 void evaluate_plan(Plan* plan, const float* charges, float* pot, float* grad, hipStream_t st);
 void evaluate_vjp(Plan* plan, const float* charges, const float* weights, const float* field, float* grad_charges,
                   float* grad_points, hipStream_t st);

@@ -81,7 +81,7 @@ def library():
         "kifmm_ops_get_info": (ctypes.c_int, [_VP, ctypes.POINTER(OpsInfo)]),
         "kifmm_ops_get_matrix": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int64]),
         "kifmm_ops_destroy": (ctypes.c_int, [_VP]),
-        "kifmm_plan_create": (ctypes.c_int, [_VP, _VP, ctypes.c_uint, ctypes.c_int, ctypes.POINTER(_VP)]),
+        "kifmm_plan_create": (ctypes.c_int, [_VP, _VP, ctypes.c_int, ctypes.c_uint, ctypes.c_int, ctypes.POINTER(_VP)]),
         "kifmm_evaluate": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
         "kifmm_evaluate_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
         "kifmm_plan_destroy": (ctypes.c_int, [_VP]),
@@ -184,9 +184,9 @@ def kifmm_ops_destroy(ops):
     _check(library().kifmm_ops_destroy(ops))
 
 
-def kifmm_plan_create(tree, ops, flags=KIFMM_POTENTIAL | KIFMM_GRADIENT, device=0):
+def kifmm_plan_create(tree, ops, nrhs=1, flags=KIFMM_POTENTIAL | KIFMM_GRADIENT, device=0):
     out = ctypes.c_void_p()
-    _check(library().kifmm_plan_create(tree, ops, int(flags), int(device), ctypes.byref(out)))
+    _check(library().kifmm_plan_create(tree, ops, int(nrhs), int(flags), int(device), ctypes.byref(out)))
     return out
 
 
@@ -219,9 +219,9 @@ def kifmm_plan_get_stage_times(plan, reset=True):
 
 
 def kifmm_plan_get_stats(plan):
-    out = np.zeros(6, dtype=np.int64)
-    _check(library().kifmm_plan_get_stats(plan, _host_ptr(out), 6))
-    keys = ["p2p_pairs", "m2l_pairs", "leaf_slots", "m2l_targets", "k", "n"]
+    out = np.zeros(7, dtype=np.int64)
+    _check(library().kifmm_plan_get_stats(plan, _host_ptr(out), 7))
+    keys = ["p2p_pairs", "m2l_pairs", "leaf_slots", "m2l_targets", "k", "n", "nrhs"]
     return dict(zip(keys, (int(v) for v in out)))
 
 
@@ -237,11 +237,11 @@ class FMM:
     """Tree + operators + plan for one point set on one device (owns the three handles)."""
 
     def __init__(self, points, depth, p, cube=None, eps_pinv=1e-7, eps_svd=1e-6, rank=0,
-                 flags=KIFMM_POTENTIAL | KIFMM_GRADIENT, device=0):
+                 flags=KIFMM_POTENTIAL | KIFMM_GRADIENT, device=0, nrhs=1):
         self.n = int(np.asarray(points).shape[0])
         self.tree = kifmm_tree_build(points, depth, cube)
         self.ops = kifmm_ops_precompute(p, eps_pinv, eps_svd, rank)
-        self.plan = kifmm_plan_create(self.tree, self.ops, flags, device)
+        self.plan = kifmm_plan_create(self.tree, self.ops, nrhs, flags, device)
 
     def evaluate(self, charges, potential=None, gradient=None, stream=None):
         kifmm_evaluate(self.plan, charges, potential, gradient, stream)

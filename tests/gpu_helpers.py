@@ -19,15 +19,17 @@ M2L_FLAGS = {"fp32": 0, "bf16x3": kifmm.KIFMM_M2L_BF16X3, "bf16x6": kifmm.KIFMM_
 
 def gpu_evaluate(points, charges, depth, p, cube, eps_svd=1e-6, rank=0, gradient=True, fmm_obj=None, serial=False,
                  m2l="fp32"):
-    """HIP path: returns (phi [n], grad [n,3] or None, FMM object) as float64 numpy arrays."""
+    """HIP path: returns (phi [n] or [n,R], grad [n,3] or None, FMM object) as float64 numpy arrays.
+    charges [n] or [n, R] (R right-hand sides: potentials only)."""
     import torch
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    nrhs = 1 if np.ndim(charges) == 1 else np.shape(charges)[1]
     flags = kifmm.KIFMM_POTENTIAL | (kifmm.KIFMM_GRADIENT if gradient else 0)
     flags |= (kifmm.KIFMM_SERIAL if serial else 0) | M2L_FLAGS[m2l]
-    f = fmm_obj or kifmm.FMM(points, depth, p, cube=cube, eps_svd=eps_svd, rank=rank, flags=flags)
+    f = fmm_obj or kifmm.FMM(points, depth, p, cube=cube, eps_svd=eps_svd, rank=rank, flags=flags, nrhs=nrhs)
     dev = torch.device("cuda:0")
     s = torch.from_numpy(np.ascontiguousarray(charges, dtype=np.float32)).to(dev)
-    pot = torch.full((len(points),), float("nan"), device=dev)
+    pot = torch.full(np.shape(charges), float("nan"), device=dev)
     grad = torch.full((len(points), 3), float("nan"), device=dev) if gradient else None
     f.evaluate(s, pot, grad, stream=torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()

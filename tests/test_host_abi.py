@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol(lib):
     assert len(names) >= 18
     for name in sorted(names):
         assert hasattr(lib, name), name
-    assert kifmm.kifmm_abi_version() == 1
+    assert kifmm.kifmm_abi_version() == 2
 
 
 @pytest.mark.parametrize("dist,depth,n", [("cube", 3, 20_000), ("cube", 5, 50_000), ("sphere", 4, 30_000),
@@ -166,8 +166,10 @@ def test_error_paths(lib):
         buf = np.zeros(4)
         assert lib.kifmm_ops_get_matrix(o, kifmm.KIFMM_OP_SURFACE, 0, buf.ctypes.data, 4) == kifmm.KIFMM_E_INVALID
         assert b"capacity" in lib.kifmm_last_error()
-        assert lib.kifmm_plan_create(t, o, 0, 0, ctypes.byref(out)) == kifmm.KIFMM_E_INVALID
-        assert lib.kifmm_plan_create(t, o, 1, -1, ctypes.byref(out)) in (kifmm.KIFMM_E_INVALID, kifmm.KIFMM_E_DEVICE)
+        assert lib.kifmm_plan_create(t, o, 1, 0, 0, ctypes.byref(out)) == kifmm.KIFMM_E_INVALID
+        assert lib.kifmm_plan_create(t, o, 1, 1, -1, ctypes.byref(out)) in (kifmm.KIFMM_E_INVALID, kifmm.KIFMM_E_DEVICE)
+        assert lib.kifmm_plan_create(t, o, 3, 1, 0, ctypes.byref(out)) == kifmm.KIFMM_E_INVALID
+        assert lib.kifmm_plan_create(t, o, 4, 3, 0, ctypes.byref(out)) == kifmm.KIFMM_E_INVALID
     finally:
         kifmm.kifmm_ops_destroy(o)
         kifmm.kifmm_tree_destroy(t)
