@@ -39,9 +39,9 @@ __device__ __forceinline__ v4f mfma16x4(const float4 a, const float4 b, v4f c) {
 __global__ __launch_bounds__(256) void k_gemm_nt(const float* __restrict__ W, int ldw, const float* __restrict__ X,
                                                  int ldx, const int* __restrict__ xrow, float* __restrict__ Y, int ldy,
                                                  const int* __restrict__ yrow, int nbox, int nout, int K, float alpha,
-                                                 int beta, long long xbs, long long ybs) {
+                                                 int beta, long long xbs, long long ybs, int ywide) {
   X += blockIdx.z * xbs;  // batch (right-hand side) blockIdx.z
-  Y += blockIdx.z * ybs;
+  if (!ywide) Y += blockIdx.z * ybs;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int i16 = lane & 15, q = lane >> 4;
@@ -91,7 +91,9 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const float* __restrict__ W, in
     for (int m = 0; m < 2; ++m) {
       const int o = o0 + 16 * m + 4 * q;
       if (o >= nout) continue;
-      float4* yp = reinterpret_cast<float4*>(Y + (size_t)r * ldy + o);
+      // ywide: the 32-right-hand-side lane order of k_m2l_wide, [row][o / 8][32][8]
+      float4* yp = reinterpret_cast<float4*>(
+          ywide ? Y + (((size_t)r * (nout >> 3) + (o >> 3)) * 32 + blockIdx.z) * 8 + (o & 7) : Y + (size_t)r * ldy + o);
       float4 v = make_float4(alpha * acc[m][nb][0], alpha * acc[m][nb][1], alpha * acc[m][nb][2], alpha * acc[m][nb][3]);
       if (beta) {
         const float4 old = *yp;
@@ -107,11 +109,11 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const float* __restrict__ W, in
 
 void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int* xrow, float* Y, int ldy,
                     const int* yrow, int nbox, int nout, int K, float alpha, int beta, hipStream_t s, int batch,
-                    long long xbs, long long ybs) {
+                    long long xbs, long long ybs, int ywide) {
   if (nbox <= 0 || batch <= 0) return;
   dim3 grid((nbox + 63) / 64, (nout + 63) / 64, batch);
   hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, s, W, ldw, X, ldx, xrow, Y, ldy, yrow, nbox, nout, K, alpha, beta,
-                     xbs, ybs);
+                     xbs, ybs, ywide);
 }
 
 // ----------------------------------------------------------------- M2L ---
@@ -319,6 +321,73 @@ bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int 
   hipLaunchKernelGGL(k_m2l, dim3(nitems, nrhs), dim3(64 * row_blocks), lds, s, cores, core_rows, ldk, lds_ld / 4,
                      items, tgt_blk, src_blk, pair_offs, uhat, chat_part, part_stride, rhs_stride);
   return true;
+}
+
+// -------------------------------------------------- M2L, 32 right-hand sides ---
+// The compressed VLI for 32 right-hand sides as wide products: per target box
+// and V-list entry (offset t, source box), chat[:, target] += C_t uhat[:, source]
+// with the 32 right-hand sides as the 32 columns of v_mfma_f32_32x32x2_f32.
+// One wave per (target box, 32-row block of C) walks the target's V list.
+// Operators are in the lane order of k_m2l; uhat is [box][k / 8][32][8], so
+// that lane (j, h) reads B[8c + 4h .. +3][right-hand side j] as one float4 and
+// a wave's read of one chunk is 1 KiB of contiguous memory.  No partial sums:
+// the wave writes chat[r][target][rows] once.  The accumulators restart every
+// kM2LFlush entries and are added into a running total (short FP32 chains).
+__global__ __launch_bounds__(64) void k_m2l_wide(const float* __restrict__ cores, long long core_stride, int nch,
+                                                 const int4* __restrict__ units, const int2* __restrict__ vlist,
+                                                 const float* __restrict__ uhat, float* __restrict__ chat,
+                                                 long long chat_rs, int ldk) {
+  const int4 u = units[blockIdx.x];  // (target slot, row block, first entry, end entry)
+  const int lane = threadIdx.x;
+  const int j = lane & 31, h = lane >> 5;
+  const float* alane = cores + (size_t)u.y * nch * 256 + 4 * lane;
+  const float* blane = uhat + 8 * j + 4 * h;
+  const size_t box_stride = (size_t)nch * 256;
+  v16f acc, tot;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = tot[e] = 0.f;
+  for (int e0 = u.z; e0 < u.w; e0 += kM2LFlush) {
+    const int e1 = min(e0 + kM2LFlush, u.w);
+    for (int e = e0; e < e1; ++e) {
+      const int2 pr = vlist[e];
+      const float* ap = alane + (size_t)pr.x * core_stride;
+      const float* bp = blane + (size_t)pr.y * box_stride;
+      float4 a = *reinterpret_cast<const float4*>(ap);
+      float4 b = *reinterpret_cast<const float4*>(bp);
+      for (int c = 0; c < nch; ++c) {
+        const int cn = min(c + 1, nch - 1);  // next chunk (the last one repeats, unused)
+        const float4 an = *reinterpret_cast<const float4*>(ap + 256 * cn);
+        const float4 bn = *reinterpret_cast<const float4*>(bp + 256 * cn);
+        acc = mfma32(a.x, b.x, acc);
+        acc = mfma32(a.y, b.y, acc);
+        acc = mfma32(a.z, b.z, acc);
+        acc = mfma32(a.w, b.w, acc);
+        a = an;
+        b = bn;
+      }
+    }
+    // a group of kM2LFlush entries: into the running total, restart
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      tot[e] += acc[e];
+      acc[e] = 0.f;
+    }
+  }
+  // tot[v]: row 32 u.y + 8 (v / 4) + 4 h + v % 4 of right-hand side j
+  float* out = chat + j * chat_rs + (size_t)u.x * ldk;
+#pragma unroll
+  for (int b4 = 0; b4 < 4; ++b4) {
+    const int row = 32 * u.y + 8 * b4 + 4 * h;
+    if (row < ldk)
+      *reinterpret_cast<float4*>(out + row) = make_float4(tot[4 * b4], tot[4 * b4 + 1], tot[4 * b4 + 2], tot[4 * b4 + 3]);
+  }
+}
+
+void launch_m2l_wide(const float* cores, long long core_stride, int ldk, const int4* units, int nunits,
+                     const int2* vlist, const float* uhat, float* chat, long long chat_rs, hipStream_t s) {
+  if (nunits <= 0) return;
+  hipLaunchKernelGGL(k_m2l_wide, dim3(nunits), dim3(64), 0, s, cores, core_stride, ldk / 8, units, vlist, uhat, chat,
+                     chat_rs, ldk);
 }
 
 // ------------------------------------------------- M2L, split bfloat16 ---

@@ -18,9 +18,11 @@ struct M2LItem {
 
 // batch > 1: the same product for `batch` right-hand sides, X and Y advanced by
 // xbs and ybs floats per right-hand side.
+// ywide: write Y in the 32-right-hand-side lane order of k_m2l_wide ([row][nout / 8][32][8],
+// batch index = right-hand side; ybs unused), nout a multiple of 8 and batch = 32.
 void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int* xrow, float* Y, int ldy,
                     const int* yrow, int nbox, int nout, int K, float alpha, int beta, hipStream_t s, int batch = 1,
-                    long long xbs = 0, long long ybs = 0);
+                    long long xbs = 0, long long ybs = 0, int ywide = 0);
 // Returns false if no kernel instance fits (rb, ldk).
 // nrhs right-hand sides: uhat and each partial sum advance by rhs_stride floats per right-hand side.
 bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int lds_ld, const M2LItem* items, int nitems,
@@ -35,6 +37,11 @@ bool launch_m2l_bf16(int pieces, int row_blocks, const uint16_t* cores, size_t c
                      const M2LItem* items, int nitems, const int* tgt_blk, const int* src_blk, const int* pair_offs,
                      const float* uhat, float* chat_part, long long part_stride, int nrhs, long long rhs_stride,
                      hipStream_t s);
+// M2L for 32 right-hand sides: units (target slot, row block, first, end V-list entry);
+// vlist entries (core index, source slot); uhat in the lane order written by
+// launch_gemm_nt(ywide); chat [32][slots][ldk] (chat_rs = slots * ldk).
+void launch_m2l_wide(const float* cores, long long core_stride, int ldk, const int4* units, int nunits,
+                     const int2* vlist, const float* uhat, float* chat, long long chat_rs, hipStream_t s);
 void launch_sum_parts(const float* part, float* chat, long long n, long long stride, hipStream_t s);
 // out[k][c] = w[k] fs[k][c] + s[k] fw[k][c] for k < n, c < 3.
 void launch_vjp_combine(const float* s, const float* w, const float* fs, const float* fw, float* out, int n,

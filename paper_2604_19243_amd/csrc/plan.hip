@@ -263,8 +263,10 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
       P->d_d = dev_upload<float>(own, nullptr, R * total * nst, "d");
       P->d_uhat = dev_upload<float>(own, nullptr, R * total * kst, "uhat");
       P->d_chat = dev_upload<float>(own, nullptr, R * total * kst, "chat");
-      // M2L partial sums, one per source position among siblings: [8][nrhs][total][kst].
-      P->d_chat_part = dev_upload<float>(own, nullptr, 8 * R * total * kst, "chat parts");
+      // M2L partial sums, one per source position among siblings: [8][nrhs][total][kst]
+      // (the wide 32-right-hand-side M2L writes chat directly and needs none).
+      P->m2l_wide = nrhs == 32 && P->m2l_pieces == 0;
+      if (!P->m2l_wide) P->d_chat_part = dev_upload<float>(own, nullptr, 8 * R * total * kst, "chat parts");
       P->d_zero = dev_upload<float>(own, nullptr, (size_t)kst + nst, "zero row");
 
       auto pad_rows = [](int rows) { return round_up(rows, 64); };
@@ -470,6 +472,66 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
       P->keys_per_level.assign(L + 1, 0);
       for (int l = 0; l <= L; ++l) P->keys_per_level[l] = (int64_t)T.keys[l].size();
       P->slot_of = slot_of;
+
+      if (P->m2l_wide) {
+        // Per-target V lists (Table 1: children of the parent's colleagues, not
+        // adjacent, non-empty) as (core index, source slot), and work units
+        // (target, 32-row block) dealt to XCDs by the target's position among its
+        // siblings, row block by row block: an XCD then works through the ~189
+        // cores of one position and one row block at a time (its L2 holds them).
+        std::vector<int> idx7(343, -1);
+        for (int t = 0; t < kNumOffsets; ++t)
+          idx7[(O.offsets[3 * t] + 3) + 7 * (O.offsets[3 * t + 1] + 3) + 49 * (O.offsets[3 * t + 2] + 3)] = t;
+        std::vector<int> vl;
+        std::vector<std::vector<int>> per_xcd(8);
+        std::vector<int64_t> tgt_first, tgt_end;
+        std::vector<int> tgt_slot, tgt_pos;
+        for (int l = 2; l <= L; ++l) {
+          const int64_t mp = 1ll << (l - 1), ml = 1ll << l;
+          for (size_t i = 0; i < T.keys[l].size(); ++i) {
+            int32_t c[3];
+            morton_decode(T.keys[l][i], l, c);
+            const int64_t first = (int64_t)vl.size() / 2;
+            for (int dz = -1; dz <= 1; ++dz)
+              for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                  const int64_t qx = (c[0] >> 1) + dx, qy = (c[1] >> 1) + dy, qz = (c[2] >> 1) + dz;
+                  if (qx < 0 || qy < 0 || qz < 0 || qx >= mp || qy >= mp || qz >= mp) continue;
+                  for (int o2 = 0; o2 < 8; ++o2) {
+                    const int64_t sx = 2 * qx + (o2 & 1), sy = 2 * qy + ((o2 >> 1) & 1), sz = 2 * qz + (o2 >> 2);
+                    const int64_t tx = c[0] - sx, ty = c[1] - sy, tz = c[2] - sz;
+                    if (std::max({std::llabs(tx), std::llabs(ty), std::llabs(tz)}) < 2) continue;
+                    if (sx >= ml || sy >= ml || sz >= ml) continue;
+                    const int64_t jj = T.find(l, morton_encode((uint32_t)sx, (uint32_t)sy, (uint32_t)sz, l));
+                    if (jj < 0) continue;
+                    const int t = idx7[(tx + 3) + 7 * (ty + 3) + 49 * (tz + 3)];
+                    require(t >= 0, "internal: V-list offset not in the operator table");
+                    vl.push_back(t);
+                    vl.push_back((int)(P->base[l] + slot_of[l][jj]));
+                  }
+                }
+            tgt_first.push_back(first);
+            tgt_end.push_back((int64_t)vl.size() / 2);
+            tgt_slot.push_back((int)(P->base[l] + slot_of[l][i]));
+            tgt_pos.push_back((int)(T.keys[l][i] & 7));
+          }
+        }
+        require(vl.size() / 2 < (size_t)INT32_MAX, "V lists too long for the wide M2L");
+        std::vector<int> units;
+        std::vector<std::vector<int>> ux(8);
+        for (int x = 0; x < 8; ++x)
+          for (int rb = 0; rb < P->m2l_rb; ++rb)
+            for (size_t i = 0; i < tgt_slot.size(); ++i)
+              if (tgt_pos[i] == x) ux[x].insert(ux[x].end(), {tgt_slot[i], rb, (int)tgt_first[i], (int)tgt_end[i]});
+        size_t most = 0;
+        for (auto& v : ux) most = std::max(most, v.size() / 4);
+        for (size_t i = 0; i < most; ++i)
+          for (int x = 0; x < 8; ++x)
+            if (i < ux[x].size() / 4) units.insert(units.end(), ux[x].begin() + 4 * i, ux[x].begin() + 4 * i + 4);
+        P->n_units = (int)(units.size() / 4);
+        P->d_vlist = reinterpret_cast<int2*>(dev_upload(own, vl.data(), vl.size(), "m2l v lists"));
+        P->d_units = reinterpret_cast<int4*>(dev_upload(own, units.data(), units.size(), "m2l units"));
+      }
     }
     if (nrhs > 1) {
       // Multi-RHS leaf tasks: up to 64 consecutive points of one non-empty leaf each.
@@ -617,11 +679,14 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
     // (2a) VLI: compress, translate with the shared cores, all levels at once.
     P->stage_begin(KIFMM_STAGE_COMPRESS, st);
     launch_gemm_nt(P->d_vt, nst, P->d_u, nst, nullptr, P->d_uhat, kst, nullptr, (int)P->total_slots, kst, nst, 1.0f,
-                   0, st, R, TS * nst, TS * kst);
+                   0, st, R, TS * nst, TS * kst, P->m2l_wide ? 1 : 0);
     P->stage_end(KIFMM_STAGE_COMPRESS, st);
     P->stage_begin(KIFMM_STAGE_M2L, st);
     const bool m2l_ok =
-        P->m2l_pieces
+        P->m2l_wide ? (launch_m2l_wide(P->d_cores, (long long)P->core_rows * kst, kst, P->d_units, P->n_units,
+                                       P->d_vlist, P->d_uhat, P->d_chat, TS * kst, st),
+                       true)
+        : P->m2l_pieces
             ? launch_m2l_bf16(P->m2l_pieces, P->m2l_rb, P->d_cores_b, P->core_stride16, kst,
                               m2l_bf16_lds_ld16(P->m2l_pieces), P->d_items, P->n_items, P->d_tgt_blk, P->d_src_blk,
                               P->d_pair_offs, P->d_uhat, P->d_chat_part, R * TS * kst, R, TS * kst, st)
@@ -632,7 +697,7 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
     P->stage_end(KIFMM_STAGE_M2L, st);
     // (2c) sum of the M2L partial sums, post (DC2E U_k) and D2D, coarse to fine.
     P->stage_begin(KIFMM_STAGE_L2L, st);
-    launch_sum_parts(P->d_chat_part, P->d_chat, R * TS * kst, R * TS * kst, st);
+    if (!P->m2l_wide) launch_sum_parts(P->d_chat_part, P->d_chat, R * TS * kst, R * TS * kst, st);
     for (int l = 2; l <= L; ++l) {
       launch_gemm_nt(P->d_post, kst, P->d_chat + P->base[l] * kst, kst, nullptr, P->d_d + P->base[l] * nst, nst,
                      nullptr, (int)P->slots[l], nst, kst, 1.0f, 0, st, R, TS * kst, TS * nst);

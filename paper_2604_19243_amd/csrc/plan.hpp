@@ -57,6 +57,10 @@ struct Plan : Object {
   hipStream_t side = nullptr;            // ULI stream (default priority)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   float4* d_near = nullptr;              // ULI result in sorted order (phi, grad)
+  bool m2l_wide = false;                 // nrhs = 32, FP32: per-target V lists with the right-hand sides as columns
+  int2* d_vlist = nullptr;               // (core index, source slot) per V-list entry, grouped by target
+  int4* d_units = nullptr;               // (target slot, row block, first entry, end entry)
+  int n_units = 0;
   float* d_qs = nullptr;                 // nrhs > 1: sorted charges [N][nrhs]
   int4* d_tasks = nullptr;               // nrhs > 1: leaf tasks (slot, first point, count <= 64, 0)
   int n_tasks = 0;
