@@ -1034,15 +1034,28 @@ __global__ __launch_bounds__(256) void k_leaf_multi(const float4* __restrict__ p
         float part[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) part[r] = 0.f;
-        for (int j = a; j < b; ++j) {
-          const float4 y = pts[j];
-          const float ex = x.x - y.x, ey = x.y - y.y, ez = x.z - y.z;
-          const float r2 = ex * ex + ey * ey + ez * ez;
-          float rinv = __builtin_amdgcn_rsqf(r2);
-          if (self) rinv = r2 > 0.f ? rinv : 0.f;  // the target itself
-          const float* qj = qs + (size_t)j * R;
+        if (a < b) {
+          // the next source's position and charges are fetched while this one is used
+          float4 yn = pts[a];
+          float qn[R];
 #pragma unroll
-          for (int r = 0; r < R; ++r) part[r] += qj[r] * rinv;
+          for (int r = 0; r < R; ++r) qn[r] = qs[(size_t)a * R + r];
+          for (int j = a; j < b; ++j) {
+            const float4 y = yn;
+            float qj[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) qj[r] = qn[r];
+            const int jn = min(j + 1, b - 1);
+            yn = pts[jn];
+#pragma unroll
+            for (int r = 0; r < R; ++r) qn[r] = qs[(size_t)jn * R + r];
+            const float ex = x.x - y.x, ey = x.y - y.y, ez = x.z - y.z;
+            const float r2 = ex * ex + ey * ey + ez * ez;
+            float rinv = __builtin_amdgcn_rsqf(r2);
+            if (self) rinv = r2 > 0.f ? rinv : 0.f;  // the target itself
+#pragma unroll
+            for (int r = 0; r < R; ++r) part[r] += qj[r] * rinv;
+          }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] += part[r];

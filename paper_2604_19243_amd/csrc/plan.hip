@@ -350,6 +350,13 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
       P->d_nbslot.assign(L + 1, nullptr);
       for (int l = 2; l <= L; ++l)
         P->d_nbslot[l] = dev_upload(own, slot_of[l].data(), slot_of[l].size(), "box slots");
+      {
+        std::vector<int> ne;
+        for (int l = 2; l <= L; ++l)
+          for (int sl : slot_of[l]) ne.push_back((int)(P->base[l] + sl));
+        P->n_nonempty = (int)ne.size();
+        P->d_nonempty = dev_upload(own, ne.data(), ne.size(), "non-empty slots");
+      }
 
       // VLI work items (see k_m2l).  For target position o and source position o'
       // (x bit 0, y bit 1, z bit 2) the V-list offsets are the parent shifts d in
@@ -678,8 +685,9 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
     P->stage_end(KIFMM_STAGE_M2M, st);
     // (2a) VLI: compress, translate with the shared cores, all levels at once.
     P->stage_begin(KIFMM_STAGE_COMPRESS, st);
-    launch_gemm_nt(P->d_vt, nst, P->d_u, nst, nullptr, P->d_uhat, kst, nullptr, (int)P->total_slots, kst, nst, 1.0f,
-                   0, st, R, TS * nst, TS * kst, P->m2l_wide ? 1 : 0);
+    // (empty boxes keep uhat = 0 from allocation: their rows are never written)
+    launch_gemm_nt(P->d_vt, nst, P->d_u, nst, P->d_nonempty, P->d_uhat, kst, P->d_nonempty, P->n_nonempty, kst, nst,
+                   1.0f, 0, st, R, TS * nst, TS * kst, P->m2l_wide ? 1 : 0);
     P->stage_end(KIFMM_STAGE_COMPRESS, st);
     P->stage_begin(KIFMM_STAGE_M2L, st);
     const bool m2l_ok =
@@ -698,15 +706,19 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
     // (2c) sum of the M2L partial sums, post (DC2E U_k) and D2D, coarse to fine.
     P->stage_begin(KIFMM_STAGE_L2L, st);
     if (!P->m2l_wide) launch_sum_parts(P->d_chat_part, P->d_chat, R * TS * kst, R * TS * kst, st);
+    // D2D first (all 8 children of each non-empty parent, overwritten), then the
+    // post product of the non-empty boxes added: d = L2L d_parent + post chat.
+    // Empty boxes' d is never read.
     for (int l = 2; l <= L; ++l) {
-      launch_gemm_nt(P->d_post, kst, P->d_chat + P->base[l] * kst, kst, nullptr, P->d_d + P->base[l] * nst, nst,
-                     nullptr, (int)P->slots[l], nst, kst, 1.0f, 0, st, R, TS * kst, TS * nst);
       if (l > 2) {
         const int parents = (int)P->keys_per_level[l - 1];
         launch_gemm_nt(P->d_l2l, nst, P->d_d + P->base[l - 1] * nst, nst, P->d_nbslot[l - 1],
-                       P->d_d + P->base[l] * nst, 8 * nst, nullptr, parents, 8 * nst, nst, 1.0f, 1, st, R, TS * nst,
+                       P->d_d + P->base[l] * nst, 8 * nst, nullptr, parents, 8 * nst, nst, 1.0f, 0, st, R, TS * nst,
                        TS * nst);
       }
+      launch_gemm_nt(P->d_post, kst, P->d_chat + P->base[l] * kst, kst, P->d_nbslot[l], P->d_d + P->base[l] * nst,
+                     nst, P->d_nbslot[l], (int)P->keys_per_level[l], nst, kst, 1.0f, l > 2 ? 1 : 0, st, R, TS * kst,
+                     TS * nst);
     }
     P->stage_end(KIFMM_STAGE_L2L, st);
   }

@@ -45,6 +45,8 @@ struct Plan : Object {
   uint16_t* d_cores_b = nullptr;         // split-bfloat16 cores (lane order, all pieces)
   size_t core_stride16 = 0;              // one offset's split cores, 16-byte units
   std::vector<int*> d_nbslot;
+  int* d_nonempty = nullptr;             // global slots of all non-empty boxes, levels 2..L
+  int n_nonempty = 0;
   float* d_chat_part = nullptr;
   int* d_pair_offs = nullptr;
   int* d_tgt_blk = nullptr;
