@@ -68,7 +68,7 @@ def cpu_baseline_worker(args):
     # accuracy of the GPU run(s): oracle direct sum at sampled targets, in blocks of sources
     gpu = np.load(args.gpu_sample)
     idx = gpu["idx"]
-    ref = np.zeros(len(idx))
+    ref = np.zeros((len(idx),) + s.shape[1:])
     for a in range(0, len(x), 250_000):
         ref += direct.potential(x[idx], x[a:a + 250_000], s[a:a + 250_000])
     acc = {"rel_l2_vs_direct_sampled": direct.rel_l2(gpu["phi"], ref), "direct_sample_targets": int(len(idx))}
