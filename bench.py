@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--backward", action="store_true",
                     help="time forward + backward: evaluate (potentials and field) then the vector-Jacobian "
                          "product of L = sum w_i f_i (adjoint evaluate + combination)")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture one step in a HIP graph (torch.cuda.graph) and time its replays")
     ap.add_argument("--compare-single", action="store_true",
                     help="with a multi-RHS workload: also time a one-RHS plan on the same tree and operators")
     ap.add_argument("--sample-leaves", type=int, default=24)
@@ -195,6 +197,10 @@ def main():
     charges = torch.from_numpy(s).to(dev)
     pot = torch.empty(w.n, device=dev) if R == 1 else torch.empty(w.n, R, device=dev)
     grad = torch.empty(w.n, 3, device=dev) if (R == 1 and (w.gradient or args.backward)) else None
+    if args.graph:
+        # graphs are captured on a (default-priority) stream of our own, not the null stream
+        torch.cuda.synchronize()
+        torch.cuda.set_stream(torch.cuda.Stream())
     stream = torch.cuda.current_stream()
     if args.backward:
         weights = torch.from_numpy(workloads.charges("normal", w.n, w.seed + 2000)).to(dev)
@@ -213,6 +219,29 @@ def main():
         for _ in range(args.warmup):
             step(plan)
         torch.cuda.synchronize()
+        if args.graph:
+            # one step captured on the evaluate stream; the timed region replays it
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=stream):
+                step(plan)
+            torch.cuda.synchronize()
+            start = torch.cuda.Event(enable_timing=True)
+            end = torch.cuda.Event(enable_timing=True)
+            start.record(stream)
+            for _ in range(args.steps):
+                g.replay()
+            end.record(stream)
+            torch.cuda.synchronize()
+            ms_ = start.elapsed_time(end) / args.steps
+            print(f"# {label} (graph replay): {ms_:.3f} ms/step", file=sys.stderr, flush=True)
+            del g
+            kifmm.kifmm_plan_set_timing(plan, True)
+            kifmm.kifmm_plan_get_stage_times(plan, reset=True)
+            step(plan)  # one eager step for the stage breakdown
+            torch.cuda.synchronize()
+            st = kifmm.kifmm_plan_get_stage_times(plan, reset=True)
+            kifmm.kifmm_plan_set_timing(plan, False)
+            return ms_, {k_: v[0] / max(v[1], 1) for k_, v in st.items()}
         kifmm.kifmm_plan_set_timing(plan, True)
         kifmm.kifmm_plan_get_stage_times(plan, reset=True)
         start = torch.cuda.Event(enable_timing=True)
@@ -288,7 +317,7 @@ def main():
         "config": {"workload": w.name, "n_points": w.n, "distribution": w.distribution, "charges": w.charges,
                    "p": w.p, "n_surface": n, "m2l_rank": k, "depth": w.depth, "nrhs": w.nrhs,
                    "outputs": "potential+gradient" if w.gradient else "potential", "parallelism": "single-gpu",
-                   "uli_overlap": not args.serial, "m2l": args.m2l,
+                   "uli_overlap": not args.serial, "m2l": args.m2l, "hip_graph": args.graph,
                    "step": ("forward (potentials and field) + backward (vector-Jacobian product of "
                             "sum w_i f_i, w ~ N(0,1))") if args.backward else "evaluate"},
         "roofline": roofline,
