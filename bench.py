@@ -136,6 +136,8 @@ def main():
                          "product of L = sum w_i f_i (adjoint evaluate + combination)")
     ap.add_argument("--graph", action="store_true",
                     help="capture one step in a HIP graph (torch.cuda.graph) and time its replays")
+    ap.add_argument("--m2l-form", choices=["auto", "blocked", "gathered"], default="auto",
+                    help="one-RHS FP32 M2L form (auto: the faster, timed at plan creation)")
     ap.add_argument("--compare-single", action="store_true",
                     help="with a multi-RHS workload: also time a one-RHS plan on the same tree and operators")
     ap.add_argument("--sample-leaves", type=int, default=24)
@@ -186,6 +188,7 @@ def main():
     else:
         flags = kifmm.KIFMM_POTENTIAL | kifmm.KIFMM_GRADIENT | (kifmm.KIFMM_SERIAL if args.serial else 0)
         flags |= kifmm.KIFMM_VJP if args.backward else 0
+    m2l_flag |= {"auto": 0, "blocked": kifmm.KIFMM_M2L_BLOCKED, "gathered": kifmm.KIFMM_M2L_GATHER}[args.m2l_form]
     f = kifmm.FMM(x, w.depth, w.p, cube=cube, eps_pinv=1e-7, eps_svd=1e-6, flags=flags | m2l_flag, nrhs=R)
     t_setup = time.perf_counter() - t_setup
     info = kifmm.kifmm_ops_get_info(f.ops)
@@ -284,7 +287,8 @@ def main():
     m2l_ms = stages["m2l"]
     m2l_flop = 2.0 * k * k * stats["m2l_pairs"] * R
     m2l_tflops = m2l_flop / (m2l_ms * 1e-3) / 1e12
-    m2l_kernel = f"k_m2l_bf16<{passes // 3 + 1}>" if bf16 else "k_m2l"
+    m2l_kernel = (f"k_m2l_bf16<{passes // 3 + 1}>" if bf16 else
+                  ["k_m2l", "k_m2l_gather", "k_m2l_wide", "k_m2l_bf16"][stats["m2l_form"]])
     traffic = load_traffic(w.name, m2l_kernel)
     # Leaf kernels: 20 FLOP per U-list pair (ULI) and per (target, downward-equivalent point) pair (D2T).
     # By default ULI runs on the plan's own stream beside the far field and D2T is a separate
@@ -318,6 +322,8 @@ def main():
                    "p": w.p, "n_surface": n, "m2l_rank": k, "depth": w.depth, "nrhs": w.nrhs,
                    "outputs": "potential+gradient" if w.gradient else "potential", "parallelism": "single-gpu",
                    "uli_overlap": not args.serial, "m2l": args.m2l, "hip_graph": args.graph,
+                   "m2l_form": ["blocked", "gathered", "wide (32 right-hand sides)", "split bfloat16 blocked"][
+                       stats["m2l_form"]],
                    "step": ("forward (potentials and field) + backward (vector-Jacobian product of "
                             "sum w_i f_i, w ~ N(0,1))") if args.backward else "evaluate"},
         "roofline": roofline,

@@ -182,6 +182,14 @@ kifmm_status kifmm_ops_destroy(kifmm_ops ops);
 /* KIFMM_VJP: allocate the workspace of kifmm_evaluate_vjp (two [n][3] float
  * fields on the device). */
 #define KIFMM_VJP 32u
+/* The plain FP32 M2L of a one-RHS plan has two forms: blocked (targets of a
+ * 4 x 4 x 4 block of parents with their sources staged in LDS; best for dense
+ * trees) and gathered (32 targets of one level and sibling position per wave,
+ * each gathering its own sources; best for sparse trees).  By default
+ * kifmm_plan_create times both on the plan's own tables and keeps the faster
+ * (stats[7] reports the choice); these flags force one. */
+#define KIFMM_M2L_BLOCKED 64u
+#define KIFMM_M2L_GATHER 128u
 
 /*
  * Place a tree and its operators on HIP device `device`: uploads the sorted
@@ -271,7 +279,9 @@ kifmm_status kifmm_plan_get_stage_times(kifmm_plan plan, double* ms, int64_t* co
  *   stats[0] = leaf-level pairs (target point, source point) of the U-list sum
  *   stats[1] = V-list (target box, source box) pairs over levels 2..L
  *   stats[2] = leaf slots, stats[3] = M2L target boxes, stats[4] = k, stats[5] = n,
- *   stats[6] = right-hand sides per evaluate */
+ *   stats[6] = right-hand sides per evaluate,
+ *   stats[7] = M2L form: 0 blocked FP32, 1 gathered FP32, 2 wide (32 right-hand sides),
+ *              3 split bfloat16 */
 kifmm_status kifmm_plan_get_stats(kifmm_plan plan, int64_t* stats, int count);
 
 /* Copy a level's densities to the host after the stream is idle, as float in

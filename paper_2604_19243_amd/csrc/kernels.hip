@@ -323,6 +323,72 @@ bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int 
   return true;
 }
 
+// ------------------------------------------------------ M2L, gathered ---
+// The compressed VLI with targets as columns, for one right-hand side: a group
+// is up to 32 target boxes of one level and one position among siblings (hence
+// one V-list offset set), and one wave per (group, 32-row block of C) walks the
+// union of the group's offsets.  Per entry lane j gathers its own target's
+// source row of uhat (a zero row where the target has no source at that offset)
+// and the MFMA columns are the group's targets, so sparse trees, whose blocked
+// items are mostly empty columns, keep full columns.  Operators in the lane
+// order of k_m2l; chat written once per target (no partial sums); accumulators
+// restarted every kM2LFlush entries (short FP32 chains).
+__global__ __launch_bounds__(64) void k_m2l_gather(const float* __restrict__ cores, long long core_stride, int nch,
+                                                   const int4* __restrict__ units, const int* __restrict__ ent_core,
+                                                   const int* __restrict__ ent_src, const int* __restrict__ grp_tgt,
+                                                   const float* __restrict__ uhat, float* __restrict__ chat, int ldk) {
+  const int4 u = units[blockIdx.x];  // (group, row block, first entry, end entry)
+  const int lane = threadIdx.x;
+  const int j = lane & 31, h = lane >> 5;
+  const float* alane = cores + (size_t)u.y * nch * 256 + 4 * lane;
+  v16f acc, tot;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = tot[e] = 0.f;
+  for (int e0 = u.z; e0 < u.w; e0 += kM2LFlush) {
+    const int e1 = min(e0 + kM2LFlush, u.w);
+    for (int e = e0; e < e1; ++e) {
+      const float* ap = alane + (size_t)ent_core[e] * core_stride;
+      const float* bp = uhat + (size_t)ent_src[(size_t)e * 32 + j] * ldk + 4 * h;
+      float4 a = *reinterpret_cast<const float4*>(ap);
+      float4 b = *reinterpret_cast<const float4*>(bp);
+      for (int c = 0; c < nch; ++c) {
+        const int cn = min(c + 1, nch - 1);  // next chunk (the last one repeats, unused)
+        const float4 an = *reinterpret_cast<const float4*>(ap + 256 * cn);
+        const float4 bn = *reinterpret_cast<const float4*>(bp + 8 * cn);
+        acc = mfma32(a.x, b.x, acc);
+        acc = mfma32(a.y, b.y, acc);
+        acc = mfma32(a.z, b.z, acc);
+        acc = mfma32(a.w, b.w, acc);
+        a = an;
+        b = bn;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      tot[e] += acc[e];
+      acc[e] = 0.f;
+    }
+  }
+  const int tgt = grp_tgt[(size_t)u.x * 32 + j];
+  if (tgt < 0) return;
+  // tot[v]: row 32 u.y + 8 (v / 4) + 4 h + v % 4 of target column j
+  float* out = chat + (size_t)tgt * ldk;
+#pragma unroll
+  for (int b4 = 0; b4 < 4; ++b4) {
+    const int row = 32 * u.y + 8 * b4 + 4 * h;
+    if (row < ldk)
+      *reinterpret_cast<float4*>(out + row) = make_float4(tot[4 * b4], tot[4 * b4 + 1], tot[4 * b4 + 2], tot[4 * b4 + 3]);
+  }
+}
+
+void launch_m2l_gather(const float* cores, long long core_stride, int ldk, const int4* units, int nunits,
+                       const int* ent_core, const int* ent_src, const int* grp_tgt, const float* uhat, float* chat,
+                       hipStream_t s) {
+  if (nunits <= 0) return;
+  hipLaunchKernelGGL(k_m2l_gather, dim3(nunits), dim3(64), 0, s, cores, core_stride, ldk / 8, units, ent_core,
+                     ent_src, grp_tgt, uhat, chat, ldk);
+}
+
 // -------------------------------------------------- M2L, 32 right-hand sides ---
 // The compressed VLI for 32 right-hand sides as wide products: per target box
 // and V-list entry (offset t, source box), chat[:, target] += C_t uhat[:, source]

@@ -42,6 +42,12 @@ bool launch_m2l_bf16(int pieces, int row_blocks, const uint16_t* cores, size_t c
 // launch_gemm_nt(ywide); chat [32][slots][ldk] (chat_rs = slots * ldk).
 void launch_m2l_wide(const float* cores, long long core_stride, int ldk, const int4* units, int nunits,
                      const int2* vlist, const float* uhat, float* chat, long long chat_rs, hipStream_t s);
+// M2L with gathered sources, one right-hand side: units (group, row block, first, end entry);
+// per entry the core index and 32 source rows of uhat (zero row where none); grp_tgt: 32
+// target slots per group (-1 = none); chat [slots][ldk].
+void launch_m2l_gather(const float* cores, long long core_stride, int ldk, const int4* units, int nunits,
+                       const int* ent_core, const int* ent_src, const int* grp_tgt, const float* uhat, float* chat,
+                       hipStream_t s);
 void launch_sum_parts(const float* part, float* chat, long long n, long long stride, hipStream_t s);
 // out[k][c] = w[k] fs[k][c] + s[k] fw[k][c] for k < n, c < 3.
 void launch_vjp_combine(const float* s, const float* w, const float* fs, const float* fw, float* out, int n,

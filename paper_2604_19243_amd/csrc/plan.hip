@@ -81,12 +81,15 @@ Plan::~Plan() {
 Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
   require(tree && ops, "null tree or ops");
   require((flags & ~(KIFMM_POTENTIAL | KIFMM_GRADIENT | KIFMM_SERIAL | KIFMM_M2L_BF16X3 | KIFMM_M2L_BF16X6 |
-                     KIFMM_VJP)) == 0 &&
+                     KIFMM_VJP | KIFMM_M2L_BLOCKED | KIFMM_M2L_GATHER)) == 0 &&
               (flags & (KIFMM_POTENTIAL | KIFMM_GRADIENT)) != 0,
           "flags must hold POTENTIAL and/or GRADIENT, optionally SERIAL, VJP and one of M2L_BF16X3, M2L_BF16X6");
   require(!((flags & KIFMM_M2L_BF16X3) && (flags & KIFMM_M2L_BF16X6)), "M2L_BF16X3 and M2L_BF16X6 exclude each other");
   require(nrhs == 1 || nrhs == 2 || nrhs == 4 || nrhs == 8 || nrhs == 16 || nrhs == 32,
           "nrhs must be 1, 2, 4, 8, 16 or 32");
+  require(!((flags & KIFMM_M2L_BLOCKED) && (flags & KIFMM_M2L_GATHER)), "M2L_BLOCKED and M2L_GATHER exclude each other");
+  require(!(flags & KIFMM_M2L_GATHER) || (nrhs == 1 && !(flags & (KIFMM_M2L_BF16X3 | KIFMM_M2L_BF16X6))),
+          "M2L_GATHER needs one right-hand side and the FP32 M2L");
   require(nrhs == 1 || !(flags & (KIFMM_GRADIENT | KIFMM_VJP)),
           "gradients and KIFMM_VJP need nrhs = 1 (plans with more right-hand sides give potentials)");
   int ndev = 0;
@@ -261,7 +264,8 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
       P->d_t = dev_upload<float>(own, nullptr, R * SL * kcst, "check coefficients");
       P->d_u = dev_upload<float>(own, nullptr, R * total * nst, "u");
       P->d_d = dev_upload<float>(own, nullptr, R * total * nst, "d");
-      P->d_uhat = dev_upload<float>(own, nullptr, R * total * kst, "uhat");
+      // one more zero row: the gathered M2L's source for "no source"
+      P->d_uhat = dev_upload<float>(own, nullptr, R * total * kst + kst, "uhat");
       P->d_chat = dev_upload<float>(own, nullptr, R * total * kst, "chat");
       // M2L partial sums, one per source position among siblings: [8][nrhs][total][kst]
       // (the wide 32-right-hand-side M2L writes chat directly and needs none).
@@ -480,19 +484,17 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
       for (int l = 0; l <= L; ++l) P->keys_per_level[l] = (int64_t)T.keys[l].size();
       P->slot_of = slot_of;
 
-      if (P->m2l_wide) {
-        // Per-target V lists (Table 1: children of the parent's colleagues, not
-        // adjacent, non-empty) as (core index, source slot), and work units
-        // (target, 32-row block) dealt to XCDs by the target's position among its
-        // siblings, row block by row block: an XCD then works through the ~189
-        // cores of one position and one row block at a time (its L2 holds them).
+      // Explicit per-target V lists (Table 1: children of the parent's colleagues,
+      // not adjacent, non-empty) as (core index, source slot), for the wide and
+      // the gathered M2L forms.
+      const bool want_gather = nrhs == 1 && P->m2l_pieces == 0 && !(flags & KIFMM_M2L_BLOCKED);
+      if (P->m2l_wide || want_gather) {
         std::vector<int> idx7(343, -1);
         for (int t = 0; t < kNumOffsets; ++t)
           idx7[(O.offsets[3 * t] + 3) + 7 * (O.offsets[3 * t + 1] + 3) + 49 * (O.offsets[3 * t + 2] + 3)] = t;
         std::vector<int> vl;
-        std::vector<std::vector<int>> per_xcd(8);
         std::vector<int64_t> tgt_first, tgt_end;
-        std::vector<int> tgt_slot, tgt_pos;
+        std::vector<int> tgt_slot, tgt_pos, tgt_level;
         for (int l = 2; l <= L; ++l) {
           const int64_t mp = 1ll << (l - 1), ml = 1ll << l;
           for (size_t i = 0; i < T.keys[l].size(); ++i) {
@@ -521,23 +523,79 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
             tgt_end.push_back((int64_t)vl.size() / 2);
             tgt_slot.push_back((int)(P->base[l] + slot_of[l][i]));
             tgt_pos.push_back((int)(T.keys[l][i] & 7));
+            tgt_level.push_back(l);
           }
         }
-        require(vl.size() / 2 < (size_t)INT32_MAX, "V lists too long for the wide M2L");
-        std::vector<int> units;
-        std::vector<std::vector<int>> ux(8);
-        for (int x = 0; x < 8; ++x)
-          for (int rb = 0; rb < P->m2l_rb; ++rb)
-            for (size_t i = 0; i < tgt_slot.size(); ++i)
-              if (tgt_pos[i] == x) ux[x].insert(ux[x].end(), {tgt_slot[i], rb, (int)tgt_first[i], (int)tgt_end[i]});
-        size_t most = 0;
-        for (auto& v : ux) most = std::max(most, v.size() / 4);
-        for (size_t i = 0; i < most; ++i)
+        require(vl.size() / 2 < (size_t)INT32_MAX, "V lists too long for the M2L tables");
+        // Units are dealt to XCDs by the target's position among its siblings, row
+        // block by row block: an XCD then works through the ~189 cores of one
+        // position and one row block at a time (its L2 holds them).
+        auto deal = [&](std::vector<std::vector<int>>& ux) {
+          std::vector<int> units;
+          size_t most = 0;
+          for (auto& v : ux) most = std::max(most, v.size() / 4);
+          for (size_t i = 0; i < most; ++i)
+            for (int x = 0; x < 8; ++x)
+              if (i < ux[x].size() / 4) units.insert(units.end(), ux[x].begin() + 4 * i, ux[x].begin() + 4 * i + 4);
+          return units;
+        };
+        if (P->m2l_wide) {
+          std::vector<std::vector<int>> ux(8);
           for (int x = 0; x < 8; ++x)
-            if (i < ux[x].size() / 4) units.insert(units.end(), ux[x].begin() + 4 * i, ux[x].begin() + 4 * i + 4);
-        P->n_units = (int)(units.size() / 4);
-        P->d_vlist = reinterpret_cast<int2*>(dev_upload(own, vl.data(), vl.size(), "m2l v lists"));
-        P->d_units = reinterpret_cast<int4*>(dev_upload(own, units.data(), units.size(), "m2l units"));
+            for (int rb = 0; rb < P->m2l_rb; ++rb)
+              for (size_t i = 0; i < tgt_slot.size(); ++i)
+                if (tgt_pos[i] == x) ux[x].insert(ux[x].end(), {tgt_slot[i], rb, (int)tgt_first[i], (int)tgt_end[i]});
+          const std::vector<int> units = deal(ux);
+          P->n_units = (int)(units.size() / 4);
+          P->d_vlist = reinterpret_cast<int2*>(dev_upload(own, vl.data(), vl.size(), "m2l v lists"));
+          P->d_units = reinterpret_cast<int4*>(dev_upload(own, units.data(), units.size(), "m2l units"));
+        } else {
+          // Gathered form: groups of up to 32 targets of one level and position; per
+          // group the union of their offsets (ascending core index) and, per offset,
+          // each target's source row (the zero row total_slots where it has none).
+          std::vector<int> ent_core, ent_src, gtgt;
+          std::vector<std::vector<int>> ux(8);
+          std::vector<int> lane_src((size_t)kNumOffsets * 32);
+          std::vector<char> used(kNumOffsets);
+          const int zero_row = (int)total;
+          for (int l = 2; l <= L; ++l)
+            for (int x = 0; x < 8; ++x) {
+              std::vector<int> members;
+              for (size_t i = 0; i < tgt_slot.size(); ++i)
+                if (tgt_level[i] == l && tgt_pos[i] == x) members.push_back((int)i);
+              for (size_t g0 = 0; g0 < members.size(); g0 += 32) {
+                const int g = (int)(gtgt.size() / 32);
+                std::fill(lane_src.begin(), lane_src.end(), zero_row);
+                std::fill(used.begin(), used.end(), 0);
+                for (int jl = 0; jl < 32; ++jl) {
+                  const bool real = g0 + jl < members.size();
+                  const int i = real ? members[g0 + jl] : -1;
+                  gtgt.push_back(real ? tgt_slot[i] : -1);
+                  if (!real) continue;
+                  for (int64_t e = tgt_first[i]; e < tgt_end[i]; ++e) {
+                    const int t = vl[2 * e];
+                    used[t] = 1;
+                    lane_src[(size_t)t * 32 + jl] = vl[2 * e + 1];
+                  }
+                }
+                const int first = (int)ent_core.size();
+                for (int t = 0; t < kNumOffsets; ++t) {
+                  if (!used[t]) continue;
+                  ent_core.push_back(t);
+                  ent_src.insert(ent_src.end(), lane_src.begin() + (size_t)t * 32, lane_src.begin() + (size_t)t * 32 + 32);
+                }
+                const int end = (int)ent_core.size();
+                for (int rb = 0; rb < P->m2l_rb; ++rb) ux[x].insert(ux[x].end(), {g, rb, first, end});
+              }
+            }
+          const std::vector<int> units = deal(ux);
+          P->n_gunits = (int)(units.size() / 4);
+          P->d_gent_core = dev_upload(own, ent_core.data(), ent_core.size(), "m2l gathered entries");
+          P->d_gent_src = dev_upload(own, ent_src.data(), ent_src.size(), "m2l gathered sources");
+          P->d_gtgt = dev_upload(own, gtgt.data(), gtgt.size(), "m2l gathered targets");
+          P->d_gunits = reinterpret_cast<int4*>(dev_upload(own, units.data(), units.size(), "m2l gathered units"));
+          P->m2l_gather = (flags & KIFMM_M2L_GATHER) != 0;
+        }
       }
     }
     if (nrhs > 1) {
@@ -568,6 +626,34 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
       P->d_vjp_fw = dev_upload<float>(own, nullptr, 3 * (size_t)T.n, "vjp field");
     }
     hip_check(hipDeviceSynchronize(), "plan upload");
+    if (P->d_gunits && !(flags & (KIFMM_M2L_BLOCKED | KIFMM_M2L_GATHER))) {
+      // Autotuning of the M2L form: each form runs once to warm up and once timed
+      // (M2L plus, for the blocked form, its partial-sum reduction) on the plan's
+      // own tables; the faster is kept.  The work does not depend on the values.
+      const long long n_red = (long long)P->nrhs * P->total_slots * P->kst;
+      hipEvent_t e0, e1;
+      hip_check(hipEventCreate(&e0), "hipEventCreate");
+      hip_check(hipEventCreate(&e1), "hipEventCreate");
+      for (int form = 0; form < 2; ++form) {
+        P->m2l_gather = form == 1;
+        float ms = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {
+          hip_check(hipEventRecord(e0, nullptr), "hipEventRecord");
+          if (!launch_m2l_form(P, nullptr)) fail(KIFMM_E_DEVICE, "M2L kernel configuration not available");
+          if (!P->m2l_gather) launch_sum_parts(P->d_chat_part, P->d_chat, n_red, n_red, nullptr);
+          hip_check(hipEventRecord(e1, nullptr), "hipEventRecord");
+          hip_check(hipEventSynchronize(e1), "M2L autotune");
+          hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        }
+        P->m2l_tune_ms[form] = ms;
+      }
+      hip_check(hipGetLastError(), "M2L autotune");
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      P->m2l_gather = P->m2l_tune_ms[1] < P->m2l_tune_ms[0];
+      hip_check(hipMemset(P->d_chat, 0, sizeof(float) * (size_t)n_red), "chat reset");
+      hip_check(hipDeviceSynchronize(), "M2L autotune");
+    }
   } catch (...) {
     delete P;
     (void)hipSetDevice(prev);
@@ -614,6 +700,29 @@ void Plan::collect_times() {
       r = 0;
     }
   ring_used = 0;
+}
+
+// The M2L launch of the plan's form (uhat -> chat, or -> the partial sums that
+// k_sum_parts adds).  False if no kernel instance fits.
+bool launch_m2l_form(Plan* P, hipStream_t st) {
+  const int kst = P->kst, R = P->nrhs;
+  const long long TS = P->total_slots;
+  if (P->m2l_wide) {
+    launch_m2l_wide(P->d_cores, (long long)P->core_rows * kst, kst, P->d_units, P->n_units, P->d_vlist, P->d_uhat,
+                    P->d_chat, TS * kst, st);
+    return true;
+  }
+  if (P->m2l_gather) {
+    launch_m2l_gather(P->d_cores, (long long)P->core_rows * kst, kst, P->d_gunits, P->n_gunits, P->d_gent_core,
+                      P->d_gent_src, P->d_gtgt, P->d_uhat, P->d_chat, st);
+    return true;
+  }
+  if (P->m2l_pieces)
+    return launch_m2l_bf16(P->m2l_pieces, P->m2l_rb, P->d_cores_b, P->core_stride16, kst,
+                           m2l_bf16_lds_ld16(P->m2l_pieces), P->d_items, P->n_items, P->d_tgt_blk, P->d_src_blk,
+                           P->d_pair_offs, P->d_uhat, P->d_chat_part, R * TS * kst, R, TS * kst, st);
+  return launch_m2l(P->m2l_rb, P->d_cores, P->core_rows, kst, P->m2l_lds_ld, P->d_items, P->n_items, P->d_tgt_blk,
+                    P->d_src_blk, P->d_pair_offs, P->d_uhat, P->d_chat_part, R * TS * kst, R, TS * kst, st);
 }
 
 void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipStream_t st) {
@@ -690,22 +799,12 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
                    1.0f, 0, st, R, TS * nst, TS * kst, P->m2l_wide ? 1 : 0);
     P->stage_end(KIFMM_STAGE_COMPRESS, st);
     P->stage_begin(KIFMM_STAGE_M2L, st);
-    const bool m2l_ok =
-        P->m2l_wide ? (launch_m2l_wide(P->d_cores, (long long)P->core_rows * kst, kst, P->d_units, P->n_units,
-                                       P->d_vlist, P->d_uhat, P->d_chat, TS * kst, st),
-                       true)
-        : P->m2l_pieces
-            ? launch_m2l_bf16(P->m2l_pieces, P->m2l_rb, P->d_cores_b, P->core_stride16, kst,
-                              m2l_bf16_lds_ld16(P->m2l_pieces), P->d_items, P->n_items, P->d_tgt_blk, P->d_src_blk,
-                              P->d_pair_offs, P->d_uhat, P->d_chat_part, R * TS * kst, R, TS * kst, st)
-            : launch_m2l(P->m2l_rb, P->d_cores, P->core_rows, kst, P->m2l_lds_ld, P->d_items, P->n_items,
-                         P->d_tgt_blk, P->d_src_blk, P->d_pair_offs, P->d_uhat, P->d_chat_part, R * TS * kst, R,
-                         TS * kst, st);
+    const bool m2l_ok = launch_m2l_form(P, st);
     if (!m2l_ok) fail(KIFMM_E_DEVICE, "M2L kernel configuration not available");
     P->stage_end(KIFMM_STAGE_M2L, st);
     // (2c) sum of the M2L partial sums, post (DC2E U_k) and D2D, coarse to fine.
     P->stage_begin(KIFMM_STAGE_L2L, st);
-    if (!P->m2l_wide) launch_sum_parts(P->d_chat_part, P->d_chat, R * TS * kst, R * TS * kst, st);
+    if (!P->m2l_wide && !P->m2l_gather) launch_sum_parts(P->d_chat_part, P->d_chat, R * TS * kst, R * TS * kst, st);
     // D2D first (all 8 children of each non-empty parent, overwritten), then the
     // post product of the non-empty boxes added: d = L2L d_parent + post chat.
     // Empty boxes' d is never read.

@@ -60,6 +60,13 @@ struct Plan : Object {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   float4* d_near = nullptr;              // ULI result in sorted order (phi, grad)
   bool m2l_wide = false;                 // nrhs = 32, FP32: per-target V lists with the right-hand sides as columns
+  bool m2l_gather = false;               // one right-hand side, FP32: gathered form (targets as columns)
+  int* d_gent_core = nullptr;            // gathered form: core index per entry
+  int* d_gent_src = nullptr;             //   32 source rows of uhat per entry (zero row = total_slots)
+  int* d_gtgt = nullptr;                 //   32 target slots per group (-1 = none)
+  int4* d_gunits = nullptr;              //   (group, row block, first entry, end entry)
+  int n_gunits = 0;
+  double m2l_tune_ms[2] = {0.0, 0.0};    // autotuned M2L forms: blocked, gathered (ms per launch)
   int2* d_vlist = nullptr;               // (core index, source slot) per V-list entry, grouped by target
   int4* d_units = nullptr;               // (target slot, row block, first entry, end entry)
   int n_units = 0;
@@ -85,6 +92,7 @@ struct Plan : Object {
 
 Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device);
 void evaluate_plan(Plan* plan, const float* charges, float* pot, float* grad, hipStream_t st);
+bool launch_m2l_form(Plan* plan, hipStream_t st);
 void evaluate_vjp(Plan* plan, const float* charges, const float* weights, const float* field, float* grad_charges,
                   float* grad_points, hipStream_t st);
 void read_density(Plan* plan, int kind, int level, float* out, int64_t capacity);

@@ -29,6 +29,8 @@ KIFMM_SERIAL = 4
 KIFMM_M2L_BF16X3 = 8
 KIFMM_M2L_BF16X6 = 16
 KIFMM_VJP = 32
+KIFMM_M2L_BLOCKED = 64
+KIFMM_M2L_GATHER = 128
 
 (KIFMM_OP_SURFACE, KIFMM_OP_UC2E, KIFMM_OP_DC2E, KIFMM_OP_M2M, KIFMM_OP_L2L, KIFMM_OP_M2L_U, KIFMM_OP_M2L_V,
  KIFMM_OP_M2L_CORE, KIFMM_OP_M2L_OFFSET, KIFMM_OP_M2L_POST) = range(10)
@@ -219,9 +221,9 @@ def kifmm_plan_get_stage_times(plan, reset=True):
 
 
 def kifmm_plan_get_stats(plan):
-    out = np.zeros(7, dtype=np.int64)
-    _check(library().kifmm_plan_get_stats(plan, _host_ptr(out), 7))
-    keys = ["p2p_pairs", "m2l_pairs", "leaf_slots", "m2l_targets", "k", "n", "nrhs"]
+    out = np.zeros(8, dtype=np.int64)
+    _check(library().kifmm_plan_get_stats(plan, _host_ptr(out), 8))
+    keys = ["p2p_pairs", "m2l_pairs", "leaf_slots", "m2l_targets", "k", "n", "nrhs", "m2l_form"]
     return dict(zip(keys, (int(v) for v in out)))
 
 

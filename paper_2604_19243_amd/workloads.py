@@ -41,6 +41,8 @@ WORKLOADS = {
     "cube1m_p6_d5": Workload("cube1m_p6_d5", 1_000_000, "cube", "uniform01", 6, 5, 1, True, 1002),
     "cube8m_p8_d6": Workload("cube8m_p8_d6", 8_000_000, "cube", "normal", 8, 6, 1, False, 1003),
     "sphere4m_p6_d7_r32": Workload("sphere4m_p6_d7_r32", 4_000_000, "sphere", "normal", 6, 7, 32, False, 1004),
+    # the same sphere points with one right-hand side, potentials and gradients
+    "sphere4m_p6_d7": Workload("sphere4m_p6_d7", 4_000_000, "sphere", "normal", 6, 7, 1, True, 1004),
     "cube2m_p7_d6": Workload("cube2m_p7_d6", 2_000_000, "cube", "uniform11", 7, 6, 1, True, 1005),
 }
 

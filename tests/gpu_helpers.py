@@ -14,7 +14,8 @@ def log(msg):
     sys.stdout.flush()
 
 
-M2L_FLAGS = {"fp32": 0, "bf16x3": kifmm.KIFMM_M2L_BF16X3, "bf16x6": kifmm.KIFMM_M2L_BF16X6}
+M2L_FLAGS = {"fp32": 0, "bf16x3": kifmm.KIFMM_M2L_BF16X3, "bf16x6": kifmm.KIFMM_M2L_BF16X6,
+             "blocked": kifmm.KIFMM_M2L_BLOCKED, "gather": kifmm.KIFMM_M2L_GATHER}
 
 
 def gpu_evaluate(points, charges, depth, p, cube, eps_svd=1e-6, rank=0, gradient=True, fmm_obj=None, serial=False,

@@ -1,0 +1,67 @@
+"""The two forms of the plain FP32 M2L for one right-hand side, forced with
+KIFMM_M2L_BLOCKED / KIFMM_M2L_GATHER, against the FP64 oracle and against each
+other; and the plan's own choice between them (timed at plan creation).
+
+Tolerance: relative L2 <= 1e-6 against the oracle (plain FP32 path).
+"""
+
+import numpy as np
+import pytest
+
+from gpu_helpers import gpu_evaluate, log, oracle_evaluate, rel_l2
+from paper_2604_19243_amd import kifmm, workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+UNIT = (0.5, 0.5, 0.5, 0.5)
+SPHERE = (0.0, 0.0, 0.0, 1.0)
+
+
+@pytest.mark.parametrize("name,n,depth,p,dist,charges", [
+    ("cube20k_p6_d3", 20_000, 3, 6, "cube", "uniform01"),
+    ("sphere", 30_000, 5, 6, "sphere", "normal"),       # sparse: the gathered form's case
+    ("ragged", 7_777, 4, 5, "cube", "uniform11"),
+    ("sparse_deep", 2_000, 6, 4, "cube", "uniform01"),
+    ("p8", 8_000, 3, 8, "cube", "uniform11"),
+])
+def test_gathered_m2l_parity_with_oracle(name, n, depth, p, dist, charges):
+    log(f"gathered M2L parity {name} n={n} depth={depth} p={p}")
+    x = workloads.points(dist, n, 1001 if name.startswith("cube20k") else 610 + n)
+    s = workloads.charges(charges, n, 2001 if name.startswith("cube20k") else 620 + n)
+    cube = UNIT if dist == "cube" else SPHERE
+    phi, g, f = gpu_evaluate(x, s, depth, p, cube, m2l="gather")
+    assert kifmm.kifmm_plan_get_stats(f.plan)["m2l_form"] == 1
+    f.close()
+    phb, gb, f = gpu_evaluate(x, s, depth, p, cube, m2l="blocked")
+    assert kifmm.kifmm_plan_get_stats(f.plan)["m2l_form"] == 0
+    f.close()
+    rphi, rg, _, _ = oracle_evaluate(x, s, depth, p, cube)
+    e, eg = rel_l2(phi, rphi), rel_l2(g, rg)
+    d = rel_l2(phi, phb)
+    log(f"  gathered rel-L2 phi {e:.3e} grad {eg:.3e}; vs blocked {d:.3e}")
+    assert e < TOL and eg < TOL and d < TOL
+
+
+def test_autotuned_form_is_reported_and_correct():
+    log("autotuned M2L form")
+    w = workloads.WORKLOADS["cube20k_p6_d3"]
+    x, s = workloads.make(w)
+    c = w.cube[0] + (w.cube[1],)
+    phi, g, f = gpu_evaluate(x, s, w.depth, w.p, c)
+    form = kifmm.kifmm_plan_get_stats(f.plan)["m2l_form"]
+    f.close()
+    assert form in (0, 1)
+    rphi, rg, _, _ = oracle_evaluate(x, s, w.depth, w.p, c)
+    log(f"  chosen form {form}: rel-L2 phi {rel_l2(phi, rphi):.3e}")
+    assert rel_l2(phi, rphi) < TOL and rel_l2(g, rg) < TOL
+
+
+def test_m2l_form_flag_errors():
+    x = workloads.points("cube", 400, 58)
+    with pytest.raises(kifmm.KifmmError):
+        kifmm.FMM(x, 3, 4, cube=UNIT, flags=kifmm.KIFMM_POTENTIAL | kifmm.KIFMM_M2L_BLOCKED | kifmm.KIFMM_M2L_GATHER)
+    with pytest.raises(kifmm.KifmmError):
+        kifmm.FMM(x, 3, 4, cube=UNIT, flags=kifmm.KIFMM_POTENTIAL | kifmm.KIFMM_M2L_GATHER | kifmm.KIFMM_M2L_BF16X3)
+    with pytest.raises(kifmm.KifmmError):
+        kifmm.FMM(x, 3, 4, cube=UNIT, flags=kifmm.KIFMM_POTENTIAL | kifmm.KIFMM_M2L_GATHER, nrhs=4)
