@@ -285,7 +285,9 @@ def main():
     # M2L (dominant kernel): 2 k^2 FLOP per (target, source) V-list pair; the split-bfloat16
     # forms execute each product as 3 or 6 bfloat16 products, counted against the BF16 peak.
     m2l_ms = stages["m2l"]
-    m2l_flop = 2.0 * k * k * stats["m2l_pairs"] * R
+    # the pairs of the KIFMM_STAGE_M2L launch (the leaf level alone when the levels above it
+    # run beside it on the plan's second stream)
+    m2l_flop = 2.0 * k * k * stats["m2l_stage_pairs"] * R
     m2l_tflops = m2l_flop / (m2l_ms * 1e-3) / 1e12
     m2l_kernel = (f"k_m2l_bf16<{passes // 3 + 1}>" if bf16 else
                   ["k_m2l", "k_m2l_gather", "k_m2l_wide", "k_m2l_bf16"][stats["m2l_form"]])
@@ -309,7 +311,7 @@ def main():
         roofline = {"kernel": m2l_kernel, "bound": "mfma", "achieved": m2l_tflops, "peak": PEAK_FP32_TFLOPS,
                     "unit": "TFLOP/s", "frac": m2l_tflops / PEAK_FP32_TFLOPS, "traffic": traffic}
     roofline.update({"ms_per_launch": m2l_ms, "algorithmic_flop_per_launch": m2l_flop,
-                     "v_list_pairs": stats["m2l_pairs"]})
+                     "v_list_pairs": stats["m2l_stage_pairs"], "v_list_pairs_all_levels": stats["m2l_pairs"]})
 
     result = {
         "metric": METRIC,

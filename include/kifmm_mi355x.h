@@ -260,9 +260,10 @@ enum {
   KIFMM_STAGE_PERMUTE = 0, /* gather charges into sorted order */
   KIFMM_STAGE_P2M = 1,     /* leaf sources -> upward-check field (S2U, first half) */
   KIFMM_STAGE_UC2E = 2,    /* upward-check field -> upward density, two factors */
-  KIFMM_STAGE_M2M = 3,     /* U2U, all levels */
-  KIFMM_STAGE_COMPRESS = 4,/* u -> V_k^T u, levels 2..L */
-  KIFMM_STAGE_M2L = 5,     /* compressed VLI over all levels (one kernel) */
+  KIFMM_STAGE_M2M = 3,     /* U2U, all levels; with the plan's second stream also the compression and
+                              VLI of the levels above the leaves, which run there beside the leaf VLI */
+  KIFMM_STAGE_COMPRESS = 4,/* u -> V_k^T u, levels 2..L (the leaf level alone with the second stream) */
+  KIFMM_STAGE_M2L = 5,     /* compressed VLI, all levels (the leaf level alone with the second stream) */
   KIFMM_STAGE_L2L = 6,     /* sum of M2L partial sums, post (DC2E U_k) and D2D, levels 2..L */
   KIFMM_STAGE_P2P = 7,     /* ULI at the leaves (on the plan's stream), or fused D2T + ULI with KIFMM_SERIAL */
   KIFMM_STAGE_L2P = 8,     /* D2T added to the ULI result, written in input order (not with KIFMM_SERIAL) */
@@ -281,7 +282,9 @@ kifmm_status kifmm_plan_get_stage_times(kifmm_plan plan, double* ms, int64_t* co
  *   stats[2] = leaf slots, stats[3] = M2L target boxes, stats[4] = k, stats[5] = n,
  *   stats[6] = right-hand sides per evaluate,
  *   stats[7] = M2L form: 0 blocked FP32, 1 gathered FP32, 2 wide (32 right-hand sides),
- *              3 split bfloat16 */
+ *              3 split bfloat16,
+ *   stats[8] = V-list pairs of the KIFMM_STAGE_M2L launch (the leaf level's
+ *              alone when the levels above it run on the plan's second stream) */
 kifmm_status kifmm_plan_get_stats(kifmm_plan plan, int64_t* stats, int count);
 
 /* Copy a level's densities to the host after the stream is idle, as float in

@@ -71,7 +71,10 @@ Plan::~Plan() {
   for (auto& e : ev) (void)hipEventDestroy(e);
   if (ev_fork) (void)hipEventDestroy(ev_fork);
   if (ev_join) (void)hipEventDestroy(ev_join);
+  if (ev_up0) (void)hipEventDestroy(ev_up0);
+  if (ev_up1) (void)hipEventDestroy(ev_up1);
   if (side) (void)hipStreamDestroy(side);
+  if (up) (void)hipStreamDestroy(up);
   for (void* p : owned) (void)hipFree(p);
   (void)hipSetDevice(prev);
   release(tree);
@@ -392,9 +395,13 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
       }
       P->d_pair_offs = dev_upload(own, pair_offs.data(), pair_offs.size(), "m2l pair offsets");
       std::vector<int> tgt_blk, src_blk;
-      std::vector<std::vector<M2LItem>> per_xcd(8);
-      int64_t vpairs = 0, ntargets = 0;
+      // items of the leaf level and of the levels above it, kept apart so that the
+      // upper levels can run beside the leaf level's M2L (see evaluate_plan)
+      std::vector<std::vector<M2LItem>> per_xcd_l[2] = {std::vector<std::vector<M2LItem>>(8),
+                                                         std::vector<std::vector<M2LItem>>(8)};
+      int64_t vpairs = 0, ntargets = 0, vpairs_leaf = 0;
       for (int l = L; l >= 2; --l) {
+        auto& per_xcd = per_xcd_l[l == L ? 0 : 1];
         const int64_t mp = 1ll << (l - 1);  // parents per axis
         const int64_t ml = 1ll << l;
         // aligned 4x4x4 blocks of parents that hold at least one non-empty parent
@@ -442,6 +449,7 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
                   const int ex = e % 6, ey = (e / 6) % 6, ez = e / 36;  // (d + 1) per axis, in 0..2
                   const int r = ((pi & 3) + ex) + 6 * (((pi >> 2) & 3) + ey) + 36 * ((pi >> 4) + ez);
                   vpairs += src_blk[src_base[o2] + r] >= 0;
+                  if (l == L) vpairs_leaf += src_blk[src_base[o2] + r] >= 0;
                 }
             }
             if (!count) {
@@ -460,17 +468,22 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
       // L2 holds the ~24 translation cores of the pair its CUs are working on, and
       // pairs with more offsets (longer items) come first, so the end of the grid
       // is made of short items.
-      for (auto& v : per_xcd)
-        std::stable_sort(v.begin(), v.end(), [](const M2LItem& a, const M2LItem& b) {
-          return a.noffs != b.noffs ? a.noffs > b.noffs : a.pair < b.pair;
-        });
       std::vector<M2LItem> items;
-      size_t most = 0;
-      for (auto& v : per_xcd) most = std::max(most, v.size());
-      for (size_t i = 0; i < most; ++i)
-        for (int x = 0; x < 8; ++x)
-          if (i < per_xcd[x].size()) items.push_back(per_xcd[x][i]);
+      for (int part = 0; part < 2; ++part) {
+        auto& per_xcd = per_xcd_l[part];
+        for (auto& v : per_xcd)
+          std::stable_sort(v.begin(), v.end(), [](const M2LItem& a, const M2LItem& b) {
+            return a.noffs != b.noffs ? a.noffs > b.noffs : a.pair < b.pair;
+          });
+        size_t most = 0;
+        for (auto& v : per_xcd) most = std::max(most, v.size());
+        for (size_t i = 0; i < most; ++i)
+          for (int x = 0; x < 8; ++x)
+            if (i < per_xcd[x].size()) items.push_back(per_xcd[x][i]);
+        if (part == 0) P->n_items_leaf = (int)items.size();
+      }
       P->m2l_pairs = vpairs;
+      P->m2l_pairs_leaf = vpairs_leaf;
       P->m2l_targets = ntargets;
       P->n_items = (int)items.size();
       // LDS row stride of one 40-k slab of the staged sources: 44 floats, an odd
@@ -554,12 +567,13 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
           // group the union of their offsets (ascending core index) and, per offset,
           // each target's source row (the zero row total_slots where it has none).
           std::vector<int> ent_core, ent_src, gtgt;
-          std::vector<std::vector<int>> ux(8);
+          std::vector<std::vector<int>> ux_leaf(8), ux_upper(8);
           std::vector<int> lane_src((size_t)kNumOffsets * 32);
           std::vector<char> used(kNumOffsets);
           const int zero_row = (int)total;
           for (int l = 2; l <= L; ++l)
             for (int x = 0; x < 8; ++x) {
+              auto& ux = l == L ? ux_leaf : ux_upper;
               std::vector<int> members;
               for (size_t i = 0; i < tgt_slot.size(); ++i)
                 if (tgt_level[i] == l && tgt_pos[i] == x) members.push_back((int)i);
@@ -588,7 +602,10 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
                 for (int rb = 0; rb < P->m2l_rb; ++rb) ux[x].insert(ux[x].end(), {g, rb, first, end});
               }
             }
-          const std::vector<int> units = deal(ux);
+          std::vector<int> units = deal(ux_leaf);
+          P->n_gunits_leaf = (int)(units.size() / 4);
+          const std::vector<int> upper = deal(ux_upper);
+          units.insert(units.end(), upper.begin(), upper.end());
           P->n_gunits = (int)(units.size() / 4);
           P->d_gent_core = dev_upload(own, ent_core.data(), ent_core.size(), "m2l gathered entries");
           P->d_gent_src = dev_upload(own, ent_src.data(), ent_src.size(), "m2l gathered sources");
@@ -615,6 +632,12 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
       P->n_tasks = (int)(tk.size() / 4);
       if (P->n_tasks) P->d_tasks = reinterpret_cast<int4*>(dev_upload(own, tk.data(), tk.size(), "leaf tasks"));
     }
+    if (P->far && !(flags & KIFMM_SERIAL) && nrhs == 1 && L >= 3) {
+      // the levels above the leaves run on a second plan stream (default priority)
+      hip_check(hipStreamCreateWithFlags(&P->up, hipStreamNonBlocking), "hipStreamCreate");
+      hip_check(hipEventCreateWithFlags(&P->ev_up0, hipEventDisableTiming), "hipEventCreate");
+      hip_check(hipEventCreateWithFlags(&P->ev_up1, hipEventDisableTiming), "hipEventCreate");
+    }
     if (P->far && !(flags & KIFMM_SERIAL) && nrhs == 1) {
       hip_check(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking), "hipStreamCreate");
       hip_check(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming), "hipEventCreate");
@@ -639,7 +662,7 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
         float ms = 0.f;
         for (int rep = 0; rep < 2; ++rep) {
           hip_check(hipEventRecord(e0, nullptr), "hipEventRecord");
-          if (!launch_m2l_form(P, nullptr)) fail(KIFMM_E_DEVICE, "M2L kernel configuration not available");
+          if (!launch_m2l_form(P, nullptr, 0)) fail(KIFMM_E_DEVICE, "M2L kernel configuration not available");
           if (!P->m2l_gather) launch_sum_parts(P->d_chat_part, P->d_chat, n_red, n_red, nullptr);
           hip_check(hipEventRecord(e1, nullptr), "hipEventRecord");
           hip_check(hipEventSynchronize(e1), "M2L autotune");
@@ -703,25 +726,31 @@ void Plan::collect_times() {
 }
 
 // The M2L launch of the plan's form (uhat -> chat, or -> the partial sums that
-// k_sum_parts adds).  False if no kernel instance fits.
-bool launch_m2l_form(Plan* P, hipStream_t st) {
+// k_sum_parts adds), for all target levels (part 0), the leaf level (part 1) or
+// the levels above it (part 2).  False if no kernel instance fits.
+bool launch_m2l_form(Plan* P, hipStream_t st, int part) {
   const int kst = P->kst, R = P->nrhs;
   const long long TS = P->total_slots;
   if (P->m2l_wide) {
+    if (part == 2) return true;
     launch_m2l_wide(P->d_cores, (long long)P->core_rows * kst, kst, P->d_units, P->n_units, P->d_vlist, P->d_uhat,
                     P->d_chat, TS * kst, st);
     return true;
   }
   if (P->m2l_gather) {
-    launch_m2l_gather(P->d_cores, (long long)P->core_rows * kst, kst, P->d_gunits, P->n_gunits, P->d_gent_core,
+    const int u0 = part == 2 ? P->n_gunits_leaf : 0;
+    const int u1 = part == 1 ? P->n_gunits_leaf : P->n_gunits;
+    launch_m2l_gather(P->d_cores, (long long)P->core_rows * kst, kst, P->d_gunits + u0, u1 - u0, P->d_gent_core,
                       P->d_gent_src, P->d_gtgt, P->d_uhat, P->d_chat, st);
     return true;
   }
+  const int i0 = part == 2 ? P->n_items_leaf : 0;
+  const int i1 = part == 1 ? P->n_items_leaf : P->n_items;
   if (P->m2l_pieces)
     return launch_m2l_bf16(P->m2l_pieces, P->m2l_rb, P->d_cores_b, P->core_stride16, kst,
-                           m2l_bf16_lds_ld16(P->m2l_pieces), P->d_items, P->n_items, P->d_tgt_blk, P->d_src_blk,
+                           m2l_bf16_lds_ld16(P->m2l_pieces), P->d_items + i0, i1 - i0, P->d_tgt_blk, P->d_src_blk,
                            P->d_pair_offs, P->d_uhat, P->d_chat_part, R * TS * kst, R, TS * kst, st);
-  return launch_m2l(P->m2l_rb, P->d_cores, P->core_rows, kst, P->m2l_lds_ld, P->d_items, P->n_items, P->d_tgt_blk,
+  return launch_m2l(P->m2l_rb, P->d_cores, P->core_rows, kst, P->m2l_lds_ld, P->d_items + i0, i1 - i0, P->d_tgt_blk,
                     P->d_src_blk, P->d_pair_offs, P->d_uhat, P->d_chat_part, R * TS * kst, R, TS * kst, st);
 }
 
@@ -784,24 +813,45 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
     launch_gemm_nt(P->d_f2, kcst, P->d_t, kcst, P->d_leaves, uL, nst, P->d_leaves, nleaves, nst, kcst,
                    (float)P->tree->radius(L), 0, st, R, (long long)SL * kcst, TS * nst);
     P->stage_end(KIFMM_STAGE_UC2E, st);
-    // (1b) U2U, child level l -> parent level l - 1, down to level 2.
-    P->stage_begin(KIFMM_STAGE_M2M, st);
+    // (1b) U2U, (2a) compression and VLI.  The leaf level's VLI needs only the
+    // leaf level's compressed densities, so with a second plan stream the levels
+    // above it (U2U to level 2, their compression and their VLI) run there,
+    // beside the leaf level's VLI, and are joined before the partial sums.
+    const bool up = P->up != nullptr;
+    const int n_upper = P->n_nonempty - (int)P->keys_per_level[L];  // non-empty rows of levels 2..L-1
+    hipStream_t su = up ? P->up : st;
+    if (up) {
+      hip_check(hipEventRecord(P->ev_up0, st), "hipEventRecord");
+      hip_check(hipStreamWaitEvent(su, P->ev_up0, 0), "hipStreamWaitEvent");
+    }
+    P->stage_begin(KIFMM_STAGE_M2M, su);
     for (int l = L; l >= 3; --l) {
       const int parents = (int)P->keys_per_level[l - 1];
       launch_gemm_nt(P->d_m2m, 8 * nst, P->d_u + P->base[l] * nst, 8 * nst, nullptr, P->d_u + P->base[l - 1] * nst,
-                     nst, P->d_nbslot[l - 1], parents, nst, 8 * nst, 1.0f, 0, st, R, TS * nst, TS * nst);
+                     nst, P->d_nbslot[l - 1], parents, nst, 8 * nst, 1.0f, 0, su, R, TS * nst, TS * nst);
     }
-    P->stage_end(KIFMM_STAGE_M2M, st);
-    // (2a) VLI: compress, translate with the shared cores, all levels at once.
-    P->stage_begin(KIFMM_STAGE_COMPRESS, st);
+    if (up) {
+      // compression and VLI of the levels above the leaves
+      launch_gemm_nt(P->d_vt, nst, P->d_u, nst, P->d_nonempty, P->d_uhat, kst, P->d_nonempty, n_upper, kst, nst, 1.0f,
+                     0, su, R, TS * nst, TS * kst, P->m2l_wide ? 1 : 0);
+      if (!launch_m2l_form(P, su, 2)) fail(KIFMM_E_DEVICE, "M2L kernel configuration not available");
+    }
+    P->stage_end(KIFMM_STAGE_M2M, su);
+    if (up) hip_check(hipEventRecord(P->ev_up1, su), "hipEventRecord");
     // (empty boxes keep uhat = 0 from allocation: their rows are never written)
-    launch_gemm_nt(P->d_vt, nst, P->d_u, nst, P->d_nonempty, P->d_uhat, kst, P->d_nonempty, P->n_nonempty, kst, nst,
-                   1.0f, 0, st, R, TS * nst, TS * kst, P->m2l_wide ? 1 : 0);
+    P->stage_begin(KIFMM_STAGE_COMPRESS, st);
+    if (up)
+      launch_gemm_nt(P->d_vt, nst, P->d_u, nst, P->d_nonempty + n_upper, P->d_uhat, kst, P->d_nonempty + n_upper,
+                     P->n_nonempty - n_upper, kst, nst, 1.0f, 0, st, R, TS * nst, TS * kst, P->m2l_wide ? 1 : 0);
+    else
+      launch_gemm_nt(P->d_vt, nst, P->d_u, nst, P->d_nonempty, P->d_uhat, kst, P->d_nonempty, P->n_nonempty, kst, nst,
+                     1.0f, 0, st, R, TS * nst, TS * kst, P->m2l_wide ? 1 : 0);
     P->stage_end(KIFMM_STAGE_COMPRESS, st);
     P->stage_begin(KIFMM_STAGE_M2L, st);
-    const bool m2l_ok = launch_m2l_form(P, st);
+    const bool m2l_ok = launch_m2l_form(P, st, up ? 1 : 0);
     if (!m2l_ok) fail(KIFMM_E_DEVICE, "M2L kernel configuration not available");
     P->stage_end(KIFMM_STAGE_M2L, st);
+    if (up) hip_check(hipStreamWaitEvent(st, P->ev_up1, 0), "hipStreamWaitEvent");
     // (2c) sum of the M2L partial sums, post (DC2E U_k) and D2D, coarse to fine.
     P->stage_begin(KIFMM_STAGE_L2L, st);
     if (!P->m2l_wide && !P->m2l_gather) launch_sum_parts(P->d_chat_part, P->d_chat, R * TS * kst, R * TS * kst, st);

@@ -25,6 +25,8 @@ struct Plan : Object {
   int64_t total_slots = 0, n_leaves = 0;
   int64_t p2p_pairs = 0, m2l_pairs = 0, m2l_targets = 0;
   int m2l_rb = 0, core_rows = 0, n_items = 0, m2l_lds_ld = 0;
+  int n_items_leaf = 0;                  // the first n_items_leaf items target the leaf level
+  int64_t m2l_pairs_leaf = 0;            // V-list pairs with a leaf-level target
 
   std::vector<void*> owned;  // device allocations
   float4* d_pts = nullptr;
@@ -58,6 +60,8 @@ struct Plan : Object {
   static constexpr int kRing = 128;
   hipStream_t side = nullptr;            // ULI stream (default priority)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t up = nullptr;              // levels above the leaves: U2U, compression, VLI (default priority)
+  hipEvent_t ev_up0 = nullptr, ev_up1 = nullptr;
   float4* d_near = nullptr;              // ULI result in sorted order (phi, grad)
   bool m2l_wide = false;                 // nrhs = 32, FP32: per-target V lists with the right-hand sides as columns
   bool m2l_gather = false;               // one right-hand side, FP32: gathered form (targets as columns)
@@ -65,7 +69,7 @@ struct Plan : Object {
   int* d_gent_src = nullptr;             //   32 source rows of uhat per entry (zero row = total_slots)
   int* d_gtgt = nullptr;                 //   32 target slots per group (-1 = none)
   int4* d_gunits = nullptr;              //   (group, row block, first entry, end entry)
-  int n_gunits = 0;
+  int n_gunits = 0, n_gunits_leaf = 0;   //   the first n_gunits_leaf units target the leaf level
   double m2l_tune_ms[2] = {0.0, 0.0};    // autotuned M2L forms: blocked, gathered (ms per launch)
   int2* d_vlist = nullptr;               // (core index, source slot) per V-list entry, grouped by target
   int4* d_units = nullptr;               // (target slot, row block, first entry, end entry)
@@ -92,7 +96,7 @@ struct Plan : Object {
 
 Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device);
 void evaluate_plan(Plan* plan, const float* charges, float* pot, float* grad, hipStream_t st);
-bool launch_m2l_form(Plan* plan, hipStream_t st);
+bool launch_m2l_form(Plan* plan, hipStream_t st, int part);
 void evaluate_vjp(Plan* plan, const float* charges, const float* weights, const float* field, float* grad_charges,
                   float* grad_points, hipStream_t st);
 void read_density(Plan* plan, int kind, int level, float* out, int64_t capacity);
