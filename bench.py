@@ -289,8 +289,10 @@ def main():
     # run beside it on the plan's second stream)
     m2l_flop = 2.0 * k * k * stats["m2l_stage_pairs"] * R
     m2l_tflops = m2l_flop / (m2l_ms * 1e-3) / 1e12
-    m2l_kernel = (f"k_m2l_bf16<{passes // 3 + 1}>" if bf16 else
-                  ["k_m2l", "k_m2l_gather", "k_m2l_wide", "k_m2l_bf16"][stats["m2l_form"]])
+    # the KIFMM_STAGE_M2L launch (instance 0; the levels above the leaves, when they run on the
+    # plan's second stream, are instance 1)
+    m2l_kernel = (f"k_m2l_bf16<{passes // 3 + 1}, 0>" if bf16 else
+                  ["k_m2l<0>", "k_m2l_gather<0>", "k_m2l_wide", "k_m2l_bf16"][stats["m2l_form"]])
     traffic = load_traffic(w.name, m2l_kernel)
     # Leaf kernels: 20 FLOP per U-list pair (ULI) and per (target, downward-equivalent point) pair (D2T).
     # By default ULI runs on the plan's own stream beside the far field and D2T is a separate
@@ -326,6 +328,7 @@ def main():
                    "uli_overlap": not args.serial, "m2l": args.m2l, "hip_graph": args.graph,
                    "m2l_form": ["blocked", "gathered", "wide (32 right-hand sides)", "split bfloat16 blocked"][
                        stats["m2l_form"]],
+                   "upper_levels_on_second_stream": bool(stats["upper_stream"]),
                    "step": ("forward (potentials and field) + backward (vector-Jacobian product of "
                             "sum w_i f_i, w ~ N(0,1))") if args.backward else "evaluate"},
         "roofline": roofline,

@@ -242,6 +242,9 @@ __device__ __forceinline__ void m2l_slab(v16f* acc, v16f* tot, const float* alan
   }
 }
 
+// UPPER = 1 for the launch of the levels above the leaves that runs on a
+// second stream beside the leaf level's (same code; a name of its own in traces).
+template <int UPPER>
 __global__ __launch_bounds__(512) void k_m2l(const float* __restrict__ cores, int core_rows, int ldk, int ld4,
                                              const M2LItem* __restrict__ items, const int* __restrict__ tgt_blk,
                                              const int* __restrict__ src_blk, const int* __restrict__ pair_offs,
@@ -307,20 +310,23 @@ __global__ __launch_bounds__(512) void k_m2l(const float* __restrict__ cores, in
 
 bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int lds_ld, const M2LItem* items,
                 int nitems, const int* tgt_blk, const int* src_blk, const int* pair_offs, const float* uhat,
-                float* chat_part, long long part_stride, int nrhs, long long rhs_stride, hipStream_t s) {
+                float* chat_part, long long part_stride, int nrhs, long long rhs_stride, hipStream_t s, bool upper) {
   if (nitems <= 0 || nrhs <= 0) return true;
   if (row_blocks < 1 || row_blocks > 8 || (ldk & 7) || lds_ld < kM2LSlab || (lds_ld & 3)) return false;
   const size_t lds = (size_t)216 * lds_ld * sizeof(float);
-  static size_t attr = 0;
-  if (lds > attr) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds) != hipSuccess)
-      return false;
-    attr = lds;
-  }
-  hipLaunchKernelGGL(k_m2l, dim3(nitems, nrhs), dim3(64 * row_blocks), lds, s, cores, core_rows, ldk, lds_ld / 4,
-                     items, tgt_blk, src_blk, pair_offs, uhat, chat_part, part_stride, rhs_stride);
-  return true;
+  auto launch = [&](auto kernel, size_t& attr) {
+    if (lds > attr) {
+      if (hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds) != hipSuccess)
+        return false;
+      attr = lds;
+    }
+    hipLaunchKernelGGL(kernel, dim3(nitems, nrhs), dim3(64 * row_blocks), lds, s, cores, core_rows, ldk, lds_ld / 4,
+                       items, tgt_blk, src_blk, pair_offs, uhat, chat_part, part_stride, rhs_stride);
+    return true;
+  };
+  static size_t attr0 = 0, attr1 = 0;
+  return upper ? launch(&k_m2l<1>, attr1) : launch(&k_m2l<0>, attr0);
 }
 
 // ------------------------------------------------------ M2L, gathered ---
@@ -333,6 +339,7 @@ bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int 
 // items are mostly empty columns, keep full columns.  Operators in the lane
 // order of k_m2l; chat written once per target (no partial sums); accumulators
 // restarted every kM2LFlush entries (short FP32 chains).
+template <int UPPER>  // as in k_m2l
 __global__ __launch_bounds__(64) void k_m2l_gather(const float* __restrict__ cores, long long core_stride, int nch,
                                                    const int4* __restrict__ units, const int* __restrict__ ent_core,
                                                    const int* __restrict__ ent_src, const int* __restrict__ grp_tgt,
@@ -383,10 +390,14 @@ __global__ __launch_bounds__(64) void k_m2l_gather(const float* __restrict__ cor
 
 void launch_m2l_gather(const float* cores, long long core_stride, int ldk, const int4* units, int nunits,
                        const int* ent_core, const int* ent_src, const int* grp_tgt, const float* uhat, float* chat,
-                       hipStream_t s) {
+                       hipStream_t s, bool upper) {
   if (nunits <= 0) return;
-  hipLaunchKernelGGL(k_m2l_gather, dim3(nunits), dim3(64), 0, s, cores, core_stride, ldk / 8, units, ent_core,
-                     ent_src, grp_tgt, uhat, chat, ldk);
+  if (upper)
+    hipLaunchKernelGGL(k_m2l_gather<1>, dim3(nunits), dim3(64), 0, s, cores, core_stride, ldk / 8, units, ent_core,
+                       ent_src, grp_tgt, uhat, chat, ldk);
+  else
+    hipLaunchKernelGGL(k_m2l_gather<0>, dim3(nunits), dim3(64), 0, s, cores, core_stride, ldk / 8, units, ent_core,
+                       ent_src, grp_tgt, uhat, chat, ldk);
 }
 
 // -------------------------------------------------- M2L, 32 right-hand sides ---
@@ -514,7 +525,10 @@ __device__ __forceinline__ void m2lb_compute(const M2LRegsB<NP>& r, v16f* acc, v
   constexpr int kTerms = NP == 2 ? 3 : 6;
   constexpr int kPa[6] = {0, 0, 1, 0, 1, 2};
   constexpr int kPb[6] = {0, 1, 0, 2, 1, 0};
-  if (r.first) m2l_flush(acc, tot);  // short FP32 chains, as in k_m2l
+  // Short FP32 chains, as in k_m2l, for the three-piece form (whose products are as
+  // accurate as FP32's); the two-piece form's error is that of its split, and the
+  // registers of a second accumulator would cost it occupancy.
+  if (NP == 3 && r.first) m2l_flush(acc, tot);
 #pragma unroll
   for (int t = 0; t < kTerms; ++t)
 #pragma unroll
@@ -567,7 +581,7 @@ __device__ __forceinline__ void split8(const float4& u, const float4& v, uint4* 
   }
 }
 
-template <int NP>
+template <int NP, int UPPER>  // UPPER as in k_m2l
 __global__ __launch_bounds__(512) void k_m2l_bf16(const uint4* __restrict__ cores, size_t core_stride, int ldk,
                                                   int ld16, const M2LItem* __restrict__ items,
                                                   const int* __restrict__ tgt_blk, const int* __restrict__ src_blk,
@@ -642,7 +656,7 @@ int m2l_bf16_lds_ld16(int pieces) { return 4 * pieces + 1; }
 bool launch_m2l_bf16(int pieces, int row_blocks, const uint16_t* cores, size_t core_stride16, int ldk, int lds_ld16,
                      const M2LItem* items, int nitems, const int* tgt_blk, const int* src_blk, const int* pair_offs,
                      const float* uhat, float* chat_part, long long part_stride, int nrhs, long long rhs_stride,
-                     hipStream_t s) {
+                     hipStream_t s, bool upper) {
   if (nitems <= 0 || nrhs <= 0) return true;
   if (row_blocks < 1 || row_blocks > 8 || (ldk & 15) || (pieces != 2 && pieces != 3) ||
       lds_ld16 < m2l_bf16_lds_ld16(pieces))
@@ -660,8 +674,9 @@ bool launch_m2l_bf16(int pieces, int row_blocks, const uint16_t* cores, size_t c
                        pair_offs, uhat, chat_part, part_stride, rhs_stride);
     return true;
   };
-  static size_t attr2 = 0, attr3 = 0;
-  return pieces == 2 ? launch(&k_m2l_bf16<2>, attr2) : launch(&k_m2l_bf16<3>, attr3);
+  static size_t attr[2][2] = {{0, 0}, {0, 0}};
+  if (pieces == 2) return upper ? launch(&k_m2l_bf16<2, 1>, attr[0][1]) : launch(&k_m2l_bf16<2, 0>, attr[0][0]);
+  return upper ? launch(&k_m2l_bf16<3, 1>, attr[1][1]) : launch(&k_m2l_bf16<3, 0>, attr[1][0]);
 }
 
 // Sum of the eight source positions' partial sums, in a fixed order:

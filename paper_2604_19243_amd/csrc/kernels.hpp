@@ -25,9 +25,10 @@ void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int*
                     long long xbs = 0, long long ybs = 0, int ywide = 0);
 // Returns false if no kernel instance fits (rb, ldk).
 // nrhs right-hand sides: uhat and each partial sum advance by rhs_stride floats per right-hand side.
+// upper: the launch for the levels above the leaves (a kernel instance of its own name).
 bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int lds_ld, const M2LItem* items, int nitems,
                 const int* tgt_blk, const int* src_blk, const int* pair_offs, const float* uhat, float* chat_part,
-                long long part_stride, int nrhs, long long rhs_stride, hipStream_t s);
+                long long part_stride, int nrhs, long long rhs_stride, hipStream_t s, bool upper = false);
 // The same translation from split-bfloat16 pieces (2 pieces: three matrix-core
 // passes; 3 pieces: six): cores are [316][row block][16-k chunk][piece][64
 // lanes][8] bfloat16 bit patterns; core_stride16 is the size of one offset's
@@ -36,7 +37,7 @@ int m2l_bf16_lds_ld16(int pieces);
 bool launch_m2l_bf16(int pieces, int row_blocks, const uint16_t* cores, size_t core_stride16, int ldk, int lds_ld16,
                      const M2LItem* items, int nitems, const int* tgt_blk, const int* src_blk, const int* pair_offs,
                      const float* uhat, float* chat_part, long long part_stride, int nrhs, long long rhs_stride,
-                     hipStream_t s);
+                     hipStream_t s, bool upper = false);
 // M2L for 32 right-hand sides: units (target slot, row block, first, end V-list entry);
 // vlist entries (core index, source slot); uhat in the lane order written by
 // launch_gemm_nt(ywide); chat [32][slots][ldk] (chat_rs = slots * ldk).
@@ -47,7 +48,7 @@ void launch_m2l_wide(const float* cores, long long core_stride, int ldk, const i
 // target slots per group (-1 = none); chat [slots][ldk].
 void launch_m2l_gather(const float* cores, long long core_stride, int ldk, const int4* units, int nunits,
                        const int* ent_core, const int* ent_src, const int* grp_tgt, const float* uhat, float* chat,
-                       hipStream_t s);
+                       hipStream_t s, bool upper = false);
 void launch_sum_parts(const float* part, float* chat, long long n, long long stride, hipStream_t s);
 // out[k][c] = w[k] fs[k][c] + s[k] fw[k][c] for k < n, c < 3.
 void launch_vjp_combine(const float* s, const float* w, const float* fs, const float* fw, float* out, int n,

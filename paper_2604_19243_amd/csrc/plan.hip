@@ -677,6 +677,41 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
       hip_check(hipMemset(P->d_chat, 0, sizeof(float) * (size_t)n_red), "chat reset");
       hip_check(hipDeviceSynchronize(), "M2L autotune");
     }
+    if (P->up) {
+      // Autotuning of the second stream: the levels above the leaves beside the leaf
+      // level's VLI pay off where U2U is latency-bound (few boxes per level) and cost
+      // L2 locality where the two VLI launches share the XCDs.  Whole evaluates of
+      // zero charges, each way: one warm-up and the best of two timed.
+      float *q = nullptr, *pot = nullptr, *grad = nullptr;
+      hip_check(hipMalloc(&q, sizeof(float) * (size_t)T.n), "autotune charges");
+      hip_check(hipMemset(q, 0, sizeof(float) * (size_t)T.n), "autotune charges");
+      hip_check(hipMalloc(&pot, sizeof(float) * (size_t)T.n), "autotune potentials");
+      if (flags & KIFMM_GRADIENT) hip_check(hipMalloc(&grad, 3 * sizeof(float) * (size_t)T.n), "autotune field");
+      hipEvent_t e0, e1;
+      hip_check(hipEventCreate(&e0), "hipEventCreate");
+      hip_check(hipEventCreate(&e1), "hipEventCreate");
+      for (int on = 0; on < 2; ++on) {
+        P->up_on = on == 1;
+        float best = 0.f;
+        for (int rep = 0; rep < 3; ++rep) {
+          hip_check(hipEventRecord(e0, nullptr), "hipEventRecord");
+          evaluate_plan(P, q, pot, grad, nullptr);
+          hip_check(hipEventRecord(e1, nullptr), "hipEventRecord");
+          hip_check(hipEventSynchronize(e1), "stream autotune");
+          float ms = 0.f;
+          hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+          if (rep == 1 || (rep > 1 && ms < best)) best = ms;
+        }
+        P->up_tune_ms[on] = best;
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      (void)hipFree(q);
+      (void)hipFree(pot);
+      if (grad) (void)hipFree(grad);
+      P->up_on = P->up_tune_ms[1] < P->up_tune_ms[0];
+      hip_check(hipDeviceSynchronize(), "stream autotune");
+    }
   } catch (...) {
     delete P;
     (void)hipSetDevice(prev);
@@ -741,7 +776,7 @@ bool launch_m2l_form(Plan* P, hipStream_t st, int part) {
     const int u0 = part == 2 ? P->n_gunits_leaf : 0;
     const int u1 = part == 1 ? P->n_gunits_leaf : P->n_gunits;
     launch_m2l_gather(P->d_cores, (long long)P->core_rows * kst, kst, P->d_gunits + u0, u1 - u0, P->d_gent_core,
-                      P->d_gent_src, P->d_gtgt, P->d_uhat, P->d_chat, st);
+                      P->d_gent_src, P->d_gtgt, P->d_uhat, P->d_chat, st, part == 2);
     return true;
   }
   const int i0 = part == 2 ? P->n_items_leaf : 0;
@@ -749,9 +784,10 @@ bool launch_m2l_form(Plan* P, hipStream_t st, int part) {
   if (P->m2l_pieces)
     return launch_m2l_bf16(P->m2l_pieces, P->m2l_rb, P->d_cores_b, P->core_stride16, kst,
                            m2l_bf16_lds_ld16(P->m2l_pieces), P->d_items + i0, i1 - i0, P->d_tgt_blk, P->d_src_blk,
-                           P->d_pair_offs, P->d_uhat, P->d_chat_part, R * TS * kst, R, TS * kst, st);
+                           P->d_pair_offs, P->d_uhat, P->d_chat_part, R * TS * kst, R, TS * kst, st, part == 2);
   return launch_m2l(P->m2l_rb, P->d_cores, P->core_rows, kst, P->m2l_lds_ld, P->d_items + i0, i1 - i0, P->d_tgt_blk,
-                    P->d_src_blk, P->d_pair_offs, P->d_uhat, P->d_chat_part, R * TS * kst, R, TS * kst, st);
+                    P->d_src_blk, P->d_pair_offs, P->d_uhat, P->d_chat_part, R * TS * kst, R, TS * kst, st,
+                    part == 2);
 }
 
 void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipStream_t st) {
@@ -817,7 +853,7 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
     // leaf level's compressed densities, so with a second plan stream the levels
     // above it (U2U to level 2, their compression and their VLI) run there,
     // beside the leaf level's VLI, and are joined before the partial sums.
-    const bool up = P->up != nullptr;
+    const bool up = P->up != nullptr && P->up_on;
     const int n_upper = P->n_nonempty - (int)P->keys_per_level[L];  // non-empty rows of levels 2..L-1
     hipStream_t su = up ? P->up : st;
     if (up) {

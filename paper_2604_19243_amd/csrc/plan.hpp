@@ -61,6 +61,8 @@ struct Plan : Object {
   hipStream_t side = nullptr;            // ULI stream (default priority)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipStream_t up = nullptr;              // levels above the leaves: U2U, compression, VLI (default priority)
+  bool up_on = true;                     // use it (timed against not using it at plan creation)
+  double up_tune_ms[2] = {0.0, 0.0};     // evaluate without / with the second stream (ms)
   hipEvent_t ev_up0 = nullptr, ev_up1 = nullptr;
   float4* d_near = nullptr;              // ULI result in sorted order (phi, grad)
   bool m2l_wide = false;                 // nrhs = 32, FP32: per-target V lists with the right-hand sides as columns
