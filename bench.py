@@ -41,17 +41,19 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic(workload, kernel):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, or None if stale/missing."""
+def load_traffic(workload, kernel, config):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, or None if stale, missing
+    or measured on another launch configuration (M2L rank, second stream)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
-            entry = json.load(f)[kernel][workload]
+            entries = json.load(f)[kernel][workload]
     except (OSError, KeyError, ValueError):
         return None
-    if entry.get("kernels_hip_sha256_16") != kernel_source_hash():
-        return None
-    return float(entry["hbm_bytes_per_launch"])
+    for entry in entries if isinstance(entries, list) else [entries]:
+        if entry.get("kernels_hip_sha256_16") == kernel_source_hash() and entry.get("config") == config:
+            return float(entry["hbm_bytes_per_launch"])
+    return None
 
 
 def cpu_baseline_worker(args):
@@ -74,13 +76,16 @@ def cpu_baseline_worker(args):
     acc = {"rel_l2_vs_direct_sampled": direct.rel_l2(gpu["phi"], ref), "direct_sample_targets": int(len(idx))}
     if "phi_fp32" in gpu:
         acc["fp32_rel_l2_vs_direct_sampled"] = direct.rel_l2(gpu["phi_fp32"], ref)
+    if "phi_rank" in gpu:
+        acc["rank_rel_l2_vs_direct_sampled"] = direct.rel_l2(gpu["phi_rank"], ref)
     if args.accuracy_only:
         print(json.dumps(acc), flush=True)
         return
 
     c, r = w.cube
     t = tree.Tree(x, w.depth, c, r)
-    ops = operators.Operators(w.p, eps_pinv=1e-7, m2l="compressed", eps_svd=1e-6)
+    rank = w.m2l_rank if args.m2l_rank is None else args.m2l_rank
+    ops = operators.Operators(w.p, eps_pinv=1e-7, m2l="compressed", eps_svd=1e-6, rank=rank or None)
     L = w.depth
     for l in range(2, L + 1):
         ops.compression(t.radius(l))          # operator setup, not timed (as on the GPU)
@@ -138,6 +143,12 @@ def main():
                     help="capture one step in a HIP graph (torch.cuda.graph) and time its replays")
     ap.add_argument("--m2l-form", choices=["auto", "blocked", "gathered"], default="auto",
                     help="one-RHS FP32 M2L form (auto: the faster, timed at plan creation)")
+    ap.add_argument("--upper-stream", choices=["auto", "on", "off"], default="auto",
+                    help="levels above the leaves on the plan's second stream (auto: timed at plan creation)")
+    ap.add_argument("--m2l-rank", type=int, default=None,
+                    help="M2L compression rank (default: the workload's; 0: singular values above 1e-6 sigma_max)")
+    ap.add_argument("--no-compare-rank", action="store_true",
+                    help="skip the second timing, at the default M2L rank, of a workload with a rank of its own")
     ap.add_argument("--compare-single", action="store_true",
                     help="with a multi-RHS workload: also time a one-RHS plan on the same tree and operators")
     ap.add_argument("--sample-leaves", type=int, default=24)
@@ -189,7 +200,9 @@ def main():
         flags = kifmm.KIFMM_POTENTIAL | kifmm.KIFMM_GRADIENT | (kifmm.KIFMM_SERIAL if args.serial else 0)
         flags |= kifmm.KIFMM_VJP if args.backward else 0
     m2l_flag |= {"auto": 0, "blocked": kifmm.KIFMM_M2L_BLOCKED, "gathered": kifmm.KIFMM_M2L_GATHER}[args.m2l_form]
-    f = kifmm.FMM(x, w.depth, w.p, cube=cube, eps_pinv=1e-7, eps_svd=1e-6, flags=flags | m2l_flag, nrhs=R)
+    m2l_flag |= {"auto": 0, "on": kifmm.KIFMM_UPPER_STREAM, "off": kifmm.KIFMM_NO_UPPER_STREAM}[args.upper_stream]
+    rank = w.m2l_rank if args.m2l_rank is None else args.m2l_rank
+    f = kifmm.FMM(x, w.depth, w.p, cube=cube, eps_pinv=1e-7, eps_svd=1e-6, rank=rank, flags=flags | m2l_flag, nrhs=R)
     t_setup = time.perf_counter() - t_setup
     info = kifmm.kifmm_ops_get_info(f.ops)
     stats = kifmm.kifmm_plan_get_stats(f.plan)
@@ -282,6 +295,19 @@ def main():
         fp32_form = {"ms_per_step": ms32, "m2l_ms": stages32["m2l"], "stages_ms": stages32,
                      "speedup_evaluate": ms32 / ms, "speedup_m2l": stages32["m2l"] / stages["m2l"]}
 
+    default_rank = None
+    phir_sample = None
+    if w.m2l_rank and args.m2l_rank is None and not args.no_compare_rank:
+        # the same evaluate with the M2L rank of the 1e-6 singular-value threshold
+        fr = kifmm.FMM(x, w.depth, w.p, cube=cube, eps_pinv=1e-7, eps_svd=1e-6, rank=0, flags=flags | m2l_flag,
+                       nrhs=R)
+        kr = kifmm.kifmm_ops_get_info(fr.ops)["rank_m2l"]
+        msr, stagesr = timed(fr.plan, f"m2l {args.m2l}, rank {kr}")
+        phir_sample = pot.cpu().numpy()[idx].astype(np.float64)
+        fr.close()
+        default_rank = {"m2l_rank": kr, "ms_per_step": msr, "value": w.n / (msr * 1e-3) / 1e6,
+                        "m2l_ms": stagesr["m2l"], "stages_ms": stagesr}
+
     # M2L (dominant kernel): 2 k^2 FLOP per (target, source) V-list pair; the split-bfloat16
     # forms execute each product as 3 or 6 bfloat16 products, counted against the BF16 peak.
     m2l_ms = stages["m2l"]
@@ -293,7 +319,7 @@ def main():
     # plan's second stream, are instance 1)
     m2l_kernel = (f"k_m2l_bf16<{passes // 3 + 1}, 0>" if bf16 else
                   ["k_m2l<0>", "k_m2l_gather<0>", "k_m2l_wide", "k_m2l_bf16"][stats["m2l_form"]])
-    traffic = load_traffic(w.name, m2l_kernel)
+    traffic = load_traffic(w.name, m2l_kernel, {"m2l_rank": k, "upper_levels_on_second_stream": bool(stats["upper_stream"])})
     # Leaf kernels: 20 FLOP per U-list pair (ULI) and per (target, downward-equivalent point) pair (D2T).
     # By default ULI runs on the plan's own stream beside the far field and D2T is a separate
     # kernel; with --serial one fused kernel does both.
@@ -344,6 +370,8 @@ def main():
     }
     if fp32_form is not None:
         result["fp32_form"] = fp32_form
+    if default_rank is not None:
+        result["default_rank"] = default_rank
     if R > 1:
         result["point_rhs_per_s"] = w.n * R / (ms * 1e-3)
     if single is not None:
@@ -354,12 +382,14 @@ def main():
     with tempfile.TemporaryDirectory() as tmp:
         path = os.path.join(tmp, "gpu_sample.npz")
         extra = {"phi_fp32": phi32_sample} if fp32_form is not None else {}
+        if phir_sample is not None:
+            extra["phi_rank"] = phir_sample
         np.savez(path, idx=idx, phi=phi_sample, **extra)
         env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
         print("# oracle leg (1 thread)...", file=sys.stderr, flush=True)
         cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker", "--workload", w.name,
                "--sample-leaves", str(args.sample_leaves), "--sample-seed", str(args.sample_seed),
-               "--gpu-sample", path] + (["--accuracy-only"] if args.no_cpu_baseline else [])
+               "--m2l-rank", str(rank), "--gpu-sample", path] + (["--accuracy-only"] if args.no_cpu_baseline else [])
         r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=900)
         if r.returncode == 0:
             cb = json.loads(r.stdout.strip().splitlines()[-1])
@@ -367,6 +397,8 @@ def main():
             result["direct_sample_targets"] = cb.pop("direct_sample_targets")
             if "fp32_rel_l2_vs_direct_sampled" in cb:
                 result["fp32_form"]["rel_l2_vs_direct_sampled"] = cb.pop("fp32_rel_l2_vs_direct_sampled")
+            if "rank_rel_l2_vs_direct_sampled" in cb:
+                result["default_rank"]["rel_l2_vs_direct_sampled"] = cb.pop("rank_rel_l2_vs_direct_sampled")
             if not args.no_cpu_baseline:
                 result["cpu_baseline"] = cb
         else:

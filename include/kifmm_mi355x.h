@@ -190,6 +190,15 @@ kifmm_status kifmm_ops_destroy(kifmm_ops ops);
  * (stats[7] reports the choice); these flags force one. */
 #define KIFMM_M2L_BLOCKED 64u
 #define KIFMM_M2L_GATHER 128u
+/* A one-RHS plan that is not KIFMM_SERIAL and has depth >= 3 can run the
+ * levels above the leaves (U2U, their compression and VLI) on a second plan
+ * stream beside the leaf level's VLI.  By default kifmm_plan_create times
+ * evaluates both ways and keeps the faster (stats[9] reports the choice);
+ * KIFMM_UPPER_STREAM forces the second stream, KIFMM_NO_UPPER_STREAM forbids
+ * it (at most one of the two; either is ignored where the second stream does
+ * not apply). */
+#define KIFMM_UPPER_STREAM 256u
+#define KIFMM_NO_UPPER_STREAM 512u
 
 /*
  * Place a tree and its operators on HIP device `device`: uploads the sorted

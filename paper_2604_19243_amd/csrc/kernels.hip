@@ -151,7 +151,9 @@ struct M2LRegs {
 
 extern __shared__ float4 s_m2l[];  // [216][ld4] float4: the current k-slab of the staged sources
 
-constexpr int kM2LSlab = 40;  // k per LDS slab: 5 chunks of 8; the row stride 44 is an odd number of float4
+// A slab holds 4 (ld4 - 1) k of each staged row (a multiple of 8); the row
+// stride ld4 is an odd number of float4, so lanes reading different rows
+// spread over the LDS banks.
 
 // The contribution of each group of kM2LFlush offsets over a slab is
 // accumulated from zero and added into the running total when the next group
@@ -278,8 +280,9 @@ __global__ __launch_bounds__(512) void k_m2l(const float* __restrict__ cores, in
   const size_t core_stride = (size_t)core_rows * ldk;
   const int* srcs = src_blk + it.src_base;
 
-  for (int k0 = 0; k0 < ldk; k0 += kM2LSlab) {
-    const int kw = min(kM2LSlab, ldk - k0);  // slab width, a multiple of 8
+  const int slab = 4 * (ld4 - 1);
+  for (int k0 = 0; k0 < ldk; k0 += slab) {
+    const int kw = min(slab, ldk - k0);  // slab width, a multiple of 8
     const int w4 = kw >> 2;
     if (k0) __syncthreads();  // previous slab fully consumed
     for (int idx = tid; idx < 216 * w4; idx += blockDim.x) {
@@ -312,7 +315,8 @@ bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int 
                 int nitems, const int* tgt_blk, const int* src_blk, const int* pair_offs, const float* uhat,
                 float* chat_part, long long part_stride, int nrhs, long long rhs_stride, hipStream_t s, bool upper) {
   if (nitems <= 0 || nrhs <= 0) return true;
-  if (row_blocks < 1 || row_blocks > 8 || (ldk & 7) || lds_ld < kM2LSlab || (lds_ld & 3)) return false;
+  // lds_ld = slab + 4 floats, the slab a multiple of 8 k
+  if (row_blocks < 1 || row_blocks > 8 || (ldk & 7) || lds_ld < 12 || ((lds_ld - 4) & 7)) return false;
   const size_t lds = (size_t)216 * lds_ld * sizeof(float);
   auto launch = [&](auto kernel, size_t& attr) {
     if (lds > attr) {

@@ -84,13 +84,16 @@ Plan::~Plan() {
 Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
   require(tree && ops, "null tree or ops");
   require((flags & ~(KIFMM_POTENTIAL | KIFMM_GRADIENT | KIFMM_SERIAL | KIFMM_M2L_BF16X3 | KIFMM_M2L_BF16X6 |
-                     KIFMM_VJP | KIFMM_M2L_BLOCKED | KIFMM_M2L_GATHER)) == 0 &&
+                     KIFMM_VJP | KIFMM_M2L_BLOCKED | KIFMM_M2L_GATHER | KIFMM_UPPER_STREAM |
+                     KIFMM_NO_UPPER_STREAM)) == 0 &&
               (flags & (KIFMM_POTENTIAL | KIFMM_GRADIENT)) != 0,
-          "flags must hold POTENTIAL and/or GRADIENT, optionally SERIAL, VJP and one of M2L_BF16X3, M2L_BF16X6");
+          "flags must hold POTENTIAL and/or GRADIENT plus only the documented KIFMM_ flags");
   require(!((flags & KIFMM_M2L_BF16X3) && (flags & KIFMM_M2L_BF16X6)), "M2L_BF16X3 and M2L_BF16X6 exclude each other");
   require(nrhs == 1 || nrhs == 2 || nrhs == 4 || nrhs == 8 || nrhs == 16 || nrhs == 32,
           "nrhs must be 1, 2, 4, 8, 16 or 32");
   require(!((flags & KIFMM_M2L_BLOCKED) && (flags & KIFMM_M2L_GATHER)), "M2L_BLOCKED and M2L_GATHER exclude each other");
+  require(!((flags & KIFMM_UPPER_STREAM) && (flags & KIFMM_NO_UPPER_STREAM)),
+          "UPPER_STREAM and NO_UPPER_STREAM exclude each other");
   require(!(flags & KIFMM_M2L_GATHER) || (nrhs == 1 && !(flags & (KIFMM_M2L_BF16X3 | KIFMM_M2L_BF16X6))),
           "M2L_GATHER needs one right-hand side and the FP32 M2L");
   require(nrhs == 1 || !(flags & (KIFMM_GRADIENT | KIFMM_VJP)),
@@ -486,9 +489,24 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
       P->m2l_pairs_leaf = vpairs_leaf;
       P->m2l_targets = ntargets;
       P->n_items = (int)items.size();
-      // LDS row stride of one 40-k slab of the staged sources: 44 floats, an odd
-      // number of 16-byte units, so lanes reading different rows spread over the banks.
-      P->m2l_lds_ld = 44;
+      // k per LDS slab of the staged sources (row stride slab + 4 floats, an odd
+      // number of 16-byte units): the most resident waves per CU first (at most
+      // 16 for the kernel's register use; rb waves per workgroup, 216 rows of
+      // LDS each), then the fewest slabs.
+      {
+        int best_slab = 0, best_waves = -1, best_n = 0;
+        for (int slab = 24; slab <= 48; slab += 8) {
+          const int lds = 216 * (slab + 4) * 4;
+          const int waves = std::min(16 / P->m2l_rb, (160 * 1024) / lds) * P->m2l_rb;
+          const int n = (P->kst + slab - 1) / slab;
+          if (waves > best_waves || (waves == best_waves && n < best_n)) {
+            best_slab = slab;
+            best_waves = waves;
+            best_n = n;
+          }
+        }
+        P->m2l_lds_ld = best_slab + 4;
+      }
       require(P->m2l_rb <= 8, "M2L rank too large for the M2L kernel (k <= 256)");
       P->d_tgt_blk = dev_upload(own, tgt_blk.data(), tgt_blk.size(), "m2l block targets");
       P->d_src_blk = dev_upload(own, src_blk.data(), src_blk.size(), "m2l block sources");
@@ -632,7 +650,7 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
       P->n_tasks = (int)(tk.size() / 4);
       if (P->n_tasks) P->d_tasks = reinterpret_cast<int4*>(dev_upload(own, tk.data(), tk.size(), "leaf tasks"));
     }
-    if (P->far && !(flags & KIFMM_SERIAL) && nrhs == 1 && L >= 3) {
+    if (P->far && !(flags & (KIFMM_SERIAL | KIFMM_NO_UPPER_STREAM)) && nrhs == 1 && L >= 3) {
       // the levels above the leaves run on a second plan stream (default priority)
       hip_check(hipStreamCreateWithFlags(&P->up, hipStreamNonBlocking), "hipStreamCreate");
       hip_check(hipEventCreateWithFlags(&P->ev_up0, hipEventDisableTiming), "hipEventCreate");
@@ -677,7 +695,9 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
       hip_check(hipMemset(P->d_chat, 0, sizeof(float) * (size_t)n_red), "chat reset");
       hip_check(hipDeviceSynchronize(), "M2L autotune");
     }
-    if (P->up) {
+    if (P->up && (flags & KIFMM_UPPER_STREAM)) {
+      P->up_on = true;
+    } else if (P->up) {
       // Autotuning of the second stream: the levels above the leaves beside the leaf
       // level's VLI pay off where U2U is latency-bound (few boxes per level) and cost
       // L2 locality where the two VLI launches share the XCDs.  Whole evaluates of

@@ -31,6 +31,8 @@ KIFMM_M2L_BF16X6 = 16
 KIFMM_VJP = 32
 KIFMM_M2L_BLOCKED = 64
 KIFMM_M2L_GATHER = 128
+KIFMM_UPPER_STREAM = 256
+KIFMM_NO_UPPER_STREAM = 512
 
 (KIFMM_OP_SURFACE, KIFMM_OP_UC2E, KIFMM_OP_DC2E, KIFMM_OP_M2M, KIFMM_OP_L2L, KIFMM_OP_M2L_U, KIFMM_OP_M2L_V,
  KIFMM_OP_M2L_CORE, KIFMM_OP_M2L_OFFSET, KIFMM_OP_M2L_POST) = range(10)

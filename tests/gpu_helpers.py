@@ -19,14 +19,14 @@ M2L_FLAGS = {"fp32": 0, "bf16x3": kifmm.KIFMM_M2L_BF16X3, "bf16x6": kifmm.KIFMM_
 
 
 def gpu_evaluate(points, charges, depth, p, cube, eps_svd=1e-6, rank=0, gradient=True, fmm_obj=None, serial=False,
-                 m2l="fp32"):
+                 m2l="fp32", flags=0):
     """HIP path: returns (phi [n] or [n,R], grad [n,3] or None, FMM object) as float64 numpy arrays.
-    charges [n] or [n, R] (R right-hand sides: potentials only)."""
+    charges [n] or [n, R] (R right-hand sides: potentials only); `flags`: further plan flags."""
     import torch
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     nrhs = 1 if np.ndim(charges) == 1 else np.shape(charges)[1]
-    flags = kifmm.KIFMM_POTENTIAL | (kifmm.KIFMM_GRADIENT if gradient else 0)
-    flags |= (kifmm.KIFMM_SERIAL if serial else 0) | M2L_FLAGS[m2l]
+    flags |= (kifmm.KIFMM_POTENTIAL | (kifmm.KIFMM_GRADIENT if gradient else 0) | (kifmm.KIFMM_SERIAL if serial else 0)
+              | M2L_FLAGS[m2l])
     f = fmm_obj or kifmm.FMM(points, depth, p, cube=cube, eps_svd=eps_svd, rank=rank, flags=flags, nrhs=nrhs)
     dev = torch.device("cuda:0")
     s = torch.from_numpy(np.ascontiguousarray(charges, dtype=np.float32)).to(dev)

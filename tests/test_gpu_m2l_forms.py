@@ -18,25 +18,26 @@ UNIT = (0.5, 0.5, 0.5, 0.5)
 SPHERE = (0.0, 0.0, 0.0, 1.0)
 
 
-@pytest.mark.parametrize("name,n,depth,p,dist,charges", [
-    ("cube20k_p6_d3", 20_000, 3, 6, "cube", "uniform01"),
-    ("sphere", 30_000, 5, 6, "sphere", "normal"),       # sparse: the gathered form's case
-    ("ragged", 7_777, 4, 5, "cube", "uniform11"),
-    ("sparse_deep", 2_000, 6, 4, "cube", "uniform01"),
-    ("p8", 8_000, 3, 8, "cube", "uniform11"),
+@pytest.mark.parametrize("name,n,depth,p,dist,charges,rank", [
+    ("cube20k_p6_d3", 20_000, 3, 6, "cube", "uniform01", 0),
+    ("sphere", 30_000, 5, 6, "sphere", "normal", 0),       # sparse: the gathered form's case
+    ("ragged", 7_777, 4, 5, "cube", "uniform11", 0),
+    ("sparse_deep", 2_000, 6, 4, "cube", "uniform01", 0),
+    ("p8", 8_000, 3, 8, "cube", "uniform11", 0),
+    ("sphere_rank94", 30_000, 5, 6, "sphere", "normal", 94),  # three 32-row blocks
 ])
-def test_gathered_m2l_parity_with_oracle(name, n, depth, p, dist, charges):
-    log(f"gathered M2L parity {name} n={n} depth={depth} p={p}")
+def test_gathered_m2l_parity_with_oracle(name, n, depth, p, dist, charges, rank):
+    log(f"gathered M2L parity {name} n={n} depth={depth} p={p} rank={rank}")
     x = workloads.points(dist, n, 1001 if name.startswith("cube20k") else 610 + n)
     s = workloads.charges(charges, n, 2001 if name.startswith("cube20k") else 620 + n)
     cube = UNIT if dist == "cube" else SPHERE
-    phi, g, f = gpu_evaluate(x, s, depth, p, cube, m2l="gather")
+    phi, g, f = gpu_evaluate(x, s, depth, p, cube, m2l="gather", rank=rank)
     assert kifmm.kifmm_plan_get_stats(f.plan)["m2l_form"] == 1
     f.close()
-    phb, gb, f = gpu_evaluate(x, s, depth, p, cube, m2l="blocked")
+    phb, gb, f = gpu_evaluate(x, s, depth, p, cube, m2l="blocked", rank=rank)
     assert kifmm.kifmm_plan_get_stats(f.plan)["m2l_form"] == 0
     f.close()
-    rphi, rg, _, _ = oracle_evaluate(x, s, depth, p, cube)
+    rphi, rg, _, _ = oracle_evaluate(x, s, depth, p, cube, rank=rank or None)
     e, eg = rel_l2(phi, rphi), rel_l2(g, rg)
     d = rel_l2(phi, phb)
     log(f"  gathered rel-L2 phi {e:.3e} grad {eg:.3e}; vs blocked {d:.3e}")
@@ -65,3 +66,24 @@ def test_m2l_form_flag_errors():
         kifmm.FMM(x, 3, 4, cube=UNIT, flags=kifmm.KIFMM_POTENTIAL | kifmm.KIFMM_M2L_GATHER | kifmm.KIFMM_M2L_BF16X3)
     with pytest.raises(kifmm.KifmmError):
         kifmm.FMM(x, 3, 4, cube=UNIT, flags=kifmm.KIFMM_POTENTIAL | kifmm.KIFMM_M2L_GATHER, nrhs=4)
+
+
+@pytest.mark.parametrize("rank", [0, 94])
+def test_upper_levels_stream_flags(rank):
+    # The levels above the leaves on the plan's second stream (forced on) or on the
+    # caller's stream (forced off): the same kernels on the same data, so the same bits.
+    log(f"upper-level stream on/off rank={rank}")
+    x = workloads.points("cube", 40_000, 71)
+    s = workloads.charges("uniform11", 40_000, 72)
+    out = {}
+    for name, fl in (("on", kifmm.KIFMM_UPPER_STREAM), ("off", kifmm.KIFMM_NO_UPPER_STREAM)):
+        phi, g, f = gpu_evaluate(x, s, 4, 6, UNIT, rank=rank, m2l="blocked", flags=fl)
+        assert kifmm.kifmm_plan_get_stats(f.plan)["upper_stream"] == (1 if name == "on" else 0)
+        f.close()
+        out[name] = (phi, g)
+    np.testing.assert_array_equal(out["on"][0], out["off"][0])
+    np.testing.assert_array_equal(out["on"][1], out["off"][1])
+    rphi, rg, _, _ = oracle_evaluate(x, s, 4, 6, UNIT, rank=rank or None)
+    e, eg = rel_l2(out["on"][0], rphi), rel_l2(out["on"][1], rg)
+    log(f"  rel-L2 phi {e:.3e} grad {eg:.3e}")
+    assert e < TOL and eg < TOL

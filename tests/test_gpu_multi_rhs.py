@@ -25,23 +25,24 @@ def _charges(n, R, seed):
     return rng.standard_normal((n, R)).astype(np.float32)
 
 
-@pytest.mark.parametrize("name,n,depth,p,dist,R,m2l", [
-    ("cube20k_p6_d3", 20_000, 3, 6, "cube", 4, "fp32"),
-    ("cube20k_p6_d3_r32", 20_000, 3, 6, "cube", 32, "fp32"),
-    ("sphere_r8", 30_000, 4, 6, "sphere", 8, "fp32"),
-    ("ragged_r2", 7_777, 4, 5, "cube", 2, "fp32"),
-    ("sparse_deep_r16", 2_000, 5, 4, "cube", 16, "fp32"),
-    ("cube20k_r4_bf16x6", 20_000, 3, 6, "cube", 4, "bf16x6"),
+@pytest.mark.parametrize("name,n,depth,p,dist,R,m2l,rank", [
+    ("cube20k_p6_d3", 20_000, 3, 6, "cube", 4, "fp32", 0),
+    ("cube20k_p6_d3_r32", 20_000, 3, 6, "cube", 32, "fp32", 0),
+    ("sphere_r8", 30_000, 4, 6, "sphere", 8, "fp32", 0),
+    ("ragged_r2", 7_777, 4, 5, "cube", 2, "fp32", 0),
+    ("sparse_deep_r16", 2_000, 5, 4, "cube", 16, "fp32", 0),
+    ("cube20k_r4_bf16x6", 20_000, 3, 6, "cube", 4, "bf16x6", 0),
+    ("sphere_r32_rank94", 30_000, 4, 6, "sphere", 32, "fp32", 94),   # wide M2L, three row blocks
 ])
-def test_multi_rhs_parity_with_oracle(name, n, depth, p, dist, R, m2l):
-    log(f"multi-RHS parity {name} n={n} depth={depth} p={p} R={R} {m2l}")
+def test_multi_rhs_parity_with_oracle(name, n, depth, p, dist, R, m2l, rank):
+    log(f"multi-RHS parity {name} n={n} depth={depth} p={p} R={R} {m2l} rank={rank}")
     x = workloads.points(dist, n, 1001 if name.startswith("cube20k") else 800 + n)
     s = _charges(n, R, 900 + n + R)
     cube = UNIT if dist == "cube" else SPHERE
-    phi, _, f = gpu_evaluate(x, s, depth, p, cube, gradient=False, m2l=m2l)
+    phi, _, f = gpu_evaluate(x, s, depth, p, cube, gradient=False, m2l=m2l, rank=rank)
     assert kifmm.kifmm_plan_get_stats(f.plan)["nrhs"] == R
     f.close()
-    rphi, _, _, _ = oracle_evaluate(x, s, depth, p, cube, gradient=False)
+    rphi, _, _, _ = oracle_evaluate(x, s, depth, p, cube, gradient=False, rank=rank or None)
     errs = [rel_l2(phi[:, r], rphi[:, r]) for r in range(R)]
     log(f"  rel-L2 per right-hand side: max {max(errs):.3e} mean {np.mean(errs):.3e}")
     assert max(errs) < TOL
@@ -101,12 +102,12 @@ def test_multi_rhs_full_size_batching_workload():
     x, s = workloads.make(w)
     assert s.shape == (w.n, 32)
     c = w.cube[0] + (w.cube[1],)
-    phi, _, f = gpu_evaluate(x, s, w.depth, w.p, c, gradient=False)
+    phi, _, f = gpu_evaluate(x, s, w.depth, w.p, c, gradient=False, rank=w.m2l_rank)
     f.close()
     assert np.isfinite(phi).all()
     single = None
     for r in (0, 31):
-        p1, _, single = gpu_evaluate(x, s[:, r], w.depth, w.p, c, gradient=False, fmm_obj=single)
+        p1, _, single = gpu_evaluate(x, s[:, r], w.depth, w.p, c, gradient=False, fmm_obj=single, rank=w.m2l_rank)
         e = rel_l2(phi[:, r], p1)
         log(f"  column {r}: rel-L2 vs single {e:.3e}")
         assert e < 1e-6

@@ -34,22 +34,25 @@ def test_shallow_tree_equals_direct_sum(depth, n):
     assert rel_l2(g, gref) < TOL
 
 
-@pytest.mark.parametrize("name,n,depth,p,dist,serial", [
-    ("cube20k_p6_d3", 20_000, 3, 6, "cube", False),   # the FP64 validation workload, full size
-    ("cube20k_p6_d3", 20_000, 3, 6, "cube", True),    # same, every kernel on the caller's stream
-    ("ragged", 7_777, 4, 5, "cube", False),           # ragged leaves and tiles, many boundary boxes
-    ("sphere", 30_000, 4, 6, "sphere", False),        # strongly non-uniform: most boxes empty
-    ("sparse_deep", 2_000, 5, 4, "cube", True),       # ~0.06 points per leaf
+@pytest.mark.parametrize("name,n,depth,p,dist,serial,rank", [
+    ("cube20k_p6_d3", 20_000, 3, 6, "cube", False, 0),   # the FP64 validation workload, full size
+    ("cube20k_p6_d3", 20_000, 3, 6, "cube", True, 0),    # same, every kernel on the caller's stream
+    ("ragged", 7_777, 4, 5, "cube", False, 0),           # ragged leaves and tiles, many boundary boxes
+    ("sphere", 30_000, 4, 6, "sphere", False, 0),        # strongly non-uniform: most boxes empty
+    ("sparse_deep", 2_000, 5, 4, "cube", True, 0),       # ~0.06 points per leaf
+    # rank 94 (the p = 6 benchmark rank): k padded to 96, three 32-row blocks, 32-k slabs
+    ("rank94", 40_000, 4, 6, "cube", False, 94),
+    ("rank94_sphere", 30_000, 4, 6, "sphere", False, 94),
 ])
-def test_parity_with_oracle(name, n, depth, p, dist, serial):
-    log(f"parity {name} n={n} depth={depth} p={p} serial={serial}")
+def test_parity_with_oracle(name, n, depth, p, dist, serial, rank):
+    log(f"parity {name} n={n} depth={depth} p={p} serial={serial} rank={rank}")
     x = workloads.points(dist, n, 1001 if name.startswith("cube20k") else 500 + n)
     s = workloads.charges("uniform01", n, 2001 if name.startswith("cube20k") else 600 + n)
     cube = UNIT if dist == "cube" else (0.0, 0.0, 0.0, 1.0)
-    phi, g, f = gpu_evaluate(x, s, depth, p, cube, serial=serial)
+    phi, g, f = gpu_evaluate(x, s, depth, p, cube, serial=serial, rank=rank)
     k = kifmm.kifmm_ops_get_info(f.ops)["rank_m2l"]
     f.close()
-    rphi, rg, _, ops = oracle_evaluate(x, s, depth, p, cube)
+    rphi, rg, _, ops = oracle_evaluate(x, s, depth, p, cube, rank=rank or None)
     assert ops.compression(1.0)[0].shape[1] == k
     e, eg = rel_l2(phi, rphi), rel_l2(g, rg)
     log(f"  rel-L2 phi {e:.3e} grad {eg:.3e} (k={k})")
@@ -82,9 +85,10 @@ def test_full_size_hot_path_sampled():
     log("full size cube1m_p6_d5")
     x, s = workloads.make(w)
     c = w.cube[0] + (w.cube[1],)
-    phi, g, f = gpu_evaluate(x, s, w.depth, w.p, c)
+    phi, g, f = gpu_evaluate(x, s, w.depth, w.p, c, rank=w.m2l_rank)
+    assert kifmm.kifmm_ops_get_info(f.ops)["rank_m2l"] == w.m2l_rank
     f.close()
-    phi_s, g_s, f = gpu_evaluate(x, s, w.depth, w.p, c, serial=True)
+    phi_s, g_s, f = gpu_evaluate(x, s, w.depth, w.p, c, rank=w.m2l_rank, serial=True)
     f.close()
     assert rel_l2(phi_s, phi) < 1e-7 and rel_l2(g_s, g) < 1e-7
     assert np.isfinite(phi).all() and np.isfinite(g).all()
@@ -93,7 +97,7 @@ def test_full_size_hot_path_sampled():
     leaves = {tuple(int(v) for v in rng.integers(0, m, 3)) for _ in range(20)}
     leaves |= {(0, 0, 0), (m - 1, m - 1, m - 1), (0, m - 1, 5), (m // 2, 0, m - 1)}
     leaves = sorted(leaves)
-    rphi, rg, t, _ = oracle_evaluate(x, s, w.depth, w.p, c, target_leaves=leaves)
+    rphi, rg, t, _ = oracle_evaluate(x, s, w.depth, w.p, c, rank=w.m2l_rank, target_leaves=leaves)
     idx = np.concatenate([t.leaf_points[b] for b in leaves if b in t.leaf_points])
     e, eg = rel_l2(phi[idx], rphi[idx]), rel_l2(g[idx], rg[idx])
     log(f"  sampled {len(idx)} points: rel-L2 phi {e:.3e} grad {eg:.3e}")

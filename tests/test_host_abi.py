@@ -170,6 +170,9 @@ def test_error_paths(lib):
         assert lib.kifmm_plan_create(t, o, 1, 1, -1, ctypes.byref(out)) in (kifmm.KIFMM_E_INVALID, kifmm.KIFMM_E_DEVICE)
         assert lib.kifmm_plan_create(t, o, 3, 1, 0, ctypes.byref(out)) == kifmm.KIFMM_E_INVALID
         assert lib.kifmm_plan_create(t, o, 4, 3, 0, ctypes.byref(out)) == kifmm.KIFMM_E_INVALID
+        both = kifmm.KIFMM_POTENTIAL | kifmm.KIFMM_UPPER_STREAM | kifmm.KIFMM_NO_UPPER_STREAM
+        assert lib.kifmm_plan_create(t, o, 1, both, 0, ctypes.byref(out)) == kifmm.KIFMM_E_INVALID
+        assert lib.kifmm_plan_create(t, o, 1, 1 | 1024, 0, ctypes.byref(out)) == kifmm.KIFMM_E_INVALID
     finally:
         kifmm.kifmm_ops_destroy(o)
         kifmm.kifmm_tree_destroy(t)
