@@ -355,6 +355,7 @@ def main():
                    "m2l_form": ["blocked", "gathered", "wide (32 right-hand sides)", "split bfloat16 blocked"][
                        stats["m2l_form"]],
                    "upper_levels_on_second_stream": bool(stats["upper_stream"]),
+                   "m2l_lds_slab": stats["m2l_lds_slab"],
                    "step": ("forward (potentials and field) + backward (vector-Jacobian product of "
                             "sum w_i f_i, w ~ N(0,1))") if args.backward else "evaluate"},
         "roofline": roofline,

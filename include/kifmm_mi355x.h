@@ -295,7 +295,10 @@ kifmm_status kifmm_plan_get_stage_times(kifmm_plan plan, double* ms, int64_t* co
  *   stats[8] = V-list pairs of the KIFMM_STAGE_M2L launch (the leaf level's
  *              alone when the levels above it run on the plan's second stream),
  *   stats[9] = 1 if the levels above the leaves run on the plan's second stream
- *              beside the leaf level's VLI (chosen by timing at plan creation) */
+ *              beside the leaf level's VLI (chosen by timing at plan creation),
+ *   stats[10] = k per LDS slab of the staged M2L sources in the blocked forms
+ *              (0 for the other forms).
+ * At most `count` entries are written. */
 kifmm_status kifmm_plan_get_stats(kifmm_plan plan, int64_t* stats, int count);
 
 /* Copy a level's densities to the host after the stream is idle, as float in

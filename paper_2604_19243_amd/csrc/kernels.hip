@@ -1,27 +1,48 @@
 // HIP kernels of the kiFMM evaluate for gfx950 (CDNA4).
 //
-// Dense contractions (check-to-equivalent factors, U2U, compression, U2D, post,
-// D2D) run on the FP32 matrix cores through v_mfma_f32_16x16x4_f32; the kernel
-// sums (S2U check fields, D2T and the U-list direct sum) run on the vector
-// ALUs.  All arithmetic is FP32.
+// Dense contractions run on the FP32 matrix cores: the check-to-equivalent
+// factors, U2U, compression, post and D2D through v_mfma_f32_16x16x4_f32, the
+// U2D translations (M2L) through v_mfma_f32_32x32x2_f32 (the split-bfloat16 M2L
+// through v_mfma_f32_32x32x16_bf16 with FP32 accumulation).  The kernel sums
+// (S2U check fields, D2T and the U-list direct sum) run on the vector ALUs.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
 
 namespace kifmm {
 
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// One 32x32x2 FP32 matrix-core step (wave64): lane (i, h) = (l % 32, l / 32)
+// holds A[i][h] and B[h][i]; the accumulator holds D[8 (v / 4) + 4 h + v % 4][i]
+// in element v.
+__device__ __forceinline__ v16f mfma32(float a, float b, v16f c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------- GEMM ---
+// Y[yrow(b)][o] = alpha * sum_k W[o][k] X[xrow(b)][k]  (+ Y[yrow(b)][o] when beta)
+// W: [>= round_up(nout, 64)][ldw] row-major, rows >= nout zero.  X rows: ldx.
+// K, nout, ldx, ldy, ldw are multiples of 4; pointers 16-byte aligned.
+// Each wave computes a 32 (outputs) x 32 (boxes) tile as 2 x 2 blocks of
+// v_mfma_f32_16x16x4_f32 over 16-k steps: lane (i, q) = (l % 16, l / 16) loads
+// one float4 of each of two W rows and two X rows (64 contiguous bytes of a
+// row per four lanes), and the four independent accumulators keep the matrix
+// core busy.  Operands are loaded one step ahead of their use; a K that is not
+// a multiple of 16 ends with 4-k steps.  SPLIT = 1: a 64 x 64 tile per
+// workgroup, its 4 waves as 2 (outputs) x 2 (boxes), each over the whole K.
+// SPLIT = 4: a 32 x 32 tile per workgroup, each wave over a quarter of the
+// 16-k steps, the four partial tiles added through LDS in a fixed order (long K
+// with few tiles: U2U of the upper levels).
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// One 16x16x4 FP32 matrix-core step.  Operand layout (wave64): lane l holds
-// A[l % 16][l / 16] and B[l / 16][l % 16]; the accumulator holds
-// D[4 (l / 16) + v][l % 16] in element v.
 __device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Four MFMA steps over 16 consecutive k.  Lane (i, q) = (l % 16, l / 16) holds
-// a = A[i][4q .. 4q+3] and b = B^T[j][4q .. 4q+3]; step r contracts k = 4q + r,
-// which covers all 16 k because the sum over k does not depend on its order.
+// Four 16x16x4 steps over 16 consecutive k.  Lane (i, q) holds a = A[i][4q ..
+// 4q+3] and b = B^T[j][4q .. 4q+3]; step r contracts k = 4q + r.  The
+// accumulator holds D[4q + v][i] in element v.
 __device__ __forceinline__ v4f mfma16x4(const float4 a, const float4 b, v4f c) {
   c = mfma16(a.x, b.x, c);
   c = mfma16(a.y, b.y, c);
@@ -30,12 +51,11 @@ __device__ __forceinline__ v4f mfma16x4(const float4 a, const float4 b, v4f c) {
   return c;
 }
 
-// ---------------------------------------------------------------- GEMM ---
-// Y[yrow(b)][o] = alpha * sum_k W[o][k] X[xrow(b)][k]  (+ Y[yrow(b)][o] when beta)
-// W: [>= round_up(nout, 64)][ldw] row-major, rows >= nout zero.  X rows: ldx.
-// K, nout, ldx, ldy, ldw are multiples of 4; pointers 16-byte aligned.
-// Block tile: 64 outputs x 64 boxes; 4 waves as 2 (outputs) x 2 (boxes), each
-// wave 32 x 32 = 2 x 2 MFMA blocks.
+struct GemmOps {
+  float4 a[2], b[2];
+};
+
+template <int SPLIT>
 __global__ __launch_bounds__(256) void k_gemm_nt(const float* __restrict__ W, int ldw, const float* __restrict__ X,
                                                  int ldx, const int* __restrict__ xrow, float* __restrict__ Y, int ldy,
                                                  const int* __restrict__ yrow, int nbox, int nout, int K, float alpha,
@@ -45,65 +65,122 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const float* __restrict__ W, in
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int i16 = lane & 15, q = lane >> 4;
-  const int o0 = blockIdx.y * 64 + (wave & 1) * 32;
-  const int b0 = blockIdx.x * 64 + (wave >> 1) * 32;
-
+  const int nstep = K >> 4;  // whole 16-k steps
+  int o0, b0, s0, s1;
+  if (SPLIT == 1) {
+    o0 = blockIdx.y * 64 + (wave & 1) * 32;
+    b0 = blockIdx.x * 64 + (wave >> 1) * 32;
+    s0 = 0;
+    s1 = nstep;
+  } else {
+    o0 = blockIdx.y * 32;
+    b0 = blockIdx.x * 32;
+    s0 = wave * nstep / 4;
+    s1 = (wave + 1) * nstep / 4;
+  }
   const float* wp[2];
   const float* xp[2];
 #pragma unroll
-  for (int m = 0; m < 2; ++m) wp[m] = W + (size_t)(o0 + 16 * m + i16) * ldw;
+  for (int m = 0; m < 2; ++m) wp[m] = W + (size_t)(o0 + 16 * m + i16) * ldw + 4 * q;
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
-    int b = min(b0 + 16 * nb + i16, nbox - 1);
-    int r = xrow ? xrow[b] : b;
-    xp[nb] = X + (size_t)r * ldx;
+    const int bb = min(b0 + 16 * nb + i16, nbox - 1);
+    xp[nb] = X + (size_t)(xrow ? xrow[bb] : bb) * ldx + 4 * q;
   }
   v4f acc[2][2];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) acc[m][nb] = v4f{0.f, 0.f, 0.f, 0.f};
-
-  int k = 0;
-  for (; k + 16 <= K; k += 16) {
-    float4 a[2], b[2];
+  auto load = [&](GemmOps& r, int st) {
 #pragma unroll
-    for (int m = 0; m < 2; ++m) a[m] = *reinterpret_cast<const float4*>(wp[m] + k + 4 * q);
+    for (int m = 0; m < 2; ++m) r.a[m] = *reinterpret_cast<const float4*>(wp[m] + 16 * st);
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) b[nb] = *reinterpret_cast<const float4*>(xp[nb] + k + 4 * q);
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) acc[m][nb] = mfma16x4(a[m], b[nb], acc[m][nb]);
-  }
-  for (; k < K; k += 4) {
+    for (int nb = 0; nb < 2; ++nb) r.b[nb] = *reinterpret_cast<const float4*>(xp[nb] + 16 * st);
+  };
+  auto compute = [&](const GemmOps& r) {
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb) acc[m][nb] = mfma16(wp[m][k + q], xp[nb][k + q], acc[m][nb]);
-  }
-#pragma unroll
-  for (int nb = 0; nb < 2; ++nb) {
-    const int b = b0 + 16 * nb + i16;
-    if (b >= nbox) continue;
-    const int r = yrow ? yrow[b] : b;
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      const int o = o0 + 16 * m + 4 * q;
-      if (o >= nout) continue;
-      // ywide: the 32-right-hand-side lane order of k_m2l_wide, [row][o / 8][32][8]
-      float4* yp = reinterpret_cast<float4*>(
-          ywide ? Y + (((size_t)r * (nout >> 3) + (o >> 3)) * 32 + blockIdx.z) * 8 + (o & 7) : Y + (size_t)r * ldy + o);
-      float4 v = make_float4(alpha * acc[m][nb][0], alpha * acc[m][nb][1], alpha * acc[m][nb][2], alpha * acc[m][nb][3]);
-      if (beta) {
-        const float4 old = *yp;
-        v.x += old.x;
-        v.y += old.y;
-        v.z += old.z;
-        v.w += old.w;
-      }
-      *yp = v;
+      for (int nb = 0; nb < 2; ++nb) acc[m][nb] = mfma16x4(r.a[m], r.b[nb], acc[m][nb]);
+  };
+  if (s0 < s1) {
+    // Two register sets, each loaded one step ahead of its use.  An odd step
+    // count takes its first step alone, so that every load and product in the
+    // loop is unconditional (the compiler keeps the loads ahead and the wait
+    // counts exact; past the end the last step is loaded again, unused).
+    GemmOps r0, r1;
+    load(r0, s0);
+    int st = s0;
+    if ((s1 - s0) & 1) {
+      compute(r0);
+      st = s0 + 1;
+      load(r0, min(st, s1 - 1));
     }
+    for (; st < s1; st += 2) {
+      load(r1, st + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(r0);
+      __builtin_amdgcn_sched_barrier(0);
+      load(r0, min(st + 2, s1 - 1));
+      __builtin_amdgcn_sched_barrier(0);
+      compute(r1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  if (SPLIT == 1 || wave == 3) {
+    // the last K mod 16: 4-k steps, lane (i, q) holding k = k0 + q
+    for (int k = 16 * nstep; k < K; k += 4) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          acc[m][nb] = mfma16(wp[m][k - 3 * q], xp[nb][k - 3 * q], acc[m][nb]);  // element k + q
+    }
+  }
+  // acc[m][nb][v]: output row o0 + 16 m + 4 q + v, box column b0 + 16 nb + i16
+  int g0 = 0, g1 = 4;  // the (m, nb) blocks g = m + 2 nb this lane stores
+  if (SPLIT == 4) {
+    __shared__ float red[4][16][64];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[wave][4 * (m + 2 * nb) + v][lane] = acc[m][nb][v];
+    __syncthreads();
+    // wave w adds the four partial tiles of block w in wave order
+    const int m = wave & 1, nb = wave >> 1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float t = red[0][4 * wave + v][lane];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) t += red[w][4 * wave + v][lane];
+      acc[m][nb][v] = t;
+    }
+    g0 = wave;
+    g1 = wave + 1;
+  }
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    if (g < g0 || g >= g1) continue;
+    const int m = g & 1, nb = g >> 1;
+    const int b = b0 + 16 * nb + i16;
+    const int o = o0 + 16 * m + 4 * q;
+    if (b >= nbox || o >= nout) continue;
+    const int r = yrow ? yrow[b] : b;
+    // ywide: the 32-right-hand-side lane order of k_m2l_wide, [row][o / 8][32][8]
+    float4* yp = reinterpret_cast<float4*>(
+        ywide ? Y + (((size_t)r * (nout >> 3) + (o >> 3)) * 32 + blockIdx.z) * 8 + (o & 7) : Y + (size_t)r * ldy + o);
+    float4 v = make_float4(alpha * acc[m][nb][0], alpha * acc[m][nb][1], alpha * acc[m][nb][2], alpha * acc[m][nb][3]);
+    if (beta) {
+      const float4 old = *yp;
+      v.x += old.x;
+      v.y += old.y;
+      v.z += old.z;
+      v.w += old.w;
+    }
+    *yp = v;
   }
 }
 
@@ -111,9 +188,16 @@ void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int*
                     const int* yrow, int nbox, int nout, int K, float alpha, int beta, hipStream_t s, int batch,
                     long long xbs, long long ybs, int ywide) {
   if (nbox <= 0 || batch <= 0) return;
-  dim3 grid((nbox + 63) / 64, (nout + 63) / 64, batch);
-  hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, s, W, ldw, X, ldx, xrow, Y, ldy, yrow, nbox, nout, K, alpha, beta,
-                     xbs, ybs, ywide);
+  const long long tiles64 = (long long)((nbox + 63) / 64) * ((nout + 63) / 64) * batch;
+  if (tiles64 < 512 && K >= 256) {
+    dim3 grid((nbox + 31) / 32, (nout + 31) / 32, batch);
+    hipLaunchKernelGGL(k_gemm_nt<4>, grid, dim3(256), 0, s, W, ldw, X, ldx, xrow, Y, ldy, yrow, nbox, nout, K, alpha,
+                       beta, xbs, ybs, ywide);
+  } else {
+    dim3 grid((nbox + 63) / 64, (nout + 63) / 64, batch);
+    hipLaunchKernelGGL(k_gemm_nt<1>, grid, dim3(256), 0, s, W, ldw, X, ldx, xrow, Y, ldy, yrow, nbox, nout, K, alpha,
+                       beta, xbs, ybs, ywide);
+  }
 }
 
 // ----------------------------------------------------------------- M2L ---
@@ -137,11 +221,6 @@ void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int*
 // stored in lane order so that a wave's float4 loads of one chunk cover 1 KiB
 // of contiguous memory; each chunk's operands are fetched two chunks ahead of
 // their use.
-typedef float v16f __attribute__((ext_vector_type(16)));
-
-__device__ __forceinline__ v16f mfma32(float a, float b, v16f c) {
-  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
-}
 
 struct M2LRegs {
   float4 a;
@@ -738,40 +817,88 @@ void launch_permute(float4* pts, const float* charges, const int* order, int n, 
 
 // ----------------------------------------------------------------- P2M ---
 // S2U, first half: field of each non-empty leaf's sources on its upward-check
-// surface c + alpha_outer r S_m.  One wave per leaf; lanes over the n check
-// points, sources read uniformly by the whole wave.  Geometry is relative to
-// the leaf centre c = c_hi + c_lo (two floats), so rounding is relative to the
-// box size rather than to |c|.
+// surface c + alpha_outer r S_m.  One wave per leaf; lane l owns the check
+// points l, l + 64, ... (NR = ceil(n / 64) of them, in registers), and the
+// sources are read uniformly by the whole wave, so that a source's position
+// relative to the leaf centre is formed once for all of the lane's check
+// points.  Geometry is relative to the leaf centre c = c_hi + c_lo (two
+// floats), so rounding is relative to the box size rather than to |c|.
+template <int NR>
 __global__ __launch_bounds__(256) void k_p2m(const float4* __restrict__ pts, const int* __restrict__ start,
                                              const int* __restrict__ leaves, const float4* __restrict__ centers,
                                              const float* __restrict__ surf, int n, float alpha, float* __restrict__ q,
                                              int ldq, int nleaves) {
-  const int leaf = blockIdx.x * 4 + (threadIdx.x >> 6);
+  // the leaf, and with it every source address, is wave-uniform: scalar loads
+  const int leaf = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (leaf >= nleaves) return;
   const int lane = threadIdx.x & 63;
   const int slot = leaves[leaf];
   const float4 ch = centers[2 * slot], cl = centers[2 * slot + 1];
   const float sc = alpha * ch.w;
-  const int s0 = start[slot], s1 = start[slot + 1];
-  for (int m = lane; m < n; m += 64) {
-    const float px = sc * surf[3 * m], py = sc * surf[3 * m + 1], pz = sc * surf[3 * m + 2];
-    float acc = 0.f;
-    for (int j = s0; j < s1; ++j) {
-      const float4 y = pts[j];
-      const float dx = px - ((y.x - ch.x) - cl.x);
-      const float dy = py - ((y.y - ch.y) - cl.y);
-      const float dz = pz - ((y.z - ch.z) - cl.z);
-      acc += y.w * __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+  const int s0 = start[slot], s1 = start[slot + 1];  // s1 > s0: the leaf is not empty
+  float px[NR], py[NR], pz[NR], acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int m = min(lane + 64 * r, n - 1);  // lanes past n repeat the last point, not stored
+    px[r] = sc * surf[3 * m];
+    py[r] = sc * surf[3 * m + 1];
+    pz[r] = sc * surf[3 * m + 2];
+    acc[r] = 0.f;
+  }
+  // four sources per step, their loads issued together; past the end the last
+  // source repeats with charge 0 (it lies inside the leaf, away from the check
+  // surface, so its term is exactly 0)
+  for (int j = s0; j < s1; j += 4) {
+    float4 y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      y[u] = pts[min(j + u, s1 - 1)];
+      if (j + u >= s1) y[u].w = 0.f;
     }
-    q[(size_t)slot * ldq + m] = acc;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float rx = (y[u].x - ch.x) - cl.x, ry = (y[u].y - ch.y) - cl.y, rz = (y[u].z - ch.z) - cl.z;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const float dx = px[r] - rx, dy = py[r] - ry, dz = pz[r] - rz;
+        acc[r] += y[u].w * __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int m = lane + 64 * r;
+    if (m < n) q[(size_t)slot * ldq + m] = acc[r];
   }
 }
 
-void launch_p2m(const float4* pts, const int* start, const int* leaves, const float4* centers, const float* surf, int n,
+bool launch_p2m(const float4* pts, const int* start, const int* leaves, const float4* centers, const float* surf, int n,
                 float alpha, float* q, int ldq, int nleaves, hipStream_t s) {
-  if (nleaves <= 0) return;
-  hipLaunchKernelGGL(k_p2m, dim3((nleaves + 3) / 4), dim3(256), 0, s, pts, start, leaves, centers, surf, n, alpha, q,
-                     ldq, nleaves);
+  if (nleaves <= 0) return true;
+  const dim3 grid((nleaves + 3) / 4);
+  switch ((n + 63) / 64) {
+#define KIFMM_P2M_CASE(R)                                                                                    \
+  case R:                                                                                                    \
+    hipLaunchKernelGGL(k_p2m<R>, grid, dim3(256), 0, s, pts, start, leaves, centers, surf, n, alpha, q, ldq, \
+                       nleaves);                                                                             \
+    break;
+    KIFMM_P2M_CASE(1)
+    KIFMM_P2M_CASE(2)
+    KIFMM_P2M_CASE(3)
+    KIFMM_P2M_CASE(4)
+    KIFMM_P2M_CASE(5)
+    KIFMM_P2M_CASE(6)
+    KIFMM_P2M_CASE(7)
+    KIFMM_P2M_CASE(8)
+    KIFMM_P2M_CASE(9)
+    KIFMM_P2M_CASE(10)
+    KIFMM_P2M_CASE(11)
+    KIFMM_P2M_CASE(12)
+#undef KIFMM_P2M_CASE
+    default:
+      return false;  // more than 768 check points
+  }
+  return true;
 }
 
 // ----------------------------------------------------------------- P2P ---

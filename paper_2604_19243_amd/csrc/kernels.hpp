@@ -54,7 +54,8 @@ void launch_sum_parts(const float* part, float* chat, long long n, long long str
 void launch_vjp_combine(const float* s, const float* w, const float* fs, const float* fw, float* out, int n,
                         hipStream_t st);
 void launch_permute(float4* pts, const float* charges, const int* order, int n, hipStream_t s);
-void launch_p2m(const float4* pts, const int* start, const int* leaves, const float4* centers, const float* surf, int n,
+// False if n > 768 (no kernel instance).
+bool launch_p2m(const float4* pts, const int* start, const int* leaves, const float4* centers, const float* surf, int n,
                 float alpha, float* q, int ldq, int nleaves, hipStream_t s);
 // centers: per leaf slot two float4, (c_hi, r) and (c_lo, 0) with c = c_hi + c_lo.
 // blk: per parent group, the 64 leaf slots of the 4x4x4 block around it (-1 = none).

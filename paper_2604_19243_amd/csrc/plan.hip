@@ -492,7 +492,8 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
       // k per LDS slab of the staged sources (row stride slab + 4 floats, an odd
       // number of 16-byte units): the most resident waves per CU first (at most
       // 16 for the kernel's register use; rb waves per workgroup, 216 rows of
-      // LDS each), then the fewest slabs.
+      // LDS each), then the fewest slabs.  (Timed at k = 94 on the 1M cube: 5,
+      // 4 and 3 workgroups per CU take 1.21, 1.34 and 1.38 ms.)
       {
         int best_slab = 0, best_waves = -1, best_n = 0;
         for (int slab = 24; slab <= 48; slab += 8) {
@@ -856,10 +857,11 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
     // With nrhs > 1 every per-box array holds the right-hand sides one after
     // the other, and each product runs as one batch over them.
     P->stage_begin(KIFMM_STAGE_P2M, st);
-    if (R == 1)
-      launch_p2m(P->d_pts, P->d_start, P->d_leaves, P->d_centers, P->d_surf, n, (float)kAlphaOuter, P->d_q, nst,
-                 nleaves, st);
-    else if (!launch_p2m_multi(R, P->d_pts, P->d_qs, P->d_start, P->d_leaves, P->d_centers, P->d_surf, n,
+    if (R == 1) {
+      if (!launch_p2m(P->d_pts, P->d_start, P->d_leaves, P->d_centers, P->d_surf, n, (float)kAlphaOuter, P->d_q, nst,
+                      nleaves, st))
+        fail(KIFMM_E_DEVICE, "leaf kernel configuration not available");
+    } else if (!launch_p2m_multi(R, P->d_pts, P->d_qs, P->d_start, P->d_leaves, P->d_centers, P->d_surf, n,
                                (float)kAlphaOuter, P->d_q, nst, (long long)SL * nst, nleaves, st))
       fail(KIFMM_E_DEVICE, "multi-RHS leaf kernel configuration not available");
     P->stage_end(KIFMM_STAGE_P2M, st);

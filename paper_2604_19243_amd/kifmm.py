@@ -223,10 +223,10 @@ def kifmm_plan_get_stage_times(plan, reset=True):
 
 
 def kifmm_plan_get_stats(plan):
-    out = np.zeros(10, dtype=np.int64)
-    _check(library().kifmm_plan_get_stats(plan, _host_ptr(out), 10))
+    out = np.zeros(11, dtype=np.int64)
+    _check(library().kifmm_plan_get_stats(plan, _host_ptr(out), 11))
     keys = ["p2p_pairs", "m2l_pairs", "leaf_slots", "m2l_targets", "k", "n", "nrhs", "m2l_form", "m2l_stage_pairs",
-            "upper_stream"]
+            "upper_stream", "m2l_lds_slab"]
     return dict(zip(keys, (int(v) for v in out)))
 
 
