@@ -211,6 +211,10 @@ kifmm_status kifmm_ops_destroy(kifmm_ops ops);
  * run as one batch and the leaf kernels compute each pair's geometry once for
  * all of them; such plans give potentials only (no KIFMM_GRADIENT, no
  * KIFMM_VJP) and run on the caller's stream alone.
+ *
+ * A tree of depth >= 2 (one with a far field) needs p <= 8 (at most 304
+ * surface points, which the leaf kernels hold in LDS); larger p gives
+ * KIFMM_E_INVALID.  Depth 0 and 1 (the direct sum) take any p.
  */
 kifmm_status kifmm_plan_create(kifmm_tree tree, kifmm_ops ops, int nrhs, unsigned flags, int device,
                                kifmm_plan* out);

@@ -147,6 +147,30 @@ def test_expansion_orders(p, n, depth):
     assert e < TOL and eg < TOL
 
 
+def test_orders_above_8_need_a_shallow_tree():
+    # p = 9 (386 surface points): the leaf kernels hold at most 304, so a tree with a far
+    # field is refused with KIFMM_E_INVALID; at depth 1 (the direct sum) the order is unused.
+    log("order p=9")
+    x = workloads.points("cube", 3_000, 709)
+    s = workloads.charges("uniform11", 3_000, 809)
+    ops = kifmm.kifmm_ops_precompute(9)
+    try:
+        for depth, ok in ((3, False), (1, True)):
+            tree = kifmm.kifmm_tree_build(x, depth, UNIT)
+            try:
+                if ok:
+                    plan = kifmm.kifmm_plan_create(tree, ops, 1, kifmm.KIFMM_POTENTIAL | kifmm.KIFMM_GRADIENT)
+                    kifmm.kifmm_plan_destroy(plan)
+                else:
+                    with pytest.raises(kifmm.KifmmError) as e:
+                        kifmm.kifmm_plan_create(tree, ops, 1, kifmm.KIFMM_POTENTIAL)
+                    assert e.value.status == kifmm.KIFMM_E_INVALID and "p <= 8" in str(e.value)
+            finally:
+                kifmm.kifmm_tree_destroy(tree)
+    finally:
+        kifmm.kifmm_ops_destroy(ops)
+
+
 @pytest.mark.parametrize("depth", [8, 10])
 def test_deep_sparse_trees(depth):
     # Maximum depth: almost every leaf holds one point and most boxes are empty.

@@ -21,26 +21,27 @@ pytestmark = pytest.mark.gpu
 TOL = {"bf16x3": 1e-5, "bf16x6": 1e-6}
 UNIT = (0.5, 0.5, 0.5, 0.5)
 CASES = [
-    ("cube20k_p6_d3", 20_000, 3, 6, "cube", "uniform01", False),
-    ("p8_normal", 40_000, 4, 8, "cube", "normal", False),      # the precision workload's order and charges
-    ("p8_normal_serial", 40_000, 4, 8, "cube", "normal", True),
-    ("ragged_p5", 7_777, 4, 5, "cube", "uniform11", False),    # k = 56 -> 64
-    ("sphere", 30_000, 4, 6, "sphere", "uniform01", False),
-    ("p2", 3_000, 3, 2, "cube", "uniform01", False),            # k = 8 -> 16: one chunk, half of it padding
+    ("cube20k_p6_d3", 20_000, 3, 6, "cube", "uniform01", False, 0),
+    ("p8_normal", 40_000, 4, 8, "cube", "normal", False, 0),      # the precision workload's order and charges
+    ("p8_normal_serial", 40_000, 4, 8, "cube", "normal", True, 0),
+    ("ragged_p5", 7_777, 4, 5, "cube", "uniform11", False, 0),    # k = 56 -> 64
+    ("sphere", 30_000, 4, 6, "sphere", "uniform01", False, 0),
+    ("p2", 3_000, 3, 2, "cube", "uniform01", False, 0),            # k = 8 -> 16: one chunk, half of it padding
+    ("rank94", 40_000, 4, 6, "cube", "uniform01", False, 94),     # k = 94 -> 96: three row blocks
 ]
 
 
 @pytest.mark.parametrize("m2l", ["bf16x3", "bf16x6"])
-@pytest.mark.parametrize("name,n,depth,p,dist,charges,serial", CASES)
-def test_split_bf16_parity_with_oracle(m2l, name, n, depth, p, dist, charges, serial):
-    log(f"{m2l} parity {name} n={n} depth={depth} p={p}")
+@pytest.mark.parametrize("name,n,depth,p,dist,charges,serial,rank", CASES)
+def test_split_bf16_parity_with_oracle(m2l, name, n, depth, p, dist, charges, serial, rank):
+    log(f"{m2l} parity {name} n={n} depth={depth} p={p} rank={rank}")
     x = workloads.points(dist, n, 1001 if name.startswith("cube20k") else 300 + n + p)
     s = workloads.charges(charges, n, 2001 if name.startswith("cube20k") else 400 + n + p)
     cube = UNIT if dist == "cube" else (0.0, 0.0, 0.0, 1.0)
-    phi, g, f = gpu_evaluate(x, s, depth, p, cube, serial=serial, m2l=m2l)
+    phi, g, f = gpu_evaluate(x, s, depth, p, cube, serial=serial, m2l=m2l, rank=rank)
     k = kifmm.kifmm_ops_get_info(f.ops)["rank_m2l"]
     f.close()
-    rphi, rg, _, _ = oracle_evaluate(x, s, depth, p, cube)
+    rphi, rg, _, _ = oracle_evaluate(x, s, depth, p, cube, rank=rank or None)
     e, eg = rel_l2(phi, rphi), rel_l2(g, rg)
     log(f"  rel-L2 {m2l} phi {e:.3e} grad {eg:.3e} (k={k})")
     assert e < TOL[m2l] and eg < TOL[m2l]
