@@ -173,7 +173,7 @@ def main():
         print(json.dumps({"copy_probe_mib": args.copy_probe, "launches": 5}), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the evaluate runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design, not built)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
