@@ -27,6 +27,14 @@ single-threaded:
 Readings of points the paper leaves open (kernel normalisation, coincident
 points, surface geometry, pseudo-inverse cutoff, compression scheme) are
 stated in the module that implements them.
+
+Pins: each module is checked by tests/test_oracle_*.py against something other
+than itself -- closed forms, the direct sum, brute force on tiny inputs,
+invariants (linearity, translation, symmetry of the derivative), convergence in
+the expansion order, and the values the paper prints.  The readings above are
+choices the paper does not fix; for them parity is unpinned: another valid
+choice (other surface radii, cutoffs or compression bases) gives a different,
+similarly accurate kiFMM.
 """
 
 from . import kernel, direct, surface, tree, operators, fmm  # noqa: F401
