@@ -151,7 +151,7 @@ def main():
                     help="skip the second timing, at the default M2L rank, of a workload with a rank of its own")
     ap.add_argument("--compare-single", action="store_true",
                     help="with a multi-RHS workload: also time a one-RHS plan on the same tree and operators")
-    ap.add_argument("--sample-leaves", type=int, default=24)
+    ap.add_argument("--sample-leaves", type=int, default=3000)
     ap.add_argument("--sample-seed", type=int, default=2)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (calibrates HBM byte counters) and exit")
