@@ -273,11 +273,13 @@ enum {
   KIFMM_STAGE_PERMUTE = 0, /* gather charges into sorted order */
   KIFMM_STAGE_P2M = 1,     /* leaf sources -> upward-check field (S2U, first half) */
   KIFMM_STAGE_UC2E = 2,    /* upward-check field -> upward density, two factors */
-  KIFMM_STAGE_M2M = 3,     /* U2U, all levels; with the plan's second stream also the compression and
-                              VLI of the levels above the leaves, which run there beside the leaf VLI */
+  KIFMM_STAGE_M2M = 3,     /* U2U, all levels; with the plan's second stream also the compression, VLI
+                              and downward pass (sum, post, D2D) of the levels above the leaves and the
+                              D2D into the leaf level, which run there beside the leaf VLI */
   KIFMM_STAGE_COMPRESS = 4,/* u -> V_k^T u, levels 2..L (the leaf level alone with the second stream) */
   KIFMM_STAGE_M2L = 5,     /* compressed VLI, all levels (the leaf level alone with the second stream) */
-  KIFMM_STAGE_L2L = 6,     /* sum of M2L partial sums, post (DC2E U_k) and D2D, levels 2..L */
+  KIFMM_STAGE_L2L = 6,     /* sum of M2L partial sums, post (DC2E U_k) and D2D, levels 2..L (with the
+                              second stream: the leaf level's sum and post) */
   KIFMM_STAGE_P2P = 7,     /* ULI at the leaves (on the plan's stream), or fused D2T + ULI with KIFMM_SERIAL */
   KIFMM_STAGE_L2P = 8,     /* D2T added to the ULI result, written in input order (not with KIFMM_SERIAL) */
   KIFMM_N_STAGES = 9

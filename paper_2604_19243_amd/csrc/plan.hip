@@ -878,6 +878,24 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
     const bool up = P->up != nullptr && P->up_on;
     const int n_upper = P->n_nonempty - (int)P->keys_per_level[L];  // non-empty rows of levels 2..L-1
     hipStream_t su = up ? P->up : st;
+    // (2c) pieces: the sum of the eight M2L partial sums over a range of box rows,
+    // D2D into level l (all 8 children of each non-empty parent, overwritten) and
+    // the post product (DC2E U_k) of level l's non-empty boxes, added above level 2:
+    // d = L2L d_parent + post chat.  Empty boxes' d is never read.
+    auto sum_rows = [&](long long r0, long long r1, hipStream_t s) {
+      if (!P->m2l_wide && !P->m2l_gather)
+        launch_sum_parts(P->d_chat_part + r0 * kst, P->d_chat + r0 * kst, R * (r1 - r0) * kst, R * TS * kst, s);
+    };
+    auto d2d = [&](int l, hipStream_t s) {
+      const int parents = (int)P->keys_per_level[l - 1];
+      launch_gemm_nt(P->d_l2l, nst, P->d_d + P->base[l - 1] * nst, nst, P->d_nbslot[l - 1], P->d_d + P->base[l] * nst,
+                     8 * nst, nullptr, parents, 8 * nst, nst, 1.0f, 0, s, R, TS * nst, TS * nst);
+    };
+    auto post = [&](int l, hipStream_t s) {
+      launch_gemm_nt(P->d_post, kst, P->d_chat + P->base[l] * kst, kst, P->d_nbslot[l], P->d_d + P->base[l] * nst,
+                     nst, P->d_nbslot[l], (int)P->keys_per_level[l], nst, kst, 1.0f, l > 2 ? 1 : 0, s, R, TS * kst,
+                     TS * nst);
+    };
     if (up) {
       hip_check(hipEventRecord(P->ev_up0, st), "hipEventRecord");
       hip_check(hipStreamWaitEvent(su, P->ev_up0, 0), "hipStreamWaitEvent");
@@ -889,10 +907,18 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
                      nst, P->d_nbslot[l - 1], parents, nst, 8 * nst, 1.0f, 0, su, R, TS * nst, TS * nst);
     }
     if (up) {
-      // compression and VLI of the levels above the leaves
+      // Compression, VLI and the downward pass of the levels above the leaves, and
+      // D2D into the leaf level (it needs only the level above): all of it beside
+      // the leaf level's VLI, whose result then only needs its sum and post.
       launch_gemm_nt(P->d_vt, nst, P->d_u, nst, P->d_nonempty, P->d_uhat, kst, P->d_nonempty, n_upper, kst, nst, 1.0f,
                      0, su, R, TS * nst, TS * kst, P->m2l_wide ? 1 : 0);
       if (!launch_m2l_form(P, su, 2)) fail(KIFMM_E_DEVICE, "M2L kernel configuration not available");
+      sum_rows(P->base[2], P->base[L], su);
+      for (int l = 2; l < L; ++l) {
+        if (l > 2) d2d(l, su);
+        post(l, su);
+      }
+      d2d(L, su);
     }
     P->stage_end(KIFMM_STAGE_M2M, su);
     if (up) hip_check(hipEventRecord(P->ev_up1, su), "hipEventRecord");
@@ -909,23 +935,18 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
     const bool m2l_ok = launch_m2l_form(P, st, up ? 1 : 0);
     if (!m2l_ok) fail(KIFMM_E_DEVICE, "M2L kernel configuration not available");
     P->stage_end(KIFMM_STAGE_M2L, st);
-    if (up) hip_check(hipStreamWaitEvent(st, P->ev_up1, 0), "hipStreamWaitEvent");
-    // (2c) sum of the M2L partial sums, post (DC2E U_k) and D2D, coarse to fine.
+    // (2c) coarse to fine; with the second stream only the leaf level's sum and post remain here
     P->stage_begin(KIFMM_STAGE_L2L, st);
-    if (!P->m2l_wide && !P->m2l_gather) launch_sum_parts(P->d_chat_part, P->d_chat, R * TS * kst, R * TS * kst, st);
-    // D2D first (all 8 children of each non-empty parent, overwritten), then the
-    // post product of the non-empty boxes added: d = L2L d_parent + post chat.
-    // Empty boxes' d is never read.
-    for (int l = 2; l <= L; ++l) {
-      if (l > 2) {
-        const int parents = (int)P->keys_per_level[l - 1];
-        launch_gemm_nt(P->d_l2l, nst, P->d_d + P->base[l - 1] * nst, nst, P->d_nbslot[l - 1],
-                       P->d_d + P->base[l] * nst, 8 * nst, nullptr, parents, 8 * nst, nst, 1.0f, 0, st, R, TS * nst,
-                       TS * nst);
+    if (up) {
+      sum_rows(P->base[L], TS, st);
+      hip_check(hipStreamWaitEvent(st, P->ev_up1, 0), "hipStreamWaitEvent");
+      post(L, st);
+    } else {
+      sum_rows(0, TS, st);
+      for (int l = 2; l <= L; ++l) {
+        if (l > 2) d2d(l, st);
+        post(l, st);
       }
-      launch_gemm_nt(P->d_post, kst, P->d_chat + P->base[l] * kst, kst, P->d_nbslot[l], P->d_d + P->base[l] * nst,
-                     nst, P->d_nbslot[l], (int)P->keys_per_level[l], nst, kst, 1.0f, l > 2 ? 1 : 0, st, R, TS * kst,
-                     TS * nst);
     }
     P->stage_end(KIFMM_STAGE_L2L, st);
   }
