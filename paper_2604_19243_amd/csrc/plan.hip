@@ -871,10 +871,11 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
     launch_gemm_nt(P->d_f2, kcst, P->d_t, kcst, P->d_leaves, uL, nst, P->d_leaves, nleaves, nst, kcst,
                    (float)P->tree->radius(L), 0, st, R, (long long)SL * kcst, TS * nst);
     P->stage_end(KIFMM_STAGE_UC2E, st);
-    // (1b) U2U, (2a) compression and VLI.  The leaf level's VLI needs only the
-    // leaf level's compressed densities, so with a second plan stream the levels
-    // above it (U2U to level 2, their compression and their VLI) run there,
-    // beside the leaf level's VLI, and are joined before the partial sums.
+    // (1b) U2U, (2a) compression and VLI, (2c) D2D.  The leaf level's VLI needs
+    // only the leaf level's compressed densities, so with a second plan stream the
+    // levels above it (U2U to level 2, their compression, VLI and downward pass,
+    // and the D2D into the leaf level) run there, beside the leaf level's VLI, and
+    // are joined before the leaf level's post product.
     const bool up = P->up != nullptr && P->up_on;
     const int n_upper = P->n_nonempty - (int)P->keys_per_level[L];  // non-empty rows of levels 2..L-1
     hipStream_t su = up ? P->up : st;

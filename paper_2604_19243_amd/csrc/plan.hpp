@@ -60,7 +60,7 @@ struct Plan : Object {
   static constexpr int kRing = 128;
   hipStream_t side = nullptr;            // ULI stream (default priority)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  hipStream_t up = nullptr;              // levels above the leaves: U2U, compression, VLI (default priority)
+  hipStream_t up = nullptr;              // levels above the leaves: U2U, compression, VLI, downward pass (default priority)
   bool up_on = true;                     // use it (timed against not using it at plan creation)
   double up_tune_ms[2] = {0.0, 0.0};     // evaluate without / with the second stream (ms)
   hipEvent_t ev_up0 = nullptr, ev_up1 = nullptr;
