@@ -192,3 +192,24 @@ def test_plan_without_device_reports_device_error():
     finally:
         kifmm.kifmm_ops_destroy(o)
         kifmm.kifmm_tree_destroy(t)
+
+
+def test_binding_constants_match_the_header():
+    # every #define KIFMM_* and every KIFMM_* = value in an enum of the header has the
+    # same value in the binding
+    header = open(os.path.join(ROOT, "include", "kifmm_mi355x.h")).read()
+    found = dict(re.findall(r"#define\s+(KIFMM_[A-Z0-9_]+)\s+(-?\d+)u?\b", header))
+    found.update(re.findall(r"\b(KIFMM_[A-Z0-9_]+)\s*=\s*(-?\d+)", header))
+    assert len(found) >= 20
+    for name, value in found.items():
+        if hasattr(kifmm, name):
+            assert getattr(kifmm, name) == int(value), name
+    # the binding's stage names in the header's stage order, and the library's ABI version
+    for i, stage in enumerate(kifmm.STAGES):
+        assert int(found["KIFMM_STAGE_" + stage.upper()]) == i, stage
+    assert int(found["KIFMM_N_STAGES"]) == len(kifmm.STAGES)
+    assert int(found["KIFMM_ABI_VERSION"]) == kifmm.kifmm_abi_version()
+    for name in ("KIFMM_POTENTIAL", "KIFMM_GRADIENT", "KIFMM_SERIAL", "KIFMM_M2L_BF16X3", "KIFMM_M2L_BF16X6",
+                 "KIFMM_VJP", "KIFMM_M2L_BLOCKED", "KIFMM_M2L_GATHER", "KIFMM_UPPER_STREAM", "KIFMM_NO_UPPER_STREAM",
+                 "KIFMM_E_INVALID", "KIFMM_E_DEVICE"):
+        assert name in found and hasattr(kifmm, name), name
