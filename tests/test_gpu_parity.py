@@ -40,6 +40,8 @@ def test_shallow_tree_equals_direct_sum(depth, n):
     ("ragged", 7_777, 4, 5, "cube", False, 0),           # ragged leaves and tiles, many boundary boxes
     ("sphere", 30_000, 4, 6, "sphere", False, 0),        # strongly non-uniform: most boxes empty
     ("sparse_deep", 2_000, 5, 4, "cube", True, 0),       # ~0.06 points per leaf
+    ("depth2", 5_000, 2, 5, "cube", False, 0),           # far field at level 2 only: no U2U, no D2D
+    ("depth2_serial", 5_000, 2, 5, "cube", True, 0),
     # rank 94 (the p = 6 benchmark rank): k padded to 96, three 32-row blocks, 32-k slabs
     ("rank94", 40_000, 4, 6, "cube", False, 94),
     ("rank94_sphere", 30_000, 4, 6, "sphere", False, 94),

@@ -28,6 +28,7 @@ CASES = [
     ("sphere", 30_000, 4, 6, "sphere", "uniform01", False, 0),
     ("p2", 3_000, 3, 2, "cube", "uniform01", False, 0),            # k = 8 -> 16: one chunk, half of it padding
     ("rank94", 40_000, 4, 6, "cube", "uniform01", False, 94),     # k = 94 -> 96: three row blocks
+    ("depth2", 5_000, 2, 5, "cube", "uniform11", False, 0),       # far field at level 2 only
 ]
 
 
