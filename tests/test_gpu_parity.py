@@ -206,3 +206,22 @@ def test_gradient_only_and_auto_cube():
     eg = rel_l2(grad.cpu().double().numpy(), rg)
     log(f"  rel-L2 grad {eg:.3e}")
     assert eg < TOL
+
+
+def test_coincident_and_grid_aligned_points():
+    # Duplicated points (pairs at zero distance contribute nothing, on both sides) and
+    # points on leaf faces and on the cube's top faces (assigned to the last box).
+    log("coincident and grid-aligned points")
+    rng = np.random.default_rng(31)
+    base = workloads.points("cube", 6_000, 30)
+    dup = base[rng.choice(len(base), 500, replace=False)]
+    grid = (rng.integers(0, 9, size=(300, 3)) / 8.0).astype(np.float32)   # k/8 in [0, 1], 1.0 included
+    x = np.concatenate([base, dup, grid]).astype(np.float32)
+    s = workloads.charges("uniform11", len(x), 32)
+    phi, g, f = gpu_evaluate(x, s, 3, 5, UNIT)
+    f.close()
+    assert np.isfinite(phi).all() and np.isfinite(g).all()
+    rphi, rg, _, _ = oracle_evaluate(x, s, 3, 5, UNIT)
+    e, eg = rel_l2(phi, rphi), rel_l2(g, rg)
+    log(f"  rel-L2 phi {e:.3e} grad {eg:.3e}")
+    assert e < TOL and eg < TOL
