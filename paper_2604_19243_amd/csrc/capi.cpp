@@ -222,7 +222,7 @@ kifmm_status kifmm_plan_get_stage_times(kifmm_plan plan, double* ms, int64_t* co
 kifmm_status kifmm_plan_get_stats(kifmm_plan plan, int64_t* stats, int count) {
   return guarded([&] {
     const Plan* p = as_plan(plan);
-    require(stats != nullptr && count >= 0, "output is null");
+    require(stats != nullptr && count >= 0, "stats is null or count is negative");
     const int64_t form = p->m2l_pieces ? 3 : p->m2l_wide ? 2 : p->m2l_gather ? 1 : 0;
     const bool up = p->up && p->up_on;
     const int64_t stage_pairs = up ? p->m2l_pairs_leaf : p->m2l_pairs;
