@@ -18,14 +18,17 @@ pytestmark = pytest.mark.gpu
 UNIT = (0.5, 0.5, 0.5, 0.5)
 
 
-@pytest.mark.parametrize("serial,nrhs", [(False, 1), (True, 1), (False, 4)])
-def test_captured_evaluate_replays_bitwise(serial, nrhs):
+@pytest.mark.parametrize("serial,nrhs,upper", [(False, 1, False), (True, 1, False), (False, 4, False),
+                                               (False, 1, True)])
+def test_captured_evaluate_replays_bitwise(serial, nrhs, upper):
+    # upper: the levels above the leaves forced onto the plan's second stream (three streams captured)
     import torch
-    log(f"graph capture serial={serial} nrhs={nrhs}")
-    n, depth, p = 20_000, 3, 6
+    log(f"graph capture serial={serial} nrhs={nrhs} upper={upper}")
+    n, depth, p = 20_000, 4 if upper else 3, 6
     x = workloads.points("cube", n, 1001)
     flags = kifmm.KIFMM_POTENTIAL | (kifmm.KIFMM_SERIAL if serial else 0)
     flags |= kifmm.KIFMM_GRADIENT if nrhs == 1 else 0
+    flags |= kifmm.KIFMM_UPPER_STREAM if upper else 0
     f = kifmm.FMM(x, depth, p, cube=UNIT, flags=flags, nrhs=nrhs)
     dev = torch.device("cuda:0")
     shape = (n,) if nrhs == 1 else (n, nrhs)
@@ -39,6 +42,8 @@ def test_captured_evaluate_replays_bitwise(serial, nrhs):
     with torch.cuda.stream(s):
         f.evaluate(q, pot, grad, stream=s.cuda_stream)   # warm-up (kernel attributes set eagerly)
     torch.cuda.synchronize()
+    if upper:
+        assert kifmm.kifmm_plan_get_stats(f.plan)["upper_stream"] == 1
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
         f.evaluate(q, pot, grad, stream=s.cuda_stream)
