@@ -304,7 +304,8 @@ kifmm_status kifmm_plan_get_stage_times(kifmm_plan plan, double* ms, int64_t* co
  *              beside the leaf level's VLI (chosen by timing at plan creation),
  *   stats[10] = k per LDS slab of the staged M2L sources in the blocked forms
  *              (0 for the other forms).
- * At most `count` entries are written. */
+ * At most `count` entries are written.  KIFMM_E_INVALID if plan or stats is
+ * null or count is negative. */
 kifmm_status kifmm_plan_get_stats(kifmm_plan plan, int64_t* stats, int count);
 
 /* Copy a level's densities to the host after the stream is idle, as float in
