@@ -918,6 +918,12 @@ bool launch_p2m(const float4* pts, const int* start, const int* leaves, const fl
 // them from global memory instead.
 //
 // Dynamic LDS: [cap] float4 sources, [n] float4 surface points, [8 n] floats d.
+//
+// Five waves per workgroup: at 30.5 points per leaf a parent's siblings hold
+// 244 targets on average (Poisson), so 320 threads take nearly every parent in
+// one pass, where 256 left about a fifth of the workgroups a second pass on a
+// few lanes while the whole workgroup kept its LDS.
+constexpr int kP2PThreads = 320;
 extern __shared__ float4 s_p2p[];
 
 __device__ __forceinline__ void p2p_pair(float xx, float xy, float xz, float4 y, float& phi, float& gx, float& gy,
@@ -949,7 +955,7 @@ __device__ __forceinline__ void p2p_pair_masked(float xx, float xy, float xz, fl
 // order to `near` (phi, grad) for a later MODE 2 launch; MODE 2: far field only,
 // added to `near` and written to input order.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_p2p(const float4* __restrict__ pts, const int* __restrict__ start,
+__global__ __launch_bounds__(kP2PThreads) void k_p2p(const float4* __restrict__ pts, const int* __restrict__ start,
                                              const int* __restrict__ blk, int group_slots, int cap,
                                              const float4* __restrict__ centers, const float* __restrict__ surf,
                                              int n, float alpha, const float* __restrict__ d, int ldd, int far,
@@ -989,7 +995,7 @@ __global__ __launch_bounds__(256) void k_p2p(const float4* __restrict__ pts, con
   const bool in_lds = total <= cap;
   if (kNear && in_lds) {
     const float big = 3.402823466e38f;
-    for (int i = tid; i < total; i += 256) {
+    for (int i = tid; i < total; i += kP2PThreads) {
       int lo = 0, hi = 64;  // entry e with s_off[e] <= i < s_off[e + 1]
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -1002,9 +1008,9 @@ __global__ __launch_bounds__(256) void k_p2p(const float4* __restrict__ pts, con
   }
   const float sc = alpha * centers[2 * c0].w;
   if (kFar && far) {
-    for (int m = tid; m < n; m += 256)
+    for (int m = tid; m < n; m += kP2PThreads)
       s_de[m] = make_float4(sc * surf[3 * m], sc * surf[3 * m + 1], sc * surf[3 * m + 2], 0.f);
-    for (int i = tid; i < group_slots * n; i += 256) {
+    for (int i = tid; i < group_slots * n; i += kP2PThreads) {
       const int o = i / n, m = i - o * n;
       s_d[o * n + m] = d[(size_t)(c0 + o) * ldd + m];
     }
@@ -1012,7 +1018,7 @@ __global__ __launch_bounds__(256) void k_p2p(const float4* __restrict__ pts, con
   __syncthreads();
 
   const int t0 = s_cs[0], t1 = s_cs[group_slots];
-  for (int tb = t0; tb < t1; tb += 256) {
+  for (int tb = t0; tb < t1; tb += kP2PThreads) {
     const int ti = tb + tid;
     if (ti >= t1) break;
     int o = 0;
@@ -1116,8 +1122,8 @@ bool launch_p2p(int mode, const float4* pts, const int* start, const int* blk, i
         return false;
       attr = lds;
     }
-    hipLaunchKernelGGL(kernel, dim3(ngroups), dim3(256), lds, s, pts, start, blk, group_slots, c, centers, surf, n,
-                       alpha, d, ldd, far, order, pot, grad, near);
+    hipLaunchKernelGGL(kernel, dim3(ngroups), dim3(kP2PThreads), lds, s, pts, start, blk, group_slots, c, centers,
+                       surf, n, alpha, d, ldd, far, order, pot, grad, near);
     return true;
   };
   static size_t attr0 = 0, attr1 = 0, attr2 = 0;
