@@ -8,7 +8,8 @@ build and operator precompute are setup and are not timed.
 
 Prints one JSON line: metric/value (Mpoints/s = N / time per evaluate), the
 roofline of the dominant kernel (M2L, FP32 matrix cores) measured with HIP
-events on the evaluate stream, the P2P kernel's FLOP rate, and the FP64 oracle
+events on the evaluate stream, the P2P kernel's FLOP rate (overlapped with the far
+field, and alone in a one-stream plan), and the FP64 oracle
 timed on a bounded sample on the host CPU.
 
 `--m2l bf16x3` runs M2L as three bfloat16 matrix-core passes with FP32
@@ -308,6 +309,33 @@ def main():
         default_rank = {"m2l_rank": kr, "ms_per_step": msr, "value": w.n / (msr * 1e-3) / 1e6,
                         "m2l_ms": stagesr["m2l"], "stages_ms": stagesr}
 
+    # The ULI kernel of the default layout shares the GPU with the far field, so its span says
+    # little about its own speed: the fused D2T + ULI kernel of a one-stream plan on the same
+    # tree and operators is timed alone (stage events on the evaluate stream).
+    p2p_alone = None
+    if R == 1 and not args.serial and not args.graph:
+        layout = kifmm.KIFMM_UPPER_STREAM | kifmm.KIFMM_NO_UPPER_STREAM
+        plan_s = kifmm.kifmm_plan_create(f.tree, f.ops, 1, (flags & ~kifmm.KIFMM_VJP) | (m2l_flag & ~layout)
+                                         | kifmm.KIFMM_SERIAL)
+        for _ in range(2):
+            kifmm.kifmm_evaluate(plan_s, charges, pot, grad, stream.cuda_stream)
+        torch.cuda.synchronize()
+        kifmm.kifmm_plan_set_timing(plan_s, True)
+        kifmm.kifmm_plan_get_stage_times(plan_s, reset=True)
+        for _ in range(10):
+            kifmm.kifmm_evaluate(plan_s, charges, pot, grad, stream.cuda_stream)
+        torch.cuda.synchronize()
+        st_s = kifmm.kifmm_plan_get_stage_times(plan_s, reset=True)
+        kifmm.kifmm_plan_destroy(plan_s)
+        ms_s = st_s["p2p"][0] / max(st_s["p2p"][1], 1)
+        pairs_s = stats["p2p_pairs"] + w.n * n * (1 if w.depth >= 2 else 0)
+        fpp = P2P_FLOPS_PER_PAIR if grad is not None else 9 + 2 * R
+        tf_s = fpp * pairs_s / (ms_s * 1e-3) / 1e12
+        p2p_alone = {"kernel": "k_p2p<0> (fused D2T + ULI, one-stream plan, alone on the GPU)", "bound": "alu",
+                     "achieved": tf_s, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": tf_s / PEAK_FP32_TFLOPS,
+                     "ms_per_launch": ms_s, "pairs_per_launch": pairs_s, "flop_per_pair": fpp, "launches": 10}
+        print(f"# fused D2T + ULI alone: {ms_s:.3f} ms, {tf_s:.1f} TFLOP/s", file=sys.stderr, flush=True)
+
     # M2L (dominant kernel): 2 k^2 FLOP per (target, source) V-list pair; the split-bfloat16
     # forms execute each product as 3 or 6 bfloat16 products, counted against the BF16 peak.
     m2l_ms = stages["m2l"]
@@ -356,6 +384,7 @@ def main():
                        stats["m2l_form"]],
                    "upper_levels_on_second_stream": bool(stats["upper_stream"]),
                    "m2l_lds_slab": stats["m2l_lds_slab"],
+                   "p2p_threads_per_workgroup": stats["p2p_threads"],
                    "step": ("forward (potentials and field) + backward (vector-Jacobian product of "
                             "sum w_i f_i, w ~ N(0,1))") if args.backward else "evaluate"},
         "roofline": roofline,
@@ -365,6 +394,7 @@ def main():
                 "unit": "TFLOP/s", "frac": p2p_tflops / PEAK_FP32_TFLOPS, "ms_per_launch": p2p_ms,
                 "pairs_per_launch": p2p_pairs, "flop_per_pair": flop_pair,
                 "d2t_ms_per_launch": None if fused else l2p_ms, "d2t_pairs_per_launch": d2t_pairs},
+        "p2p_alone": p2p_alone,
         "stages_ms": stages,
         "setup_s": t_setup,
         "cpu_baseline": None,

@@ -303,7 +303,11 @@ kifmm_status kifmm_plan_get_stage_times(kifmm_plan plan, double* ms, int64_t* co
  *   stats[9] = 1 if the levels above the leaves run on the plan's second stream
  *              beside the leaf level's VLI (chosen by timing at plan creation),
  *   stats[10] = k per LDS slab of the staged M2L sources in the blocked forms
- *              (0 for the other forms).
+ *              (0 for the other forms),
+ *   stats[11] = threads per workgroup of the one-RHS leaf kernels (U-list sum
+ *              and D2T): 256 or 320, chosen by timing at plan creation when the
+ *              U-list sum runs on its own stream, else 320; 0 when nrhs > 1.
+ *              The results do not depend on it.
  * At most `count` entries are written.  KIFMM_E_INVALID if plan or stats is
  * null or count is negative. */
 kifmm_status kifmm_plan_get_stats(kifmm_plan plan, int64_t* stats, int count);

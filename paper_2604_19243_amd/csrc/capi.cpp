@@ -227,9 +227,10 @@ kifmm_status kifmm_plan_get_stats(kifmm_plan plan, int64_t* stats, int count) {
     const bool up = p->up && p->up_on;
     const int64_t stage_pairs = up ? p->m2l_pairs_leaf : p->m2l_pairs;
     const int64_t slab = form == 0 ? p->m2l_lds_ld - 4 : form == 3 ? 32 : 0;
-    const int64_t v[11] = {p->p2p_pairs, p->m2l_pairs, p->far ? p->slots[p->L] : 0, p->m2l_targets, p->k, p->n,
-                           p->nrhs, form, stage_pairs, up ? 1 : 0, slab};
-    for (int i = 0; i < count && i < 11; ++i) stats[i] = v[i];
+    const int64_t threads = p->nrhs == 1 ? p->p2p_threads : 0;
+    const int64_t v[12] = {p->p2p_pairs, p->m2l_pairs, p->far ? p->slots[p->L] : 0, p->m2l_targets, p->k, p->n,
+                           p->nrhs, form, stage_pairs, up ? 1 : 0, slab, threads};
+    for (int i = 0; i < count && i < 12; ++i) stats[i] = v[i];
   });
 }
 

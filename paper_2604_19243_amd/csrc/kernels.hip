@@ -919,11 +919,11 @@ bool launch_p2m(const float4* pts, const int* start, const int* leaves, const fl
 //
 // Dynamic LDS: [cap] float4 sources, [n] float4 surface points, [8 n] floats d.
 //
-// Five waves per workgroup: at 30.5 points per leaf a parent's siblings hold
-// 244 targets on average (Poisson), so 320 threads take nearly every parent in
-// one pass, where 256 left about a fifth of the workgroups a second pass on a
-// few lanes while the whole workgroup kept its LDS.
-constexpr int kP2PThreads = 320;
+// Four or five waves per workgroup (the plan's choice).  At 30.5 points per
+// leaf a parent's siblings hold 244 targets on average (Poisson): 320 threads
+// take nearly every parent in one pass, where 256 leave about a fifth of the
+// workgroups a second pass on a few lanes while the workgroup keeps its LDS.
+// Each target's sums do not depend on the choice.
 extern __shared__ float4 s_p2p[];
 
 __device__ __forceinline__ void p2p_pair(float xx, float xy, float xz, float4 y, float& phi, float& gx, float& gy,
@@ -955,7 +955,7 @@ __device__ __forceinline__ void p2p_pair_masked(float xx, float xy, float xz, fl
 // order to `near` (phi, grad) for a later MODE 2 launch; MODE 2: far field only,
 // added to `near` and written to input order.
 template <int MODE>
-__global__ __launch_bounds__(kP2PThreads) void k_p2p(const float4* __restrict__ pts, const int* __restrict__ start,
+__global__ __launch_bounds__(kP2PMaxThreads) void k_p2p(const float4* __restrict__ pts, const int* __restrict__ start,
                                              const int* __restrict__ blk, int group_slots, int cap,
                                              const float4* __restrict__ centers, const float* __restrict__ surf,
                                              int n, float alpha, const float* __restrict__ d, int ldd, int far,
@@ -995,7 +995,7 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(const float4* __restrict__ 
   const bool in_lds = total <= cap;
   if (kNear && in_lds) {
     const float big = 3.402823466e38f;
-    for (int i = tid; i < total; i += kP2PThreads) {
+    for (int i = tid; i < total; i += (int)blockDim.x) {
       int lo = 0, hi = 64;  // entry e with s_off[e] <= i < s_off[e + 1]
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -1008,9 +1008,9 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(const float4* __restrict__ 
   }
   const float sc = alpha * centers[2 * c0].w;
   if (kFar && far) {
-    for (int m = tid; m < n; m += kP2PThreads)
+    for (int m = tid; m < n; m += (int)blockDim.x)
       s_de[m] = make_float4(sc * surf[3 * m], sc * surf[3 * m + 1], sc * surf[3 * m + 2], 0.f);
-    for (int i = tid; i < group_slots * n; i += kP2PThreads) {
+    for (int i = tid; i < group_slots * n; i += (int)blockDim.x) {
       const int o = i / n, m = i - o * n;
       s_d[o * n + m] = d[(size_t)(c0 + o) * ldd + m];
     }
@@ -1018,7 +1018,7 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(const float4* __restrict__ 
   __syncthreads();
 
   const int t0 = s_cs[0], t1 = s_cs[group_slots];
-  for (int tb = t0; tb < t1; tb += kP2PThreads) {
+  for (int tb = t0; tb < t1; tb += (int)blockDim.x) {
     const int ti = tb + tid;
     if (ti >= t1) break;
     int o = 0;
@@ -1111,8 +1111,9 @@ size_t p2p_lds_bytes(int cap, int n) { return (size_t)cap * 16 + (size_t)n * 16 
 
 bool launch_p2p(int mode, const float4* pts, const int* start, const int* blk, int ngroups, int group_slots, int cap,
                 const float4* centers, const float* surf, int n, float alpha, const float* d, int ldd, int far,
-                const int* order, float* pot, float* grad, float4* near, hipStream_t s) {
+                const int* order, float* pot, float* grad, float4* near, int threads, hipStream_t s) {
   if (ngroups <= 0) return true;
+  if (threads != 256 && threads != kP2PMaxThreads) return false;
   const int c = mode == 2 ? 0 : cap;
   const size_t lds = mode == 1 ? (size_t)cap * 16 : p2p_lds_bytes(c, n);  // near-only: sources alone
   auto launch = [&](auto kernel, size_t& attr) {
@@ -1122,7 +1123,7 @@ bool launch_p2p(int mode, const float4* pts, const int* start, const int* blk, i
         return false;
       attr = lds;
     }
-    hipLaunchKernelGGL(kernel, dim3(ngroups), dim3(kP2PThreads), lds, s, pts, start, blk, group_slots, c, centers,
+    hipLaunchKernelGGL(kernel, dim3(ngroups), dim3(threads), lds, s, pts, start, blk, group_slots, c, centers,
                        surf, n, alpha, d, ldd, far, order, pot, grad, near);
     return true;
   };

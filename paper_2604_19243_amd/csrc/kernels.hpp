@@ -63,10 +63,12 @@ bool launch_p2m(const float4* pts, const int* start, const int* leaves, const fl
 size_t p2p_lds_bytes(int cap, int n);
 // mode 0: near + far field fused, written to input order; mode 1: near field only,
 // written in sorted order to `near` (phi, grad); mode 2: far field added to `near`,
-// written to input order.
+// written to input order.  threads: 256 or kP2PMaxThreads per workgroup (false
+// otherwise); the results do not depend on it.
+constexpr int kP2PMaxThreads = 320;
 bool launch_p2p(int mode, const float4* pts, const int* start, const int* blk, int ngroups, int group_slots, int cap,
                 const float4* centers, const float* surf, int n, float alpha, const float* d, int ldd, int far,
-                const int* order, float* pot, float* grad, float4* near, hipStream_t s);
+                const int* order, float* pot, float* grad, float4* near, int threads, hipStream_t s);
 
 
 // Multi-RHS leaf kernels (R = 2, 4, 8, 16, 32; potentials only).  qs: sorted

@@ -696,13 +696,19 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
       hip_check(hipMemset(P->d_chat, 0, sizeof(float) * (size_t)n_red), "chat reset");
       hip_check(hipDeviceSynchronize(), "M2L autotune");
     }
-    if (P->up && (flags & KIFMM_UPPER_STREAM)) {
-      P->up_on = true;
-    } else if (P->up) {
-      // Autotuning of the second stream: the levels above the leaves beside the leaf
-      // level's VLI pay off where U2U is latency-bound (few boxes per level) and cost
-      // L2 locality where the two VLI launches share the XCDs.  Whole evaluates of
-      // zero charges, each way: one warm-up and the best of two timed.
+    // Autotuning of the stream layout, by whole evaluates of zero charges, each
+    // way: one warm-up and the best of two timed.
+    // * The second stream: the levels above the leaves beside the leaf level's VLI
+    //   pay off where U2U is latency-bound (few boxes per level) and cost L2
+    //   locality where the two VLI launches share the XCDs.
+    // * The leaf kernels' workgroup size (256 or 320 threads) sets how the U-list
+    //   sum shares the CUs with the far field: fewer, wider workgroups leave the far
+    //   field more of the GPU early and finish the U-list sums later.
+    // Neither choice changes any result bit.
+    const bool tune_up = P->up != nullptr && !(flags & KIFMM_UPPER_STREAM);
+    const bool tune_threads = P->side != nullptr;
+    if (P->up && (flags & KIFMM_UPPER_STREAM)) P->up_on = true;
+    if (tune_up || tune_threads) {
       float *q = nullptr, *pot = nullptr, *grad = nullptr;
       hip_check(hipMalloc(&q, sizeof(float) * (size_t)T.n), "autotune charges");
       hip_check(hipMemset(q, 0, sizeof(float) * (size_t)T.n), "autotune charges");
@@ -711,26 +717,40 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device) {
       hipEvent_t e0, e1;
       hip_check(hipEventCreate(&e0), "hipEventCreate");
       hip_check(hipEventCreate(&e1), "hipEventCreate");
+      const bool up_fixed = P->up_on;
+      double best_all = -1.0;
+      int best_on = up_fixed ? 1 : 0, best_th = kP2PMaxThreads;
       for (int on = 0; on < 2; ++on) {
-        P->up_on = on == 1;
-        float best = 0.f;
-        for (int rep = 0; rep < 3; ++rep) {
-          hip_check(hipEventRecord(e0, nullptr), "hipEventRecord");
-          evaluate_plan(P, q, pot, grad, nullptr);
-          hip_check(hipEventRecord(e1, nullptr), "hipEventRecord");
-          hip_check(hipEventSynchronize(e1), "stream autotune");
-          float ms = 0.f;
-          hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-          if (rep == 1 || (rep > 1 && ms < best)) best = ms;
+        if (!tune_up && on != (up_fixed ? 1 : 0)) continue;
+        for (int th = 0; th < 2; ++th) {
+          if (!tune_threads && th == 0) continue;
+          P->up_on = on == 1;
+          P->p2p_threads = th ? kP2PMaxThreads : 256;
+          float best = 0.f;
+          for (int rep = 0; rep < 3; ++rep) {
+            hip_check(hipEventRecord(e0, nullptr), "hipEventRecord");
+            evaluate_plan(P, q, pot, grad, nullptr);
+            hip_check(hipEventRecord(e1, nullptr), "hipEventRecord");
+            hip_check(hipEventSynchronize(e1), "stream autotune");
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            if (rep == 1 || (rep > 1 && ms < best)) best = ms;
+          }
+          P->tune_ms[on][th] = best;
+          if (best_all < 0.0 || best < best_all) {
+            best_all = best;
+            best_on = on;
+            best_th = P->p2p_threads;
+          }
         }
-        P->up_tune_ms[on] = best;
       }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
       (void)hipFree(q);
       (void)hipFree(pot);
       if (grad) (void)hipFree(grad);
-      P->up_on = P->up_tune_ms[1] < P->up_tune_ms[0];
+      P->up_on = best_on == 1;
+      P->p2p_threads = best_th;
       hip_check(hipDeviceSynchronize(), "stream autotune");
     }
   } catch (...) {
@@ -841,7 +861,7 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
     P->stage_begin(KIFMM_STAGE_P2P, P->side);
     if (!launch_p2p(1, P->d_pts, P->d_start, P->d_blk, (int)P->n_groups, P->group_slots, P->p2p_cap, P->d_centers,
                     P->d_surf, P->n, (float)kAlphaOuter, d_leaf, P->nst, 0, P->d_order, nullptr, nullptr, P->d_near,
-                    P->side))
+                    P->p2p_threads, P->side))
       fail(KIFMM_E_DEVICE, "leaf kernel configuration not available");
     P->stage_end(KIFMM_STAGE_P2P, P->side);
     hip_check(hipEventRecord(P->ev_join, P->side), "hipEventRecord");
@@ -956,7 +976,8 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
     hip_check(hipStreamWaitEvent(st, P->ev_join, 0), "hipStreamWaitEvent");
     P->stage_begin(KIFMM_STAGE_L2P, st);
     if (!launch_p2p(2, P->d_pts, P->d_start, P->d_blk, (int)P->n_groups, P->group_slots, P->p2p_cap, P->d_centers,
-                    P->d_surf, P->n, (float)kAlphaOuter, d_leaf, P->nst, 1, P->d_order, pot, grad, P->d_near, st))
+                    P->d_surf, P->n, (float)kAlphaOuter, d_leaf, P->nst, 1, P->d_order, pot, grad, P->d_near,
+                    P->p2p_threads, st))
       fail(KIFMM_E_DEVICE, "leaf kernel configuration not available");
     P->stage_end(KIFMM_STAGE_L2P, st);
   } else if (R > 1) {
@@ -972,7 +993,7 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
     P->stage_begin(KIFMM_STAGE_P2P, st);
     if (!launch_p2p(0, P->d_pts, P->d_start, P->d_blk, (int)P->n_groups, P->group_slots, P->p2p_cap, P->d_centers,
                     P->d_surf, P->n, (float)kAlphaOuter, d_leaf, P->nst, P->far ? 1 : 0, P->d_order, pot, grad,
-                    nullptr, st))
+                    nullptr, P->p2p_threads, st))
       fail(KIFMM_E_DEVICE, "leaf kernel configuration not available");
     P->stage_end(KIFMM_STAGE_P2P, st);
   }

@@ -62,7 +62,8 @@ struct Plan : Object {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipStream_t up = nullptr;              // levels above the leaves: U2U, compression, VLI, downward pass (default priority)
   bool up_on = true;                     // use it (timed against not using it at plan creation)
-  double up_tune_ms[2] = {0.0, 0.0};     // evaluate without / with the second stream (ms)
+  int p2p_threads = kP2PMaxThreads;      // leaf-kernel workgroup size (timed against 256 at plan creation)
+  double tune_ms[2][2] = {};             // evaluate [without / with the second stream][256 / 320 leaf threads] (ms)
   hipEvent_t ev_up0 = nullptr, ev_up1 = nullptr;
   float4* d_near = nullptr;              // ULI result in sorted order (phi, grad)
   bool m2l_wide = false;                 // nrhs = 32, FP32: per-target V lists with the right-hand sides as columns

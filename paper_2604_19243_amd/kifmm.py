@@ -223,10 +223,10 @@ def kifmm_plan_get_stage_times(plan, reset=True):
 
 
 def kifmm_plan_get_stats(plan):
-    out = np.zeros(11, dtype=np.int64)
-    _check(library().kifmm_plan_get_stats(plan, _host_ptr(out), 11))
+    out = np.zeros(12, dtype=np.int64)
+    _check(library().kifmm_plan_get_stats(plan, _host_ptr(out), 12))
     keys = ["p2p_pairs", "m2l_pairs", "leaf_slots", "m2l_targets", "k", "n", "nrhs", "m2l_form", "m2l_stage_pairs",
-            "upper_stream", "m2l_lds_slab"]
+            "upper_stream", "m2l_lds_slab", "p2p_threads"]
     return dict(zip(keys, (int(v) for v in out)))
 
 

@@ -78,7 +78,9 @@ def test_upper_levels_stream_flags(rank):
     out = {}
     for name, fl in (("on", kifmm.KIFMM_UPPER_STREAM), ("off", kifmm.KIFMM_NO_UPPER_STREAM)):
         phi, g, f = gpu_evaluate(x, s, 4, 6, UNIT, rank=rank, m2l="blocked", flags=fl)
-        assert kifmm.kifmm_plan_get_stats(f.plan)["upper_stream"] == (1 if name == "on" else 0)
+        st = kifmm.kifmm_plan_get_stats(f.plan)
+        assert st["upper_stream"] == (1 if name == "on" else 0)
+        assert st["p2p_threads"] in (256, 320)   # timed at plan creation; no result bit depends on it
         f.close()
         out[name] = (phi, g)
     np.testing.assert_array_equal(out["on"][0], out["off"][0])
