@@ -213,3 +213,22 @@ def test_binding_constants_match_the_header():
                  "KIFMM_VJP", "KIFMM_M2L_BLOCKED", "KIFMM_M2L_GATHER", "KIFMM_UPPER_STREAM", "KIFMM_NO_UPPER_STREAM",
                  "KIFMM_E_INVALID", "KIFMM_E_DEVICE"):
         assert name in found and hasattr(kifmm, name), name
+
+
+def test_parent_target_counts_of_the_1m_workload():
+    # The leaf kernels take one parent (8 sibling leaves) per workgroup. On the 1M-point, depth-5
+    # workload a parent holds 244 targets on average: about a fifth exceed 256 (a second pass with
+    # 256 threads) and none exceeds 320 (one pass with 320 threads).
+    w = workloads.WORKLOADS["cube1m_p6_d5"]
+    x, _ = workloads.make(w)
+    t = kifmm.kifmm_tree_build(x, w.depth, w.cube[0] + (w.cube[1],))
+    try:
+        ijk = np.asarray(kifmm.kifmm_tree_get_leaf_coords(t, len(x))).astype(np.int64)
+    finally:
+        kifmm.kifmm_tree_destroy(t)
+    side = 1 << (w.depth - 1)
+    par = ijk >> 1
+    counts = np.bincount((par[:, 0] * side + par[:, 1]) * side + par[:, 2], minlength=side ** 3)
+    assert counts.sum() == w.n and abs(counts.mean() - w.n / side ** 3) < 1e-9
+    assert 0.15 < (counts > 256).mean() < 0.30
+    assert counts.max() <= 320
