@@ -196,7 +196,9 @@ kifmm_status kifmm_ops_destroy(kifmm_ops ops);
  * evaluates both ways and keeps the faster (stats[9] reports the choice);
  * KIFMM_UPPER_STREAM forces the second stream, KIFMM_NO_UPPER_STREAM forbids
  * it (at most one of the two; either is ignored where the second stream does
- * not apply). */
+ * not apply).  Where the U-list sum has a stream of its own, the same timing
+ * also chooses 256 or 320 threads per leaf-kernel workgroup (stats[11]); no
+ * result bit depends on that choice. */
 #define KIFMM_UPPER_STREAM 256u
 #define KIFMM_NO_UPPER_STREAM 512u
 
