@@ -18,11 +18,18 @@ from . import kifmm
 class DifferentiableFMM:
     """Tree, operators and a plan with KIFMM_VJP for one point set on one device."""
 
-    def __init__(self, points, depth, p, cube=None, eps_pinv=1e-7, eps_svd=1e-6, m2l_flags=0, device=0):
-        pts = points.detach().cpu().numpy() if isinstance(points, torch.Tensor) else np.asarray(points)
+    def __init__(self, points, depth, p, cube=None, eps_pinv=1e-7, eps_svd=1e-6, m2l_flags=0, stream=None):
+        """points: host [n,3] float32 array, or a [n,3] float32 device tensor (the tree is then built
+        from device memory, on `stream`, and the plan lives on that tensor's device)."""
+        if isinstance(points, torch.Tensor):
+            pts = points.detach().to(torch.float32).contiguous()
+            if not pts.is_cuda:
+                pts = pts.numpy()
+        else:
+            pts = np.ascontiguousarray(points, dtype=np.float32)
         flags = kifmm.KIFMM_POTENTIAL | kifmm.KIFMM_GRADIENT | kifmm.KIFMM_VJP | m2l_flags
         self.fmm = kifmm.FMM(pts, depth, p, cube=cube, eps_pinv=eps_pinv, eps_svd=eps_svd, flags=flags,
-                             device=device)
+                             stream=stream)
         self.n = self.fmm.n
 
     def close(self):

@@ -1,8 +1,19 @@
-// The extern "C" boundary: status codes, thread-local messages, handle checks.
+// The extern "C" boundary: status codes, thread-local messages and the handle
+// registry.
+//
+// Handles are opaque identifiers (a serial number and a kind tag), not
+// pointers, and serial numbers are never reused: a destroyed handle, or a value
+// this library never returned, is found missing from the registry and the
+// call fails with KIFMM_E_STATE instead of touching freed memory.  A call takes
+// a reference on the object for its duration, so an object destroyed by
+// another thread meanwhile stays alive until the call returns.
 #include <algorithm>
+#include <atomic>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 
 #include "common.hpp"
 #include "plan.hpp"
@@ -40,17 +51,69 @@ kifmm_status guarded(F&& body) {
   }
 }
 
-Tree* as_tree(kifmm_tree h) {
-  require(h != nullptr, "null tree handle");
-  return reinterpret_cast<Tree*>(h);
+enum Kind : uint64_t { kTree = 1, kOps = 2, kPlan = 3 };
+const char* kind_name(Kind k) { return k == kTree ? "tree" : k == kOps ? "ops" : "plan"; }
+
+// Live handles: value (serial << 4 | kind) -> object.  The registry holds the
+// caller's reference of each object.
+struct Registry {
+  std::mutex mu;
+  std::unordered_map<uint64_t, Object*> live;
+  uint64_t next = 1;
+};
+Registry& registry() {
+  static Registry r;
+  return r;
 }
-Ops* as_ops(kifmm_ops h) {
-  require(h != nullptr, "null ops handle");
-  return reinterpret_cast<Ops*>(h);
+
+void* add_handle(Kind k, Object* obj) {
+  Registry& r = registry();
+  std::lock_guard<std::mutex> lock(r.mu);
+  const uint64_t h = (r.next++ << 4) | (uint64_t)k;
+  r.live.emplace(h, obj);
+  return reinterpret_cast<void*>((uintptr_t)h);
 }
-Plan* as_plan(kifmm_plan h) {
-  require(h != nullptr, "null plan handle");
-  return reinterpret_cast<Plan*>(h);
+
+// A reference on a live object of kind K for the duration of one call.
+template <class T>
+struct Held {
+  T* p = nullptr;
+  Held(const Held&) = delete;
+  Held& operator=(const Held&) = delete;
+  explicit Held(T* q) : p(q) {}
+  Held(Held&& o) noexcept : p(o.p) { o.p = nullptr; }
+  ~Held() { release(p); }
+  T* operator->() const { return p; }
+  T& operator*() const { return *p; }
+};
+
+template <class T>
+Held<T> hold(const void* handle, Kind k) {
+  require(handle != nullptr, std::string("null ") + kind_name(k) + " handle");
+  Registry& r = registry();
+  std::lock_guard<std::mutex> lock(r.mu);
+  const uint64_t h = (uint64_t)(uintptr_t)handle;
+  auto it = r.live.find(h);
+  if ((h & 15u) != (uint64_t)k || it == r.live.end())
+    fail(KIFMM_E_STATE, std::string("the ") + kind_name(k) + " handle is destroyed or was not made by this library");
+  it->second->refs.fetch_add(1);
+  return Held<T>(static_cast<T*>(it->second));
+}
+
+void drop_handle(const void* handle, Kind k) {
+  require(handle != nullptr, std::string("null ") + kind_name(k) + " handle");
+  Object* obj = nullptr;
+  {
+    Registry& r = registry();
+    std::lock_guard<std::mutex> lock(r.mu);
+    const uint64_t h = (uint64_t)(uintptr_t)handle;
+    auto it = r.live.find(h);
+    if ((h & 15u) != (uint64_t)k || it == r.live.end())
+      fail(KIFMM_E_STATE, std::string("the ") + kind_name(k) + " handle is already destroyed or was not made by this library");
+    obj = it->second;
+    r.live.erase(it);
+  }
+  release(obj);
 }
 
 void copy_out(const double* src, int64_t count, double* out, int64_t capacity) {
@@ -59,7 +122,13 @@ void copy_out(const double* src, int64_t count, double* out, int64_t capacity) {
   std::memcpy(out, src, count * sizeof(double));
 }
 
+std::atomic<int64_t> g_device_limit{0};
+
 }  // namespace
+
+namespace kifmm {
+int64_t device_memory_limit() { return g_device_limit.load(); }
+}  // namespace kifmm
 
 extern "C" {
 
@@ -67,22 +136,33 @@ int kifmm_abi_version(void) { return KIFMM_ABI_VERSION; }
 
 const char* kifmm_last_error(void) { return last_error_cstr(); }
 
-kifmm_status kifmm_tree_build(const float* xyz, int64_t n, int depth, const double* cube, kifmm_tree* out) {
+kifmm_status kifmm_tree_build(const float* xyz, int64_t n, int depth, const double* cube, void* stream,
+                              kifmm_tree* out) {
   return guarded([&] {
     require(out != nullptr, "out is null");
     *out = nullptr;
-    *out = reinterpret_cast<kifmm_tree>(build_tree(xyz, n, depth, cube));
+    Tree* t = build_tree_device(xyz, n, depth, cube, (hipStream_t)stream);
+    *out = reinterpret_cast<kifmm_tree>(add_handle(kTree, t));
   });
 }
 
-kifmm_status kifmm_tree_get_info(kifmm_tree tree, kifmm_tree_info* out) {
+kifmm_status kifmm_tree_build_host(const float* xyz, int64_t n, int depth, const double* cube, kifmm_tree* out) {
   return guarded([&] {
-    const Tree* t = as_tree(tree);
+    require(out != nullptr, "out is null");
+    *out = nullptr;
+    Tree* t = build_tree(xyz, n, depth, cube);
+    *out = reinterpret_cast<kifmm_tree>(add_handle(kTree, t));
+  });
+}
+
+kifmm_status kifmm_tree_stats_get(kifmm_tree tree, kifmm_tree_stats* out) {
+  return guarded([&] {
+    Held<Tree> t = hold<Tree>(tree, kTree);
     require(out != nullptr, "out is null");
     std::memset(out, 0, sizeof(*out));
-    out->n_points = t->n;
+    out->n = t->n;
     out->depth = t->depth;
-    out->max_leaf_points = t->max_leaf;
+    out->max_leaf = t->max_leaf;
     out->nonempty_leaves = (int64_t)t->keys[t->depth].size();
     for (int l = 0; l <= t->depth; ++l) out->nonempty_boxes[l] = (int64_t)t->keys[l].size();
     for (int d = 0; d < 3; ++d) out->center[d] = t->center[d];
@@ -92,7 +172,7 @@ kifmm_status kifmm_tree_get_info(kifmm_tree tree, kifmm_tree_info* out) {
 
 kifmm_status kifmm_tree_get_order(kifmm_tree tree, int64_t* order) {
   return guarded([&] {
-    const Tree* t = as_tree(tree);
+    Held<Tree> t = hold<Tree>(tree, kTree);
     require(order != nullptr, "order is null");
     std::copy(t->order.begin(), t->order.end(), order);
   });
@@ -100,27 +180,29 @@ kifmm_status kifmm_tree_get_order(kifmm_tree tree, int64_t* order) {
 
 kifmm_status kifmm_tree_get_leaf_coords(kifmm_tree tree, int32_t* ijk) {
   return guarded([&] {
-    const Tree* t = as_tree(tree);
+    Held<Tree> t = hold<Tree>(tree, kTree);
     require(ijk != nullptr, "ijk is null");
     std::copy(t->ijk.begin(), t->ijk.end(), ijk);
   });
 }
 
 kifmm_status kifmm_tree_destroy(kifmm_tree tree) {
-  return guarded([&] { release(as_tree(tree)); });
+  return guarded([&] { drop_handle(tree, kTree); });
 }
 
-kifmm_status kifmm_ops_precompute(int p, double eps_pinv, double eps_svd, int rank, kifmm_ops* out) {
+kifmm_status kifmm_ops_precompute(int p, double alpha_inner, double alpha_outer, double eps_pinv, double eps_svd,
+                                  kifmm_ops* out) {
   return guarded([&] {
     require(out != nullptr, "out is null");
     *out = nullptr;
-    *out = reinterpret_cast<kifmm_ops>(precompute_ops(p, eps_pinv, eps_svd, rank));
+    Ops* o = precompute_ops(p, alpha_inner, alpha_outer, eps_pinv, eps_svd);
+    *out = reinterpret_cast<kifmm_ops>(add_handle(kOps, o));
   });
 }
 
 kifmm_status kifmm_ops_get_info(kifmm_ops ops, kifmm_ops_info* out) {
   return guarded([&] {
-    const Ops* o = as_ops(ops);
+    Held<Ops> o = hold<Ops>(ops, kOps);
     require(out != nullptr, "out is null");
     std::memset(out, 0, sizeof(*out));
     out->p = o->p;
@@ -130,14 +212,14 @@ kifmm_status kifmm_ops_get_info(kifmm_ops ops, kifmm_ops_info* out) {
     out->n_m2l_offsets = kNumOffsets;
     out->eps_pinv = o->eps_pinv;
     out->eps_svd = o->eps_svd;
-    out->alpha_inner = kAlphaInner;
-    out->alpha_outer = kAlphaOuter;
+    out->alpha_inner = o->alpha_inner;
+    out->alpha_outer = o->alpha_outer;
   });
 }
 
 kifmm_status kifmm_ops_get_matrix(kifmm_ops ops, int which, int index, double* out, int64_t capacity) {
   return guarded([&] {
-    const Ops* o = as_ops(ops);
+    Held<Ops> o = hold<Ops>(ops, kOps);
     const int64_t n = o->n, k = o->k;
     switch (which) {
       case KIFMM_OP_SURFACE: copy_out(o->surf.data(), 3 * n, out, capacity); break;
@@ -168,36 +250,59 @@ kifmm_status kifmm_ops_get_matrix(kifmm_ops ops, int which, int index, double* o
 }
 
 kifmm_status kifmm_ops_destroy(kifmm_ops ops) {
-  return guarded([&] { release(as_ops(ops)); });
+  return guarded([&] { drop_handle(ops, kOps); });
 }
 
-kifmm_status kifmm_plan_create(kifmm_tree tree, kifmm_ops ops, int nrhs, unsigned flags, int device,
+kifmm_status kifmm_plan_create(kifmm_tree tree, kifmm_ops ops, int nrhs, unsigned flags, void* stream,
                                kifmm_plan* out) {
   return guarded([&] {
     require(out != nullptr, "out is null");
     *out = nullptr;
-    *out = reinterpret_cast<kifmm_plan>(create_plan(as_tree(tree), as_ops(ops), nrhs, flags, device));
+    Held<Tree> t = hold<Tree>(tree, kTree);
+    Held<Ops> o = hold<Ops>(ops, kOps);
+    Plan* p = create_plan(t.p, o.p, nrhs, flags, (hipStream_t)stream);
+    *out = reinterpret_cast<kifmm_plan>(add_handle(kPlan, p));
+  });
+}
+
+kifmm_status kifmm_plan_workspace_bytes(kifmm_tree tree, kifmm_ops ops, int nrhs, unsigned flags, int64_t* bytes) {
+  return guarded([&] {
+    require(bytes != nullptr, "bytes is null");
+    Held<Tree> t = hold<Tree>(tree, kTree);
+    Held<Ops> o = hold<Ops>(ops, kOps);
+    *bytes = plan_workspace_bytes(t.p, o.p, nrhs, flags);
+  });
+}
+
+kifmm_status kifmm_set_device_memory_limit(int64_t bytes) {
+  return guarded([&] {
+    require(bytes >= 0, "the device memory limit must be >= 0 (0: no limit)");
+    g_device_limit.store(bytes);
   });
 }
 
 kifmm_status kifmm_evaluate(kifmm_plan plan, const float* charges, float* potential, float* gradient, void* stream) {
-  return guarded([&] { evaluate_plan(as_plan(plan), charges, potential, gradient, (hipStream_t)stream); });
+  return guarded([&] {
+    Held<Plan> p = hold<Plan>(plan, kPlan);
+    evaluate_plan(p.p, charges, potential, gradient, (hipStream_t)stream);
+  });
 }
 
 kifmm_status kifmm_evaluate_vjp(kifmm_plan plan, const float* charges, const float* weights, const float* field,
                                 float* grad_charges, float* grad_points, void* stream) {
   return guarded([&] {
-    evaluate_vjp(as_plan(plan), charges, weights, field, grad_charges, grad_points, (hipStream_t)stream);
+    Held<Plan> p = hold<Plan>(plan, kPlan);
+    evaluate_vjp(p.p, charges, weights, field, grad_charges, grad_points, (hipStream_t)stream);
   });
 }
 
 kifmm_status kifmm_plan_destroy(kifmm_plan plan) {
-  return guarded([&] { release(as_plan(plan)); });
+  return guarded([&] { drop_handle(plan, kPlan); });
 }
 
 kifmm_status kifmm_plan_set_timing(kifmm_plan plan, int enable) {
   return guarded([&] {
-    Plan* p = as_plan(plan);
+    Held<Plan> p = hold<Plan>(plan, kPlan);
     if (!enable && p->timing) p->collect_times();
     p->timing = enable != 0;
   });
@@ -205,7 +310,7 @@ kifmm_status kifmm_plan_set_timing(kifmm_plan plan, int enable) {
 
 kifmm_status kifmm_plan_get_stage_times(kifmm_plan plan, double* ms, int64_t* counts, int reset) {
   return guarded([&] {
-    Plan* p = as_plan(plan);
+    Held<Plan> p = hold<Plan>(plan, kPlan);
     require(ms != nullptr && counts != nullptr, "output is null");
     p->collect_times();
     for (int s = 0; s < KIFMM_N_STAGES; ++s) {
@@ -221,21 +326,19 @@ kifmm_status kifmm_plan_get_stage_times(kifmm_plan plan, double* ms, int64_t* co
 
 kifmm_status kifmm_plan_get_stats(kifmm_plan plan, int64_t* stats, int count) {
   return guarded([&] {
-    const Plan* p = as_plan(plan);
+    Held<Plan> p = hold<Plan>(plan, kPlan);
     require(stats != nullptr && count >= 0, "stats is null or count is negative");
-    const int64_t form = p->m2l_pieces ? 3 : p->m2l_wide ? 2 : p->m2l_gather ? 1 : 0;
-    const bool up = p->up && p->up_on;
-    const int64_t stage_pairs = up ? p->m2l_pairs_leaf : p->m2l_pairs;
-    const int64_t slab = form == 0 ? p->m2l_lds_ld - 4 : form == 3 ? 32 : 0;
-    const int64_t threads = p->nrhs == 1 ? p->p2p_threads : 0;
-    const int64_t v[12] = {p->p2p_pairs, p->m2l_pairs, p->far ? p->slots[p->L] : 0, p->m2l_targets, p->k, p->n,
-                           p->nrhs, form, stage_pairs, up ? 1 : 0, slab, threads};
-    for (int i = 0; i < count && i < 12; ++i) stats[i] = v[i];
+    int64_t v[KIFMM_N_STATS];
+    plan_stats(p.p, v);
+    for (int i = 0; i < count && i < KIFMM_N_STATS; ++i) stats[i] = v[i];
   });
 }
 
 kifmm_status kifmm_plan_read_density(kifmm_plan plan, int kind, int level, float* host_out, int64_t capacity) {
-  return guarded([&] { read_density(as_plan(plan), kind, level, host_out, capacity); });
+  return guarded([&] {
+    Held<Plan> p = hold<Plan>(plan, kPlan);
+    read_density(p.p, kind, level, host_out, capacity);
+  });
 }
 
 }  // extern "C"

@@ -79,6 +79,7 @@ struct Tree : Object {
 struct Ops : Object {
   int p = 0, n = 0, k = 0, kc = 0;      // surface size n, M2L rank k, pinv rank kc
   double eps_pinv = 0, eps_svd = 0;
+  double alpha_inner = 0, alpha_outer = 0;  // surface radius factors (equivalent/check)
   std::vector<double> surf;             // [n][3]
   std::vector<double> uc2e, dc2e;       // [n][n]
   std::vector<double> f1, f2;           // UC2E = f2 * f1: f1 = U_kc^T [kc][n], f2 = V_kc S^-1 [n][kc]
@@ -90,10 +91,9 @@ struct Ops : Object {
 };
 
 Tree* build_tree(const float* xyz, int64_t n, int depth, const double* cube);
-Ops* precompute_ops(int p, double eps_pinv, double eps_svd, int rank);
+// eps_svd > 0: relative compression cutoff; eps_svd = -k (k >= 1 integral): rank k.
+Ops* precompute_ops(int p, double alpha_inner, double alpha_outer, double eps_pinv, double eps_svd);
 
-constexpr double kAlphaInner = 1.05;
-constexpr double kAlphaOuter = 2.95;
 constexpr int kNumOffsets = 316;
 constexpr int kOffsetsPerOctant = 189;
 

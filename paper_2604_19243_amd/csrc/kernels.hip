@@ -390,26 +390,26 @@ __global__ __launch_bounds__(512) void k_m2l(const float* __restrict__ cores, in
   }
 }
 
+bool m2l_supported(int row_blocks, int ldk, int lds_ld) {
+  // lds_ld = slab + 4 floats, the slab a multiple of 8 k
+  return row_blocks >= 1 && row_blocks <= 8 && (ldk & 7) == 0 && lds_ld >= 12 && ((lds_ld - 4) & 7) == 0 &&
+         (size_t)216 * lds_ld * sizeof(float) <= kMaxDynamicLds;
+}
+
 bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int lds_ld, const M2LItem* items,
                 int nitems, const int* tgt_blk, const int* src_blk, const int* pair_offs, const float* uhat,
                 float* chat_part, long long part_stride, int nrhs, long long rhs_stride, hipStream_t s, bool upper) {
   if (nitems <= 0 || nrhs <= 0) return true;
-  // lds_ld = slab + 4 floats, the slab a multiple of 8 k
-  if (row_blocks < 1 || row_blocks > 8 || (ldk & 7) || lds_ld < 12 || ((lds_ld - 4) & 7)) return false;
+  if (!m2l_supported(row_blocks, ldk, lds_ld)) return false;
   const size_t lds = (size_t)216 * lds_ld * sizeof(float);
-  auto launch = [&](auto kernel, size_t& attr) {
-    if (lds > attr) {
-      if (hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds) != hipSuccess)
-        return false;
-      attr = lds;
-    }
-    hipLaunchKernelGGL(kernel, dim3(nitems, nrhs), dim3(64 * row_blocks), lds, s, cores, core_rows, ldk, lds_ld / 4,
-                       items, tgt_blk, src_blk, pair_offs, uhat, chat_part, part_stride, rhs_stride);
-    return true;
-  };
-  static size_t attr0 = 0, attr1 = 0;
-  return upper ? launch(&k_m2l<1>, attr1) : launch(&k_m2l<0>, attr0);
+  const dim3 grid(nitems, nrhs), block(64 * row_blocks);
+  if (upper)
+    hipLaunchKernelGGL(k_m2l<1>, grid, block, lds, s, cores, core_rows, ldk, lds_ld / 4, items, tgt_blk, src_blk,
+                       pair_offs, uhat, chat_part, part_stride, rhs_stride);
+  else
+    hipLaunchKernelGGL(k_m2l<0>, grid, block, lds, s, cores, core_rows, ldk, lds_ld / 4, items, tgt_blk, src_blk,
+                       pair_offs, uhat, chat_part, part_stride, rhs_stride);
+  return true;
 }
 
 // ------------------------------------------------------ M2L, gathered ---
@@ -736,30 +736,32 @@ __global__ __launch_bounds__(512) void k_m2l_bf16(const uint4* __restrict__ core
 
 int m2l_bf16_lds_ld16(int pieces) { return 4 * pieces + 1; }
 
+bool m2l_bf16_supported(int pieces, int row_blocks, int ldk) {
+  return row_blocks >= 1 && row_blocks <= 8 && (ldk & 15) == 0 && (pieces == 2 || pieces == 3) &&
+         (size_t)216 * m2l_bf16_lds_ld16(pieces) * 16 <= kMaxDynamicLds;
+}
+
 bool launch_m2l_bf16(int pieces, int row_blocks, const uint16_t* cores, size_t core_stride16, int ldk, int lds_ld16,
                      const M2LItem* items, int nitems, const int* tgt_blk, const int* src_blk, const int* pair_offs,
                      const float* uhat, float* chat_part, long long part_stride, int nrhs, long long rhs_stride,
                      hipStream_t s, bool upper) {
   if (nitems <= 0 || nrhs <= 0) return true;
-  if (row_blocks < 1 || row_blocks > 8 || (ldk & 15) || (pieces != 2 && pieces != 3) ||
-      lds_ld16 < m2l_bf16_lds_ld16(pieces))
-    return false;
+  if (!m2l_bf16_supported(pieces, row_blocks, ldk) || lds_ld16 < m2l_bf16_lds_ld16(pieces)) return false;
   const size_t lds = (size_t)216 * lds_ld16 * 16;
-  auto launch = [&](auto kernel, size_t& attr) {
-    if (lds > attr) {
-      if (hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds) != hipSuccess)
-        return false;
-      attr = lds;
-    }
-    hipLaunchKernelGGL(kernel, dim3(nitems, nrhs), dim3(64 * row_blocks), lds, s,
-                       reinterpret_cast<const uint4*>(cores), core_stride16, ldk, lds_ld16, items, tgt_blk, src_blk,
-                       pair_offs, uhat, chat_part, part_stride, rhs_stride);
-    return true;
-  };
-  static size_t attr[2][2] = {{0, 0}, {0, 0}};
-  if (pieces == 2) return upper ? launch(&k_m2l_bf16<2, 1>, attr[0][1]) : launch(&k_m2l_bf16<2, 0>, attr[0][0]);
-  return upper ? launch(&k_m2l_bf16<3, 1>, attr[1][1]) : launch(&k_m2l_bf16<3, 0>, attr[1][0]);
+  const dim3 grid(nitems, nrhs), block(64 * row_blocks);
+  const uint4* c = reinterpret_cast<const uint4*>(cores);
+#define KIFMM_M2L_BF16(NP, UP)                                                                                     \
+  hipLaunchKernelGGL((k_m2l_bf16<NP, UP>), grid, block, lds, s, c, core_stride16, ldk, lds_ld16, items, tgt_blk, \
+                     src_blk, pair_offs, uhat, chat_part, part_stride, rhs_stride)
+  if (pieces == 2) {
+    if (upper) KIFMM_M2L_BF16(2, 1);
+    else KIFMM_M2L_BF16(2, 0);
+  } else {
+    if (upper) KIFMM_M2L_BF16(3, 1);
+    else KIFMM_M2L_BF16(3, 0);
+  }
+#undef KIFMM_M2L_BF16
+  return true;
 }
 
 // Sum of the eight source positions' partial sums, in a fixed order:
@@ -871,6 +873,8 @@ __global__ __launch_bounds__(256) void k_p2m(const float4* __restrict__ pts, con
     if (m < n) q[(size_t)slot * ldq + m] = acc[r];
   }
 }
+
+bool p2m_supported(int n) { return n >= 1 && n <= 768; }
 
 bool launch_p2m(const float4* pts, const int* start, const int* leaves, const float4* centers, const float* surf, int n,
                 float alpha, float* q, int ldq, int nleaves, hipStream_t s) {
@@ -1109,29 +1113,175 @@ __global__ __launch_bounds__(kP2PMaxThreads) void k_p2p(const float4* __restrict
 
 size_t p2p_lds_bytes(int cap, int n) { return (size_t)cap * 16 + (size_t)n * 16 + (size_t)8 * n * 4; }
 
+bool p2p_supported(int threads, int cap, int n) {
+  return (threads == 256 || threads == kP2PMaxThreads) && cap >= 0 && p2p_lds_bytes(cap, n) <= kMaxDynamicLds;
+}
+
 bool launch_p2p(int mode, const float4* pts, const int* start, const int* blk, int ngroups, int group_slots, int cap,
                 const float4* centers, const float* surf, int n, float alpha, const float* d, int ldd, int far,
                 const int* order, float* pot, float* grad, float4* near, int threads, hipStream_t s) {
   if (ngroups <= 0) return true;
-  if (threads != 256 && threads != kP2PMaxThreads) return false;
+  if (!p2p_supported(threads, cap, n) || mode < 0 || mode > 2) return false;
   const int c = mode == 2 ? 0 : cap;
   const size_t lds = mode == 1 ? (size_t)cap * 16 : p2p_lds_bytes(c, n);  // near-only: sources alone
-  auto launch = [&](auto kernel, size_t& attr) {
-    if (lds > attr) {
-      if (hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds) != hipSuccess)
-        return false;
-      attr = lds;
+  const dim3 grid(ngroups), block(threads);
+#define KIFMM_P2P(M)                                                                                            \
+  hipLaunchKernelGGL(k_p2p<M>, grid, block, lds, s, pts, start, blk, group_slots, c, centers, surf, n, alpha, d, \
+                     ldd, far, order, pot, grad, near)
+  if (mode == 0) KIFMM_P2P(0);
+  else if (mode == 1) KIFMM_P2P(1);
+  else KIFMM_P2P(2);
+#undef KIFMM_P2P
+  return true;
+}
+
+// ---------------------------------------------------- leaf work queue ---
+// Fused D2T and ULI (Algorithm 1 steps 3b, 3c) as a persistent kernel over a
+// work queue of target tiles.  A tile is up to 64 consecutive targets of one
+// leaf, one per lane, so all lanes of a wave share the tile's U list and D2T
+// surface: every source is read at a wave-uniform address (scalar loads) and
+// used by the whole wave, and loop bounds are wave-uniform.  Tiles are ordered
+// longest first at plan creation; each wave takes the next tile from a counter
+// in device memory (cleared by k_clear_queue before the launch) until none is
+// left, so the waves finish together on trees whose leaves hold very different
+// numbers of points (points on a surface).
+//
+// The sums follow k_p2p exactly: a leaf's sources in sorted order, four per
+// step (a step past the leaf's end repeats its last source with charge zero,
+// which adds exactly zero), FP32 partials per source leaf and per 8 surface
+// points accumulated in FP64 in the same order, so the two kernels give the
+// same result bits.  MODE as in k_p2p.
+__global__ void k_clear_queue(int* queue, int n) {
+  if ((int)threadIdx.x < n) queue[threadIdx.x] = 0;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_leaf_queue(const float4* __restrict__ pts, const int* __restrict__ start,
+                                                    const int4* __restrict__ tiles, int ntiles, int* queue,
+                                                    const int* __restrict__ blk, int group_slots,
+                                                    const float4* __restrict__ centers,
+                                                    const float* __restrict__ surf, int n, float alpha,
+                                                    const float* __restrict__ d, int ldd, int far,
+                                                    const int* __restrict__ order, float* __restrict__ pot,
+                                                    float* __restrict__ grad, float4* __restrict__ near) {
+  constexpr bool kNear = MODE != 2;
+  constexpr bool kFar = MODE != 1;
+  // the downward-equivalent surface alpha r S_m of a leaf (every leaf has the same
+  // half-width), staged once per workgroup as k_p2p stages it
+  __shared__ float4 s_de[kMaxLeafSurface];
+  const int lane = threadIdx.x & 63;
+  if (kFar && far) {
+    const float sc = alpha * centers[0].w;
+    for (int m = threadIdx.x; m < n; m += blockDim.x)
+      s_de[m] = make_float4(sc * surf[3 * m], sc * surf[3 * m + 1], sc * surf[3 * m + 2], 0.f);
+    __syncthreads();
+  }
+  for (;;) {
+    int mine = 0;
+    if (lane == 0) mine = atomicAdd(queue, 1);
+    const int t = __builtin_amdgcn_readfirstlane(mine);
+    if (t >= ntiles) break;  // every wave leaves once the counter has passed the last tile
+    const int4 tile = tiles[t];
+    const int slot = tile.x, cnt = tile.z;
+    const int ti = tile.y + min(lane, cnt - 1);
+    const float4 x = pts[ti];
+    const int g = slot / group_slots, o = slot - g * group_slots;
+    const int bx = 1 + (o & 1), by = 1 + ((o >> 1) & 1), bz = 1 + ((o >> 2) & 1);
+    double aphi = 0.0, agx = 0.0, agy = 0.0, agz = 0.0;
+    if (kNear) {
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int ns = blk[(size_t)g * 64 + (bx + dx) + 4 * (by + dy) + 16 * (bz + dz)];
+            if (ns < 0) continue;
+            const int a = start[ns], b = start[ns + 1];
+            float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+            if (ns == slot) {
+              for (int j = a; j < b; j += 4) {
+                float4 y[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                  y[u] = pts[min(j + u, b - 1)];
+                  if (j + u >= b) y[u].w = 0.f;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) p2p_pair_masked(x.x, x.y, x.z, y[u], phi, gx, gy, gz);
+              }
+            } else {
+              for (int j = a; j < b; j += 4) {
+                float4 y[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                  y[u] = pts[min(j + u, b - 1)];
+                  if (j + u >= b) y[u].w = 0.f;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) p2p_pair(x.x, x.y, x.z, y[u], phi, gx, gy, gz);
+              }
+            }
+            aphi += phi;
+            agx += gx;
+            agy += gy;
+            agz += gz;
+          }
+    } else {
+      const float4 v = near[ti];
+      aphi = v.x;
+      agx = v.y;
+      agy = v.z;
+      agz = v.w;
     }
-    hipLaunchKernelGGL(kernel, dim3(ngroups), dim3(threads), lds, s, pts, start, blk, group_slots, c, centers,
-                       surf, n, alpha, d, ldd, far, order, pot, grad, near);
-    return true;
-  };
-  static size_t attr0 = 0, attr1 = 0, attr2 = 0;
-  if (mode == 0) return launch(&k_p2p<0>, attr0);
-  if (mode == 1) return launch(&k_p2p<1>, attr1);
-  if (mode == 2) return launch(&k_p2p<2>, attr2);
-  return false;
+    if (kFar && far) {
+      const float4 ch = centers[2 * slot], cl = centers[2 * slot + 1];
+      const float xx = (x.x - ch.x) - cl.x, xy = (x.y - ch.y) - cl.y, xz = (x.z - ch.z) - cl.z;
+      const float* dl = d + (size_t)slot * ldd;
+      for (int m0 = 0; m0 < n; m0 += 8) {
+        float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        const int m1 = min(m0 + 8, n);
+        for (int m = m0; m < m1; ++m) {
+          const float4 de = s_de[m];
+          p2p_pair(xx, xy, xz, make_float4(de.x, de.y, de.z, dl[m]), phi, gx, gy, gz);
+        }
+        aphi += phi;
+        agx += gx;
+        agy += gy;
+        agz += gz;
+      }
+    }
+    if (lane < cnt) {
+      if (MODE == 1) {
+        near[ti] = make_float4((float)aphi, (float)agx, (float)agy, (float)agz);
+      } else {
+        const int oi = order[ti];
+        if (pot) pot[oi] = (float)aphi;
+        if (grad) {
+          grad[3 * (size_t)oi] = (float)agx;
+          grad[3 * (size_t)oi + 1] = (float)agy;
+          grad[3 * (size_t)oi + 2] = (float)agz;
+        }
+      }
+    }
+  }
+}
+
+void launch_clear_queue(int* queue, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_queue, dim3(1), dim3(64), 0, s, queue, n);
+}
+
+bool launch_leaf_queue(int mode, const float4* pts, const int* start, const int4* tiles, int ntiles, int* queue,
+                       int grid, const int* blk, int group_slots, const float4* centers, const float* surf, int n,
+                       float alpha, const float* d, int ldd, int far, const int* order, float* pot, float* grad,
+                       float4* near, hipStream_t s) {
+  if (ntiles <= 0) return true;
+  if (grid < 1 || mode < 0 || mode > 2) return false;
+#define KIFMM_LEAF_QUEUE(M)                                                                                  \
+  hipLaunchKernelGGL(k_leaf_queue<M>, dim3(grid), dim3(256), 0, s, pts, start, tiles, ntiles, queue, blk,  \
+                     group_slots, centers, surf, n, alpha, d, ldd, far, order, pot, grad, near)
+  if (mode == 0) KIFMM_LEAF_QUEUE(0);
+  else if (mode == 1) KIFMM_LEAF_QUEUE(1);
+  else KIFMM_LEAF_QUEUE(2);
+#undef KIFMM_LEAF_QUEUE
+  return true;
 }
 
 // ---------------------------------------------------- multi-RHS leaves ---
@@ -1336,6 +1486,23 @@ bool launch_leaf_multi(int R, const float4* pts, const float* qs, const int* sta
     default: return false;
   }
 #undef KIFMM_LEAF_MULTI
+}
+
+// Dynamic LDS limit of every kernel that stages data in LDS, for the current
+// device.  Plans call this once per device (under a lock) before their first
+// launch; the launchers then only check their sizes against kMaxDynamicLds.
+hipError_t configure_kernels() {
+  const void* kernels[] = {
+      reinterpret_cast<const void*>(&k_m2l<0>),          reinterpret_cast<const void*>(&k_m2l<1>),
+      reinterpret_cast<const void*>(&k_m2l_bf16<2, 0>), reinterpret_cast<const void*>(&k_m2l_bf16<2, 1>),
+      reinterpret_cast<const void*>(&k_m2l_bf16<3, 0>), reinterpret_cast<const void*>(&k_m2l_bf16<3, 1>),
+      reinterpret_cast<const void*>(&k_p2p<0>),          reinterpret_cast<const void*>(&k_p2p<1>),
+      reinterpret_cast<const void*>(&k_p2p<2>)};
+  for (const void* k : kernels) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynamicLds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace kifmm

@@ -6,6 +6,14 @@
 
 namespace kifmm {
 
+// Dynamic LDS any launch here may request (gfx950 has 160 KiB per CU; the rest
+// covers the kernels' static LDS).
+constexpr size_t kMaxDynamicLds = 156 * 1024;
+// Surface points the leaf kernels hold in LDS (p <= 8).
+constexpr int kMaxLeafSurface = 304;
+// Sets the dynamic LDS limit of every LDS-staging kernel on the current device.
+hipError_t configure_kernels();
+
 // An M2L work item (see k_m2l in kernels.hip): one aligned 4x4x4 block of
 // parents at one level, target sibling position o and source position o'.
 struct M2LItem {
@@ -23,6 +31,8 @@ struct M2LItem {
 void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int* xrow, float* Y, int ldy,
                     const int* yrow, int nbox, int nout, int K, float alpha, int beta, hipStream_t s, int batch = 1,
                     long long xbs = 0, long long ybs = 0, int ywide = 0);
+// Whether a kernel instance fits (row blocks, padded rank, LDS row stride).
+bool m2l_supported(int row_blocks, int ldk, int lds_ld);
 // Returns false if no kernel instance fits (rb, ldk).
 // nrhs right-hand sides: uhat and each partial sum advance by rhs_stride floats per right-hand side.
 // upper: the launch for the levels above the leaves (a kernel instance of its own name).
@@ -34,6 +44,7 @@ bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int 
 // lanes][8] bfloat16 bit patterns; core_stride16 is the size of one offset's
 // operator in 16-byte units; lds_ld16 >= m2l_bf16_lds_ld16(pieces).
 int m2l_bf16_lds_ld16(int pieces);
+bool m2l_bf16_supported(int pieces, int row_blocks, int ldk);
 bool launch_m2l_bf16(int pieces, int row_blocks, const uint16_t* cores, size_t core_stride16, int ldk, int lds_ld16,
                      const M2LItem* items, int nitems, const int* tgt_blk, const int* src_blk, const int* pair_offs,
                      const float* uhat, float* chat_part, long long part_stride, int nrhs, long long rhs_stride,
@@ -55,6 +66,7 @@ void launch_vjp_combine(const float* s, const float* w, const float* fs, const f
                         hipStream_t st);
 void launch_permute(float4* pts, const float* charges, const int* order, int n, hipStream_t s);
 // False if n > 768 (no kernel instance).
+bool p2m_supported(int n);
 bool launch_p2m(const float4* pts, const int* start, const int* leaves, const float4* centers, const float* surf, int n,
                 float alpha, float* q, int ldq, int nleaves, hipStream_t s);
 // centers: per leaf slot two float4, (c_hi, r) and (c_lo, 0) with c = c_hi + c_lo.
@@ -66,10 +78,20 @@ size_t p2p_lds_bytes(int cap, int n);
 // written to input order.  threads: 256 or kP2PMaxThreads per workgroup (false
 // otherwise); the results do not depend on it.
 constexpr int kP2PMaxThreads = 320;
+bool p2p_supported(int threads, int cap, int n);
 bool launch_p2p(int mode, const float4* pts, const int* start, const int* blk, int ngroups, int group_slots, int cap,
                 const float4* centers, const float* surf, int n, float alpha, const float* d, int ldd, int far,
                 const int* order, float* pot, float* grad, float4* near, int threads, hipStream_t s);
 
+// The same sums as k_p2p (modes as there) by a persistent kernel over tiles
+// (leaf slot, first sorted point, count <= 64, 0) taken from queue[0], which
+// launch_clear_queue zeroes (n counters) and must precede each launch.  `grid`
+// workgroups of four waves.
+void launch_clear_queue(int* queue, int n, hipStream_t s);
+bool launch_leaf_queue(int mode, const float4* pts, const int* start, const int4* tiles, int ntiles, int* queue,
+                       int grid, const int* blk, int group_slots, const float4* centers, const float* surf, int n,
+                       float alpha, const float* d, int ldd, int far, const int* order, float* pot, float* grad,
+                       float4* near, hipStream_t s);
 
 // Multi-RHS leaf kernels (R = 2, 4, 8, 16, 32; potentials only).  qs: sorted
 // charges [N][R].  q: check fields [R][leaf slots][ldq], qrs = leaf slots * ldq.

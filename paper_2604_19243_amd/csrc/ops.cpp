@@ -68,12 +68,25 @@ void check_finite(const std::vector<double>& v, const char* what) {
 
 }  // namespace
 
-Ops* precompute_ops(int p, double eps_pinv, double eps_svd, int rank) {
+Ops* precompute_ops(int p, double alpha_inner, double alpha_outer, double eps_pinv, double eps_svd) {
   require(p >= 2 && p <= 12, "p must be in [2, 12]");
+  // The equivalent surface must enclose the box (alpha_inner > 1) inside the check
+  // surface (alpha_inner < alpha_outer), and a V-list source's equivalent surface
+  // must stay outside the target's check surface: V-list centres are at least 4 r
+  // apart in the max norm, so alpha_inner + alpha_outer <= 4.
+  require(std::isfinite(alpha_inner) && std::isfinite(alpha_outer) && alpha_inner > 1.0 &&
+              alpha_inner < alpha_outer && alpha_inner + alpha_outer <= 4.0 + 1e-12,
+          "surface radii must satisfy 1 < alpha_inner < alpha_outer and alpha_inner + alpha_outer <= 4");
   require(eps_pinv > 0.0 && eps_pinv < 1.0, "eps_pinv must be in (0, 1)");
-  require(rank > 0 || (eps_svd > 0.0 && eps_svd < 1.0), "eps_svd must be in (0, 1) when rank is 0");
   const int n = 6 * (p - 1) * (p - 1) + 2;
-  require(rank >= 0 && rank <= n, "rank must be in [0, n]");
+  int rank = 0;
+  if (eps_svd < 0.0) {
+    require(eps_svd == std::floor(eps_svd) && -eps_svd <= (double)n,
+            "a negative eps_svd gives the rank: it must be an integer -k with 1 <= k <= n");
+    rank = (int)(-eps_svd);
+  } else {
+    require(eps_svd > 0.0 && eps_svd < 1.0, "eps_svd must be in (0, 1), or a negative integer rank");
+  }
 
   Ops* o = new Ops();
   try {
@@ -81,6 +94,9 @@ Ops* precompute_ops(int p, double eps_pinv, double eps_svd, int rank) {
     o->n = n;
     o->eps_pinv = eps_pinv;
     o->eps_svd = eps_svd;
+    o->alpha_inner = alpha_inner;
+    o->alpha_outer = alpha_outer;
+    const double ai = alpha_inner, ao = alpha_outer;
     // Surface: grid points of {-1..1}^3, p per edge, on the cube boundary; each
     // coordinate is (2i - (p-1)) / (p-1).
     for (int i = 0; i < p; ++i)
@@ -96,7 +112,7 @@ Ops* precompute_ops(int p, double eps_pinv, double eps_svd, int rank) {
 
     // Check-to-equivalent pseudo-inverses.  K(DC, DE) = K(UC, UE)^T at equal radius,
     // so DC2E = UC2E^T.
-    std::vector<double> kuc = surface_kernel(S, n, kAlphaOuter, zero, kAlphaInner, zero);
+    std::vector<double> kuc = surface_kernel(S, n, ao, zero, ai, zero);
     std::vector<double> g((size_t)n * n);  // column-major copy
     for (int a = 0; a < n; ++a)
       for (int b = 0; b < n; ++b) g[(size_t)b * n + a] = kuc[(size_t)a * n + b];
@@ -124,10 +140,10 @@ Ops* precompute_ops(int p, double eps_pinv, double eps_svd, int rank) {
     for (int oc = 0; oc < 8; ++oc) {
       const double off[3] = {(double)(2 * (oc & 1) - 1), (double)(2 * ((oc >> 1) & 1) - 1),
                              (double)(2 * ((oc >> 2) & 1) - 1)};
-      std::vector<double> kup = surface_kernel(S, n, 2.0 * kAlphaOuter, zero, kAlphaInner, off);
+      std::vector<double> kup = surface_kernel(S, n, 2.0 * ao, zero, ai, off);
       std::vector<double> m = matmul(uc2e_parent, kup, n, n, n);
       std::copy(m.begin(), m.end(), o->m2m.begin() + (size_t)oc * n * n);
-      std::vector<double> kdn = surface_kernel(S, n, kAlphaInner, off, 2.0 * kAlphaOuter, zero);
+      std::vector<double> kdn = surface_kernel(S, n, ai, off, 2.0 * ao, zero);
       std::vector<double> l = matmul(o->dc2e, kdn, n, n, n);
       std::copy(l.begin(), l.end(), o->l2l.begin() + (size_t)oc * n * n);
     }
@@ -145,7 +161,7 @@ Ops* precompute_ops(int p, double eps_pinv, double eps_svd, int rank) {
     std::vector<std::vector<double>> kt(nt);
     parallel_for(nt, [&](int64_t t) {
       const double c[3] = {2.0 * o->offsets[3 * t], 2.0 * o->offsets[3 * t + 1], 2.0 * o->offsets[3 * t + 2]};
-      kt[t] = surface_kernel(S, n, kAlphaInner, c, kAlphaInner, zero);
+      kt[t] = surface_kernel(S, n, ai, c, ai, zero);
     });
     // Column-major stacks: fat^T = [K_1^T; ...; K_m^T] and tall = [K_1; ...; K_m], both (m n) x n.
     const int64_t rows = (int64_t)nt * n;

@@ -64,6 +64,14 @@ struct Plan : Object {
   bool up_on = true;                     // use it (timed against not using it at plan creation)
   int p2p_threads = kP2PMaxThreads;      // leaf-kernel workgroup size (timed against 256 at plan creation)
   double tune_ms[2][2] = {};             // evaluate [without / with the second stream][256 / 320 leaf threads] (ms)
+  bool leaf_queue = false;               // one-RHS leaf sums as the persistent work-queue kernel
+  double leaf_tune_ms[2] = {0.0, 0.0};   // leaf sums timed at plan creation: per-parent kernels, work queue (ms)
+  int4* d_tiles = nullptr;               // work-queue tiles (leaf slot, first point, count <= 64, 0), longest first
+  int n_tiles = 0;
+  int* d_queue = nullptr;                // work-queue counter (cleared by a kernel before each use)
+  int queue_grid = 1;                    // workgroups of the persistent leaf kernel
+  bool want_up = false, want_side = false;  // the plan has the second stream / the U-list stream
+  bool on_device = false;                // device resources were created (the destructor releases them)
   hipEvent_t ev_up0 = nullptr, ev_up1 = nullptr;
   float4* d_near = nullptr;              // ULI result in sorted order (phi, grad)
   bool m2l_wide = false;                 // nrhs = 32, FP32: per-target V lists with the right-hand sides as columns
@@ -97,7 +105,11 @@ struct Plan : Object {
   void collect_times();
 };
 
-Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, int device);
+Tree* build_tree_device(const float* xyz, int64_t n, int depth, const double* cube, hipStream_t st);
+Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, hipStream_t st);
+int64_t plan_workspace_bytes(Tree* tree, Ops* ops, int nrhs, unsigned flags);
+void plan_stats(const Plan* plan, int64_t* v);  // KIFMM_N_STATS entries
+int64_t device_memory_limit();                  // 0: none (kifmm_set_device_memory_limit)
 void evaluate_plan(Plan* plan, const float* charges, float* pot, float* grad, hipStream_t st);
 bool launch_m2l_form(Plan* plan, hipStream_t st, int part);
 void evaluate_vjp(Plan* plan, const float* charges, const float* weights, const float* field, float* grad_charges,

@@ -46,3 +46,34 @@ def oracle_evaluate(points, charges, depth, p, cube, eps_svd=1e-6, rank=None, gr
 
 
 rel_l2 = direct.rel_l2
+
+
+def leaf_groups(t, leaves=None):
+    """Input indices of the points of each non-empty leaf of the oracle tree `t` (or of the given leaves)."""
+    if leaves is None:
+        return list(t.leaf_points.values())
+    return [t.leaf_points[tuple(int(v) for v in b)] for b in leaves if tuple(int(v) for v in b) in t.leaf_points]
+
+
+def assert_parity(label, gpu, ref, groups, tol):
+    """Relative L2 over the points of `groups` <= tol, and per group (leaf) <= 10 tol, so that an error
+    confined to a few leaves is not diluted by all the others.
+
+    A leaf's error is taken relative to its own norm, floored at its share of the whole norm,
+    |ref| sqrt(m / M) for m of the M points: where a leaf's values happen to nearly cancel (one or
+    two points with signed charges), its own norm is no scale for FP32 rounding made in sums of
+    many terms."""
+    idx = np.concatenate(groups)
+    e = rel_l2(gpu[idx], ref[idx])
+    total = np.linalg.norm(np.asarray(ref[idx], dtype=np.float64).ravel())
+    worst = 0.0
+    for g in groups:
+        if not len(g):
+            continue
+        err = np.linalg.norm((np.asarray(gpu[g], dtype=np.float64) - ref[g]).ravel())
+        floor = total * np.sqrt(len(g) / len(idx))
+        worst = max(worst, err / max(np.linalg.norm(np.asarray(ref[g], dtype=np.float64).ravel()), floor))
+    log(f"  {label}: rel-L2 {e:.3e}, worst leaf {worst:.3e} ({len(groups)} leaves, {len(idx)} points)")
+    assert e < tol, (label, e)
+    assert worst < 10 * tol, (label, worst)
+    return e, worst

@@ -18,17 +18,20 @@ pytestmark = pytest.mark.gpu
 UNIT = (0.5, 0.5, 0.5, 0.5)
 
 
-@pytest.mark.parametrize("serial,nrhs,upper", [(False, 1, False), (True, 1, False), (False, 4, False),
-                                               (False, 1, True)])
-def test_captured_evaluate_replays_bitwise(serial, nrhs, upper):
-    # upper: the levels above the leaves forced onto the plan's second stream (three streams captured)
+@pytest.mark.parametrize("serial,nrhs,upper,queue", [(False, 1, False, False), (True, 1, False, False),
+                                                     (False, 4, False, False), (False, 1, True, False),
+                                                     (False, 1, False, True), (True, 1, False, True)])
+def test_captured_evaluate_replays_bitwise(serial, nrhs, upper, queue):
+    # upper: the levels above the leaves forced onto the plan's second stream (three streams captured);
+    # queue: the persistent leaf kernel, whose work-queue counters a kernel clears in every replay
     import torch
-    log(f"graph capture serial={serial} nrhs={nrhs} upper={upper}")
+    log(f"graph capture serial={serial} nrhs={nrhs} upper={upper} queue={queue}")
     n, depth, p = 20_000, 4 if upper else 3, 6
     x = workloads.points("cube", n, 1001)
     flags = kifmm.KIFMM_POTENTIAL | (kifmm.KIFMM_SERIAL if serial else 0)
     flags |= kifmm.KIFMM_GRADIENT if nrhs == 1 else 0
     flags |= kifmm.KIFMM_UPPER_STREAM if upper else 0
+    flags |= kifmm.KIFMM_LEAF_QUEUE if queue else (kifmm.KIFMM_LEAF_BLOCKS if nrhs == 1 else 0)
     f = kifmm.FMM(x, depth, p, cube=UNIT, flags=flags, nrhs=nrhs)
     dev = torch.device("cuda:0")
     shape = (n,) if nrhs == 1 else (n, nrhs)
@@ -44,6 +47,7 @@ def test_captured_evaluate_replays_bitwise(serial, nrhs, upper):
     torch.cuda.synchronize()
     if upper:
         assert kifmm.kifmm_plan_get_stats(f.plan)["upper_stream"] == 1
+    assert kifmm.kifmm_plan_get_stats(f.plan)["leaf_queue"] == (1 if queue else 0)
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
         f.evaluate(q, pot, grad, stream=s.cuda_stream)

@@ -6,7 +6,7 @@ Tolerance: relative L2 <= 1e-6 for potentials and gradients of the plain FP32 pa
 import numpy as np
 import pytest
 
-from gpu_helpers import gpu_evaluate, log, oracle_evaluate, rel_l2
+from gpu_helpers import assert_parity, gpu_evaluate, leaf_groups, log, oracle_evaluate, rel_l2
 from oracle import direct
 from paper_2604_19243_amd import kifmm, workloads
 
@@ -54,11 +54,11 @@ def test_parity_with_oracle(name, n, depth, p, dist, serial, rank):
     phi, g, f = gpu_evaluate(x, s, depth, p, cube, serial=serial, rank=rank)
     k = kifmm.kifmm_ops_get_info(f.ops)["rank_m2l"]
     f.close()
-    rphi, rg, _, ops = oracle_evaluate(x, s, depth, p, cube, rank=rank or None)
+    rphi, rg, t, ops = oracle_evaluate(x, s, depth, p, cube, rank=rank or None)
     assert ops.compression(1.0)[0].shape[1] == k
-    e, eg = rel_l2(phi, rphi), rel_l2(g, rg)
-    log(f"  rel-L2 phi {e:.3e} grad {eg:.3e} (k={k})")
-    assert e < TOL and eg < TOL
+    groups = leaf_groups(t)
+    assert_parity(f"phi (k={k})", phi, rphi, groups, TOL)
+    assert_parity("grad", g, rg, groups, TOL)
 
 
 def test_linearity_and_determinism():
@@ -100,10 +100,9 @@ def test_full_size_hot_path_sampled():
     leaves |= {(0, 0, 0), (m - 1, m - 1, m - 1), (0, m - 1, 5), (m // 2, 0, m - 1)}
     leaves = sorted(leaves)
     rphi, rg, t, _ = oracle_evaluate(x, s, w.depth, w.p, c, rank=w.m2l_rank, target_leaves=leaves)
-    idx = np.concatenate([t.leaf_points[b] for b in leaves if b in t.leaf_points])
-    e, eg = rel_l2(phi[idx], rphi[idx]), rel_l2(g[idx], rg[idx])
-    log(f"  sampled {len(idx)} points: rel-L2 phi {e:.3e} grad {eg:.3e}")
-    assert e < TOL and eg < TOL
+    groups = leaf_groups(t, leaves)
+    assert_parity("phi, sampled leaves", phi, rphi, groups, TOL)
+    assert_parity("grad, sampled leaves", g, rg, groups, TOL)
 
 
 def test_stream_and_outputs_subset():
@@ -142,11 +141,10 @@ def test_expansion_orders(p, n, depth):
     phi, g, f = gpu_evaluate(x, s, depth, p, UNIT)
     k = kifmm.kifmm_ops_get_info(f.ops)["rank_m2l"]
     f.close()
-    rphi, rg, _, ops = oracle_evaluate(x, s, depth, p, UNIT)
+    rphi, rg, t, ops = oracle_evaluate(x, s, depth, p, UNIT)
     assert ops.compression(1.0)[0].shape[1] == k
-    e, eg = rel_l2(phi, rphi), rel_l2(g, rg)
-    log(f"  rel-L2 phi {e:.3e} grad {eg:.3e} (k={k})")
-    assert e < TOL and eg < TOL
+    assert_parity(f"phi (k={k})", phi, rphi, leaf_groups(t), TOL)
+    assert_parity("grad", g, rg, leaf_groups(t), TOL)
 
 
 def test_orders_above_8_need_a_shallow_tree():
@@ -158,7 +156,7 @@ def test_orders_above_8_need_a_shallow_tree():
     ops = kifmm.kifmm_ops_precompute(9)
     try:
         for depth, ok in ((3, False), (1, True)):
-            tree = kifmm.kifmm_tree_build(x, depth, UNIT)
+            tree = kifmm.kifmm_tree_build_host(x, depth, UNIT)
             try:
                 if ok:
                     plan = kifmm.kifmm_plan_create(tree, ops, 1, kifmm.KIFMM_POTENTIAL | kifmm.KIFMM_GRADIENT)
@@ -182,10 +180,9 @@ def test_deep_sparse_trees(depth):
     s = workloads.charges("uniform01", n, 901 + depth)
     phi, g, f = gpu_evaluate(x, s, depth, 4, (0.0, 0.0, 0.0, 1.0))
     f.close()
-    rphi, rg, _, _ = oracle_evaluate(x, s, depth, 4, (0.0, 0.0, 0.0, 1.0))
-    e, eg = rel_l2(phi, rphi), rel_l2(g, rg)
-    log(f"  rel-L2 phi {e:.3e} grad {eg:.3e}")
-    assert e < TOL and eg < TOL
+    rphi, rg, t, _ = oracle_evaluate(x, s, depth, 4, (0.0, 0.0, 0.0, 1.0))
+    assert_parity("phi", phi, rphi, leaf_groups(t), TOL)
+    assert_parity("grad", g, rg, leaf_groups(t), TOL)
 
 
 def test_gradient_only_and_auto_cube():
@@ -199,13 +196,11 @@ def test_gradient_only_and_auto_cube():
     grad = torch.zeros(n, 3, device=dev)
     f.evaluate(torch.from_numpy(s).to(dev), None, grad)
     torch.cuda.synchronize()
-    info = kifmm.kifmm_tree_get_info(f.tree)
+    info = kifmm.kifmm_tree_stats_get(f.tree)
     f.close()
     c, r = info["center"], info["half_width"]
-    _, rg, _, _ = oracle_evaluate(x, s, 3, 5, (c[0], c[1], c[2], r))
-    eg = rel_l2(grad.cpu().double().numpy(), rg)
-    log(f"  rel-L2 grad {eg:.3e}")
-    assert eg < TOL
+    _, rg, t, _ = oracle_evaluate(x, s, 3, 5, (c[0], c[1], c[2], r))
+    assert_parity("grad", grad.cpu().double().numpy(), rg, leaf_groups(t), TOL)
 
 
 def test_coincident_and_grid_aligned_points():
@@ -221,7 +216,130 @@ def test_coincident_and_grid_aligned_points():
     phi, g, f = gpu_evaluate(x, s, 3, 5, UNIT)
     f.close()
     assert np.isfinite(phi).all() and np.isfinite(g).all()
-    rphi, rg, _, _ = oracle_evaluate(x, s, 3, 5, UNIT)
-    e, eg = rel_l2(phi, rphi), rel_l2(g, rg)
-    log(f"  rel-L2 phi {e:.3e} grad {eg:.3e}")
-    assert e < TOL and eg < TOL
+    rphi, rg, t, _ = oracle_evaluate(x, s, 3, 5, UNIT)
+    assert_parity("phi", phi, rphi, leaf_groups(t), TOL)
+    assert_parity("grad", g, rg, leaf_groups(t), TOL)
+
+
+@pytest.mark.parametrize("depth,n,p,dist", [
+    (1, 6_000, 6, "cube"),      # the direct sum: every leaf block exceeds the LDS capacity (fused kernel)
+    (2, 20_000, 5, "cube"),     # far field at level 2; the U-list kernel on its own stream
+    (3, 40_000, 4, "sphere"),   # dense sphere leaves: some blocks fit in LDS, others do not
+])
+def test_leaf_blocks_beyond_lds_capacity(depth, n, p, dist):
+    # A parent's 4 x 4 x 4 leaf block holding more sources than the leaf kernel's LDS
+    # capacity (about 4,100 padded sources at p = 5..6) is read from global memory instead.
+    log(f"LDS overflow depth={depth} n={n} p={p} {dist}")
+    x = workloads.points(dist, n, 4100 + n)
+    s = workloads.charges("uniform11", n, 4200 + n)
+    cube = UNIT if dist == "cube" else (0.0, 0.0, 0.0, 1.0)
+    blocks = kifmm.KIFMM_LEAF_BLOCKS
+    phi, g, f = gpu_evaluate(x, s, depth, p, cube, flags=blocks)
+    f.close()
+    if depth <= 1:
+        x64, s64 = x.astype(np.float64), s.astype(np.float64)
+        rphi, rg = direct.potential(x64, x64, s64), direct.gradient(x64, x64, s64)
+        groups = [np.arange(n)]
+    else:
+        rphi, rg, t, _ = oracle_evaluate(x, s, depth, p, cube)
+        groups = leaf_groups(t)
+    assert_parity("phi", phi, rphi, groups, TOL)
+    assert_parity("grad", g, rg, groups, TOL)
+
+
+@pytest.mark.parametrize("name,n,depth,p,dist,serial", [
+    ("sphere", 60_000, 5, 6, "sphere", False),     # uneven leaves: the case the work queue is for
+    ("sphere_serial", 60_000, 5, 6, "sphere", True),
+    ("cube", 30_000, 4, 5, "cube", False),
+    ("shallow", 2_000, 1, 4, "cube", True),        # the direct sum
+])
+def test_leaf_work_queue_matches_per_parent_kernel(name, n, depth, p, dist, serial):
+    # The persistent work-queue kernel takes each leaf's sources in the per-parent kernel's
+    # order with the same FP32 partials and FP64 accumulation, so the two give the same
+    # bits; both against the oracle.  The per-parent kernel's result does not depend on its
+    # workgroup size (256 or 320 threads) either.
+    log(f"leaf queue {name} n={n} depth={depth} p={p} serial={serial}")
+    x = workloads.points(dist, n, 4300 + n)
+    s = workloads.charges("normal", n, 4400 + n)
+    cube = UNIT if dist == "cube" else (0.0, 0.0, 0.0, 1.0)
+    out = {}
+    for label, fl in (("queue", kifmm.KIFMM_LEAF_QUEUE), ("blocks320", kifmm.KIFMM_LEAF_BLOCKS | kifmm.KIFMM_LEAF_THREADS_320),
+                      ("blocks256", kifmm.KIFMM_LEAF_BLOCKS | kifmm.KIFMM_LEAF_THREADS_256)):
+        phi, g, f = gpu_evaluate(x, s, depth, p, cube, serial=serial, flags=fl)
+        st = kifmm.kifmm_plan_get_stats(f.plan)
+        f.close()
+        assert st["leaf_queue"] == (1 if label == "queue" else 0)
+        if label != "queue":
+            assert st["p2p_threads"] == int(label[-3:])
+        else:
+            assert st["leaf_tiles"] >= 1
+        out[label] = (phi, g)
+    for label in ("blocks256", "queue"):
+        np.testing.assert_array_equal(out[label][0], out["blocks320"][0])
+        np.testing.assert_array_equal(out[label][1], out["blocks320"][1])
+    rphi, rg, t, _ = oracle_evaluate(x, s, depth, p, cube)
+    assert_parity("phi (queue)", out["queue"][0], rphi, leaf_groups(t), TOL)
+    assert_parity("grad (queue)", out["queue"][1], rg, leaf_groups(t), TOL)
+
+
+def test_device_tree_build_and_plan_on_a_stream():
+    # The tree built from device points (copied on a stream), the plan created on that
+    # stream and evaluated on it, with non-default surface radii; against the oracle with
+    # the same radii.
+    import torch
+    log("device tree build, plan on a stream, alpha 1.2 / 2.7")
+    n = 12_000
+    x = workloads.points("cube", n, 4501)
+    s = workloads.charges("uniform01", n, 4502)
+    dev = torch.device("cuda:0")
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        xd = torch.from_numpy(x).to(dev)
+        f = kifmm.FMM(xd, 3, 5, cube=UNIT, stream=st.cuda_stream, alpha_inner=1.2, alpha_outer=2.7)
+        sd = torch.from_numpy(s).to(dev)
+        pot = torch.full((n,), float("nan"), device=dev)
+        grad = torch.full((n, 3), float("nan"), device=dev)
+        f.evaluate(sd, pot, grad, stream=st.cuda_stream)
+    st.synchronize()
+    order = kifmm.kifmm_tree_get_order(f.tree, n)
+    f.close()
+    from oracle import fmm, operators, tree
+    t = tree.Tree(x.astype(np.float64), 3, UNIT[:3], UNIT[3])
+    np.testing.assert_array_equal(order, t.order)
+    ops = operators.Operators(5, eps_pinv=1e-7, m2l="compressed", eps_svd=1e-6, alpha_inner=1.2, alpha_outer=2.7)
+    rphi, rg = fmm.evaluate(t, ops, s.astype(np.float64))
+    assert_parity("phi", pot.cpu().double().numpy(), rphi, leaf_groups(t), TOL)
+    assert_parity("grad", grad.cpu().double().numpy(), rg, leaf_groups(t), TOL)
+
+
+def test_destroyed_plan_and_capability_errors():
+    import torch
+    log("handle states and plan capabilities")
+    x = workloads.points("cube", 3000, 4601)
+    dev = torch.device("cuda:0")
+    sd = torch.ones(3000, device=dev)
+    pot = torch.zeros(3000, device=dev)
+    grad = torch.zeros(3000, 3, device=dev)
+    f = kifmm.FMM(x, 3, 4, cube=UNIT, flags=kifmm.KIFMM_POTENTIAL)
+    with pytest.raises(kifmm.KifmmError) as e:
+        f.evaluate(sd, pot, grad)   # no KIFMM_GRADIENT
+    assert e.value.status == kifmm.KIFMM_E_STATE
+    with pytest.raises(kifmm.KifmmError) as e:
+        f.vjp(sd, sd, None, pot, None)   # no KIFMM_VJP
+    assert e.value.status == kifmm.KIFMM_E_STATE
+    # the plan keeps its tree and operators: destroying their handles first is allowed
+    kifmm.kifmm_tree_destroy(f.tree)
+    kifmm.kifmm_ops_destroy(f.ops)
+    f.tree = f.ops = None
+    f.evaluate(sd, pot)
+    torch.cuda.synchronize()
+    assert np.isfinite(pot.cpu().numpy()).all()
+    plan = f.plan
+    kifmm.kifmm_plan_destroy(plan)
+    f.plan = None
+    with pytest.raises(kifmm.KifmmError) as e:
+        kifmm.kifmm_evaluate(plan, sd, pot)
+    assert e.value.status == kifmm.KIFMM_E_STATE
+    with pytest.raises(kifmm.KifmmError) as e:
+        kifmm.kifmm_plan_destroy(plan)
+    assert e.value.status == kifmm.KIFMM_E_STATE
