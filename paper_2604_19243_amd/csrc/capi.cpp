@@ -303,8 +303,7 @@ kifmm_status kifmm_plan_destroy(kifmm_plan plan) {
 kifmm_status kifmm_plan_set_timing(kifmm_plan plan, int enable) {
   return guarded([&] {
     Held<Plan> p = hold<Plan>(plan, kPlan);
-    if (!enable && p->timing) p->collect_times();
-    p->timing = enable != 0;
+    p->set_timing(enable != 0);
   });
 }
 

@@ -102,6 +102,7 @@ struct Staging {
 std::mutex g_config_mu;
 std::set<int> g_configured;
 
+// Once per device, with the device current: kernel attributes.
 void configure_device(int device) {
   std::lock_guard<std::mutex> lock(g_config_mu);
   if (g_configured.count(device)) return;
@@ -880,14 +881,29 @@ void plan_stats(const Plan* P, int64_t* v) {
   for (int i = 0; i < KIFMM_N_STATS; ++i) v[i] = vals[i];
 }
 
+void Plan::set_timing(bool on) {
+  if (on && ev.empty()) {
+    // the events are created here, so that evaluates create nothing
+    DeviceScope scope(device);
+    std::vector<hipEvent_t> made((size_t)kRing * KIFMM_N_STAGES * 2, nullptr);
+    for (auto& e : made) {
+      const hipError_t err = hipEventCreate(&e);
+      if (err != hipSuccess) {
+        for (auto& d : made)
+          if (d) (void)hipEventDestroy(d);
+        hip_check(err, "hipEventCreate");
+      }
+    }
+    ev = std::move(made);
+    recorded.assign((size_t)kRing * KIFMM_N_STAGES, 0);
+  }
+  if (!on && timing) collect_times();
+  timing = on;
+}
+
 void Plan::timing_begin_call() {
   ring_slot = -1;
   if (!timing) return;
-  if (ev.empty()) {
-    ev.resize((size_t)kRing * KIFMM_N_STAGES * 2);
-    for (auto& e : ev) hip_check(hipEventCreate(&e), "hipEventCreate");
-    recorded.assign((size_t)kRing * KIFMM_N_STAGES, 0);
-  }
   if (ring_used == kRing) collect_times();
   ring_slot = ring_used++;
 }

@@ -99,6 +99,7 @@ struct Plan : Object {
   int64_t stage_count[KIFMM_N_STAGES] = {};
 
   ~Plan() override;
+  void set_timing(bool on);
   void timing_begin_call();
   void stage_begin(int s, hipStream_t st);
   void stage_end(int s, hipStream_t st);
