@@ -2,20 +2,21 @@
 """Throughput of one kiFMM evaluate (3D Laplace) on one MI355X.
 
 A step is one full evaluate through the C ABI: permute, S2U (P2M), U2U, M2L
-compression and VLI, post + D2D, fused D2T + ULI (L2P + P2P) writing potentials
-and gradients in input order.  Inputs are resident in HBM before timing; tree
-build and operator precompute are setup and are not timed.
+compression and VLI, post + D2D, D2T + ULI (L2P + P2P) writing potentials and
+gradients in input order.  Inputs are resident in HBM before timing; tree build
+and operator precompute are setup and are not timed.
 
-Prints one JSON line: metric/value (Mpoints/s = N / time per evaluate), the
-roofline of the dominant kernel (M2L, FP32 matrix cores) measured with HIP
-events on the evaluate stream, the P2P kernel's FLOP rate (overlapped with the far
-field, and alone in a one-stream plan), and the FP64 oracle
-timed on a bounded sample on the host CPU.
+Prints one JSON line: metric/value (Mpoints/s = N / time per evaluate, exactly
+--steps evaluates between two events with stage timing off), the mean and spread
+over --repeats such blocks, the roofline of the dominant kernel (M2L on the
+matrix cores, timed with HIP events on its stream in a separate pass), the P2P
+kernels' FLOP rates, the accuracy gate (GPU against the FP64 oracle on the points
+of sampled leaves, and against the direct sum on sampled targets), the FP64
+oracle timed on a bounded sample on the host CPU (one core and all cores), and
+compact measurements of the precision, batching and differentiation workloads.
 
-`--m2l bf16x3` runs M2L as three bfloat16 matrix-core passes with FP32
-accumulation (roofline against the BF16 peak, three passes counted);
-`--compare-fp32` then also times the plain FP32 form on the same tree and
-operators and reports both forms' accuracy against the direct sum.
+The headline value is printed as null, and the exit status is 1, when the
+accuracy gate fails or could not be evaluated.
 """
 
 import argparse
@@ -35,6 +36,8 @@ PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 (vector and matrix), dense
 PEAK_BF16_TFLOPS = 2500.0  # MI355X BF16 matrix, dense (no sparsity)
 P2P_FLOPS_PER_PAIR = 20    # potential + gradient: 3 sub, 5 for r^2, 1 rsqrt, 2 potential, 1 + 8 gradient
 METRIC = "Mpoints/s per kiFMM evaluate at rel-L2<=1e-5; P2P/M2L % roofline"
+ORACLE_TOL = {"fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 1e-5}   # GPU against the FP64 oracle
+DIRECT_TOL = 1e-5                                              # the metric's rel-L2 bar, against eq. (1)
 
 
 def kernel_source_hash():
@@ -44,7 +47,7 @@ def kernel_source_hash():
 
 def load_traffic(workload, kernel, config):
     """HBM bytes per launch from committed rocprofv3 counter summaries, or None if stale, missing
-    or measured on another launch configuration (M2L rank, second stream)."""
+    or measured on another launch configuration."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -57,8 +60,64 @@ def load_traffic(workload, kernel, config):
     return None
 
 
-def cpu_baseline_worker(args):
-    """Runs in a child process with single-threaded BLAS: times the FP64 oracle on a sample."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# --------------------------------------------------------------------------- CPU children
+
+def leaf_parity(gpu, ref, groups):
+    """Relative L2 over all sampled points and the worst leaf (its own norm floored at its
+    share of the total), as in the parity tests."""
+    import numpy as np
+    idx = np.concatenate(groups)
+    total = np.linalg.norm(ref[idx].ravel())
+    e = float(np.linalg.norm((gpu[idx] - ref[idx]).ravel()) / total)
+    worst = 0.0
+    for g in groups:
+        err = np.linalg.norm((gpu[g] - ref[g]).ravel())
+        worst = max(worst, err / max(np.linalg.norm(ref[g].ravel()), total * np.sqrt(len(g) / len(idx))))
+    return e, float(worst)
+
+
+_SHARED = {}
+
+
+def _direct_block(job):
+    from oracle import direct
+    kind, a, b = job
+    x, s, idx = _SHARED["x"], _SHARED["s"], _SHARED["idx"]
+    if kind == "potential":
+        return direct.potential(x[idx], x[a:b], s[a:b], block=256)
+    return direct.gradient(x[idx], x[a:b], s[a:b], block=16)
+
+
+def direct_sum(kind, x, s, idx, block=100_000):
+    """oracle.direct's potential or gradient at the targets x[idx] from all sources, the source
+    blocks spread over the host's cores (forked workers) and added in block order."""
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    _SHARED.update(x=x, s=s, idx=idx)
+    jobs = [(kind, a, min(a + block, len(x))) for a in range(0, len(x), block)]
+    workers = max(1, min(len(jobs), len(os.sched_getaffinity(0))))
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
+        parts = list(ex.map(_direct_block, jobs))
+    out = parts[0]
+    for part in parts[1:]:
+        out = out + part
+    return out
+
+
+def oracle_worker(args):
+    """Child process: the FP64 oracle on a bounded sample of the workload (timed), its parity with
+    the GPU on the sampled leaves, and the direct sum at sampled targets."""
     import numpy as np
 
     from oracle import direct, fmm, operators, tree
@@ -67,22 +126,8 @@ def cpu_baseline_worker(args):
     w = workloads.WORKLOADS[args.workload]
     x32, s32 = workloads.make(w)
     x, s = x32.astype(np.float64), s32.astype(np.float64)
-
-    # accuracy of the GPU run(s): oracle direct sum at sampled targets, in blocks of sources
-    gpu = np.load(args.gpu_sample)
-    idx = gpu["idx"]
-    ref = np.zeros((len(idx),) + s.shape[1:])
-    for a in range(0, len(x), 250_000):
-        ref += direct.potential(x[idx], x[a:a + 250_000], s[a:a + 250_000])
-    acc = {"rel_l2_vs_direct_sampled": direct.rel_l2(gpu["phi"], ref), "direct_sample_targets": int(len(idx))}
-    if "phi_fp32" in gpu:
-        acc["fp32_rel_l2_vs_direct_sampled"] = direct.rel_l2(gpu["phi_fp32"], ref)
-    if "phi_rank" in gpu:
-        acc["rank_rel_l2_vs_direct_sampled"] = direct.rel_l2(gpu["phi_rank"], ref)
-    if args.accuracy_only:
-        print(json.dumps(acc), flush=True)
-        return
-
+    gpu = np.load(args.gpu_sample, allow_pickle=False)
+    out = {}
     c, r = w.cube
     t = tree.Tree(x, w.depth, c, r)
     rank = w.m2l_rank if args.m2l_rank is None else args.m2l_rank
@@ -90,7 +135,7 @@ def cpu_baseline_worker(args):
     L = w.depth
     for l in range(2, L + 1):
         ops.compression(t.radius(l))          # operator setup, not timed (as on the GPU)
-    s2 = s[:, None]
+    s2 = s[:, None] if s.ndim == 1 else s
     rng = np.random.default_rng(4000 + args.sample_seed)
     all_leaves = list(t.leaf_points)
     pick = rng.choice(len(all_leaves), size=min(args.sample_leaves, len(all_leaves)), replace=False)
@@ -106,22 +151,291 @@ def cpu_baseline_worker(args):
     t1 = time.perf_counter()
     d = fmm.downward_pass(t, ops, u, needed)
     t2 = time.perf_counter()
-    phi, _ = fmm.leaf_pass(t, ops, s2, d, leaves, w.gradient)
+    phi, grad = fmm.leaf_pass(t, ops, s2, d, leaves, w.gradient)
     t3 = time.perf_counter()
     boxes_all = sum(len(t.boxes[l]) for l in range(2, L + 1))
     boxes_sampled = sum(len(needed[l]) for l in range(2, L + 1))
     t_full = (t1 - t0) + (t2 - t1) * boxes_all / boxes_sampled + (t3 - t2) * len(all_leaves) / len(leaves)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "1"))
+    out["timing"] = {
+        "value": w.n / t_full / 1e6, "unit": "Mpoints/s", "cores": threads, "kind": "oracle",
+        "sample": (f"FP64 NumPy oracle, {threads} BLAS thread(s): full upward pass ({t1 - t0:.2f} s) timed; "
+                   f"downward pass timed on the {boxes_sampled} ancestors of {len(leaves)} random leaves "
+                   f"({t2 - t1:.2f} s) and leaf pass on those leaves ({t3 - t2:.2f} s), each scaled by box/leaf "
+                   f"counts to the full workload; extrapolated evaluate {t_full:.1f} s"),
+        "seconds_measured": t3 - t0, "seconds_extrapolated": t_full, "cpu_model": cpu_model()}
+    if args.timing_only:
+        print(json.dumps(out), flush=True)
+        return
 
-    out = {
-        "value": w.n / t_full / 1e6, "unit": "Mpoints/s", "cores": 1, "kind": "oracle",
-        "sample": (f"FP64 NumPy oracle, single thread: full upward pass ({t1 - t0:.2f} s) timed; downward pass "
-                   f"timed on the {boxes_sampled} ancestors of {len(leaves)} random leaves ({t2 - t1:.2f} s) and "
-                   f"leaf pass on those leaves ({t3 - t2:.2f} s), each scaled by box/leaf counts to the full "
-                   f"workload; extrapolated evaluate {t_full:.1f} s"),
-        "seconds_measured": t3 - t0, "seconds_extrapolated": t_full,
-    }
-    out.update(acc)
+    # GPU against the oracle on the points of the sampled leaves
+    groups = [t.leaf_points[b] for b in leaves]
+    gphi = gpu["phi"].astype(np.float64)
+    e, worst = leaf_parity(gphi, phi[:, 0] if gphi.ndim == 1 else phi, groups)
+    out["oracle_parity"] = {"leaves": len(leaves), "points": int(sum(len(g) for g in groups)),
+                            "rel_l2_phi": e, "worst_leaf_phi": worst}
+    if w.gradient and "grad" in gpu:
+        e, worst = leaf_parity(gpu["grad"].astype(np.float64), grad[:, 0, :], groups)
+        out["oracle_parity"].update(rel_l2_grad=e, worst_leaf_grad=worst)
+
+    # the direct sum of eq. (1) at sampled targets, sources in blocks
+    idx = gpu["direct_idx"]
+    ref = direct_sum("potential", x, s, idx)
+    out["direct"] = {"targets": int(len(idx)), "rel_l2_phi": direct.rel_l2(gphi[idx], ref)}
+    if w.gradient and "grad" in gpu:
+        gidx = idx[:args.direct_grad_targets]
+        gref = direct_sum("gradient", x, s, gidx)
+        out["direct"].update(grad_targets=int(len(gidx)), rel_l2_grad=direct.rel_l2(gpu["grad"][gidx], gref))
+    for key in gpu.files:
+        if key.startswith("extra_phi_"):   # other runs of the same workload (another M2L rank or form)
+            out["direct"][key[len("extra_"):]] = direct.rel_l2(gpu[key], ref)
     print(json.dumps(out), flush=True)
+
+
+def direct_worker(args):
+    """Child process: the direct sum of eq. (1) (or its derivative) at sampled targets of a
+    workload, against the GPU values of several runs."""
+    import numpy as np
+
+    from oracle import direct
+    from paper_2604_19243_amd import workloads
+
+    w = workloads.WORKLOADS[args.workload]
+    x32, s32 = workloads.make(w)
+    x, s = x32.astype(np.float64), s32.astype(np.float64)
+    gpu = np.load(args.gpu_sample, allow_pickle=False)
+    idx = gpu["idx"]
+    out = {"targets": int(len(idx))}
+    if "weights" in gpu.files:
+        # the derivative of sum w_i f_i: dL/ds (potential of w) and dL/dx
+        wts = gpu["weights"].astype(np.float64)
+        sw = np.stack([s, wts], axis=1)
+        ph = direct_sum("potential", x, sw, idx)
+        gr = direct_sum("gradient", x, sw, idx)
+        gp = wts[idx, None] * gr[:, 0, :] + s[idx, None] * gr[:, 1, :]
+        out["grad_charges"] = direct.rel_l2(gpu["grad_charges"], ph[:, 1])
+        out["grad_points"] = direct.rel_l2(gpu["grad_points"], gp)
+        out["phi"] = direct.rel_l2(gpu["phi"], ph[:, 0])
+    else:
+        ref = direct_sum("potential", x, s, idx)
+        for key in gpu.files:
+            if key.startswith("phi_"):
+                out[key[4:]] = direct.rel_l2(gpu[key], ref)
+    print(json.dumps(out), flush=True)
+
+
+def run_child(mode, path, workload, extra, threads, timeout=900):
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads), OPENBLAS_NUM_THREADS=str(threads),
+               MKL_NUM_THREADS=str(threads))
+    cmd = [sys.executable, os.path.abspath(__file__), mode, "--workload", workload, "--gpu-sample", path] + extra
+    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=timeout)
+    if r.returncode != 0:
+        print(r.stderr[-3000:], file=sys.stderr, flush=True)
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+# --------------------------------------------------------------------------- GPU timing
+
+class Timer:
+    """Warm-up, then blocks of exactly `steps` steps between two events on the evaluate stream."""
+
+    def __init__(self, torch, stream):
+        self.torch = torch
+        self.stream = stream
+
+    def block(self, step, steps):
+        torch = self.torch
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(self.stream)
+        for _ in range(steps):
+            step()
+        end.record(self.stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(end) / steps
+
+    def stages(self, plan, step, steps):
+        """Per-stage milliseconds per call from the plan's stage events (a separate pass)."""
+        from paper_2604_19243_amd import kifmm
+        kifmm.kifmm_plan_set_timing(plan, True)
+        kifmm.kifmm_plan_get_stage_times(plan, reset=True)
+        for _ in range(steps):
+            step()
+        self.torch.cuda.synchronize()
+        st = kifmm.kifmm_plan_get_stage_times(plan, reset=True)
+        kifmm.kifmm_plan_set_timing(plan, False)
+        return {k: v[0] / max(v[1], 1) for k, v in st.items()}
+
+
+def mean_std(v):
+    import numpy as np
+    a = np.asarray(v, dtype=np.float64)
+    return float(a.mean()), float(a.std(ddof=1)) if len(a) > 1 else 0.0
+
+
+def leaf_kernel_name(stats, serial, R):
+    if R > 1:
+        return f"k_leaf_multi<{R}>"
+    if stats["leaf_queue"]:
+        return "k_leaf_queue<0>" if serial else "k_leaf_queue<1>"
+    return "k_p2p<0>" if serial else "k_p2p<1>"
+
+
+def next_rows(args, torch, dev):
+    """Compact measurements of the precision, batching and differentiation workloads."""
+    import numpy as np
+
+    from paper_2604_19243_amd import kifmm, workloads
+    rows = {}
+    stream = torch.cuda.current_stream()
+    tm = Timer(torch, stream)
+    steps = args.next_steps
+
+    # precision: 8M points, p = 8, depth 6, N(0,1) charges, potentials; FP32 and split bfloat16 M2L
+    w = workloads.WORKLOADS["cube8m_p8_d6"]
+    print(f"# next: {w.name}", file=sys.stderr, flush=True)
+    x, s = workloads.make(w)
+    tree = kifmm.kifmm_tree_build_host(x, w.depth, w.cube[0] + (w.cube[1],))
+    ops = kifmm.kifmm_ops_precompute(w.p, eps_pinv=1e-7, eps_svd=1e-6)
+    k = kifmm.kifmm_ops_get_info(ops)["rank_m2l"]
+    q = torch.from_numpy(s).to(dev)
+    pot = torch.empty(w.n, device=dev)
+    idx = np.sort(np.random.default_rng(4003).choice(w.n, size=128, replace=False))
+    prec = {"workload": w.name, "m2l_rank": k, "forms": {}}
+    sample = {"idx": idx}
+    for form, fl, passes in (("fp32", 0, 1), ("bf16x3", kifmm.KIFMM_M2L_BF16X3, 3), ("bf16x6", kifmm.KIFMM_M2L_BF16X6, 6)):
+        plan = kifmm.kifmm_plan_create(tree, ops, 1, kifmm.KIFMM_POTENTIAL | fl)
+        st = kifmm.kifmm_plan_get_stats(plan)
+        step = lambda: kifmm.kifmm_evaluate(plan, q, pot, None, stream.cuda_stream)  # noqa: E731
+        for _ in range(2):
+            step()
+        ms = tm.block(step, steps)
+        stg = tm.stages(plan, step, max(2, steps // 2))
+        flop = 2.0 * k * k * st["m2l_stage_pairs"]
+        peak = PEAK_FP32_TFLOPS if passes == 1 else PEAK_BF16_TFLOPS
+        ach = (passes if passes > 1 else 1) * flop / (stg["m2l"] * 1e-3) / 1e12
+        sample[f"phi_{form}"] = pot.cpu().numpy()[idx].astype(np.float64)
+        prec["forms"][form] = {"ms_per_evaluate": ms, "mpoints_per_s": w.n / (ms * 1e-3) / 1e6,
+                               "m2l_ms": stg["m2l"], "m2l_roofline": {"achieved": ach, "peak": peak,
+                                                                      "unit": "TFLOP/s", "frac": ach / peak,
+                                                                      "passes": passes},
+                               "upper_levels_on_second_stream": bool(st["upper_stream"])}
+        kifmm.kifmm_plan_destroy(plan)
+        print(f"#   {form}: {ms:.2f} ms/evaluate, M2L {stg['m2l']:.2f} ms ({ach / peak:.3f} of peak)",
+              file=sys.stderr, flush=True)
+    kifmm.kifmm_ops_destroy(ops)
+    kifmm.kifmm_tree_destroy(tree)
+    del q, pot, x, s
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "p.npz")
+        np.savez(path, **sample)
+        acc = run_child("--direct-worker", path, w.name, [], 1)
+    if acc:
+        prec["rel_l2_vs_direct_sampled"] = acc
+        f = prec["forms"]
+        prec["speedup_bf16x6_vs_fp32_at_equal_accuracy"] = f["fp32"]["ms_per_evaluate"] / f["bf16x6"]["ms_per_evaluate"]
+        prec["speedup_bf16x3_vs_fp32"] = f["fp32"]["ms_per_evaluate"] / f["bf16x3"]["ms_per_evaluate"]
+        prec["bf16x6_equal_accuracy"] = acc["bf16x6"] <= 1.25 * acc["fp32"]
+    rows["precision"] = prec
+
+    # batching: 4M points on the unit sphere, depth 7, 32 N(0,1) right-hand sides, potentials
+    w = workloads.WORKLOADS["sphere4m_p6_d7_r32"]
+    print(f"# next: {w.name}", file=sys.stderr, flush=True)
+    x, s = workloads.make(w)
+    tree = kifmm.kifmm_tree_build_host(x, w.depth, w.cube[0] + (w.cube[1],))
+    ops = kifmm.kifmm_ops_precompute(w.p, eps_pinv=1e-7, eps_svd=1e-6)
+    k = kifmm.kifmm_ops_get_info(ops)["rank_m2l"]
+    q = torch.from_numpy(s).to(dev)
+    pot = torch.empty(w.n, 32, device=dev)
+    plan = kifmm.kifmm_plan_create(tree, ops, 32, kifmm.KIFMM_POTENTIAL)
+    st = kifmm.kifmm_plan_get_stats(plan)
+    step = lambda: kifmm.kifmm_evaluate(plan, q, pot, None, stream.cuda_stream)  # noqa: E731
+    step()
+    ms32 = tm.block(step, max(2, steps // 2))
+    stg = tm.stages(plan, step, 2)
+    m2l_flop = 2.0 * k * k * st["m2l_pairs"] * 32
+    leaf_flop = (9 + 2 * 32) * (st["p2p_pairs"] + w.n * st["n"])
+    idx = np.sort(np.random.default_rng(4004).choice(w.n, size=64, replace=False))
+    sample = {"idx": idx, "phi_r32": pot.cpu().numpy()[idx].astype(np.float64)}
+    kifmm.kifmm_plan_destroy(plan)
+    q1 = q[:, 0].contiguous()
+    pot1 = torch.empty(w.n, device=dev)
+    plan1 = kifmm.kifmm_plan_create(tree, ops, 1, kifmm.KIFMM_POTENTIAL)
+    st1 = kifmm.kifmm_plan_get_stats(plan1)
+    step1 = lambda: kifmm.kifmm_evaluate(plan1, q1, pot1, None, stream.cuda_stream)  # noqa: E731
+    for _ in range(2):
+        step1()
+    ms1 = tm.block(step1, steps)
+    stg1 = tm.stages(plan1, step1, max(2, steps // 2))
+    kifmm.kifmm_plan_destroy(plan1)
+    kifmm.kifmm_ops_destroy(ops)
+    kifmm.kifmm_tree_destroy(tree)
+    del q, pot, q1, pot1, x, s
+    bat = {"workload": w.name, "m2l_rank": k, "ms_per_evaluate": ms32,
+           "point_rhs_per_s": w.n * 32 / (ms32 * 1e-3), "stages_ms": stg,
+           "m2l_roofline": {"kernel": "k_m2l_wide", "achieved": m2l_flop / (stg["m2l"] * 1e-3) / 1e12,
+                            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"},
+           "leaf": {"kernel": "k_leaf_multi<32>", "achieved": leaf_flop / (stg["p2p"] * 1e-3) / 1e12,
+                    "flop_per_pair": 9 + 2 * 32, "unit": "TFLOP/s"},
+           "one_rhs": {"ms_per_evaluate": ms1, "stages_ms": stg1,
+                       "leaf_kernel": "k_leaf_queue" if st1["leaf_queue"] else "k_p2p",
+                       "m2l_form": ["blocked", "gathered"][st1["m2l_form"]] if st1["m2l_form"] < 2 else st1["m2l_form"]},
+           "batching_speedup": 32 * ms1 / ms32}
+    bat["m2l_roofline"]["frac"] = bat["m2l_roofline"]["achieved"] / PEAK_FP32_TFLOPS
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "b.npz")
+        np.savez(path, **sample)
+        acc = run_child("--direct-worker", path, w.name, [], 1)
+    if acc:
+        bat["rel_l2_vs_direct_sampled"] = acc["r32"]
+        bat["direct_sample_targets"] = acc["targets"]
+    print(f"#   32 RHS: {ms32:.1f} ms; one RHS {ms1:.2f} ms; speedup {bat['batching_speedup']:.2f}",
+          file=sys.stderr, flush=True)
+    rows["batching"] = bat
+
+    # differentiation: 2M points, p = 7, depth 6, forward (potentials and field) + backward
+    w = workloads.WORKLOADS["cube2m_p7_d6"]
+    print(f"# next: {w.name}", file=sys.stderr, flush=True)
+    x, s = workloads.make(w)
+    wts = workloads.charges("normal", w.n, w.seed + 2000)
+    tree = kifmm.kifmm_tree_build_host(x, w.depth, w.cube[0] + (w.cube[1],))
+    ops = kifmm.kifmm_ops_precompute(w.p, eps_pinv=1e-7, eps_svd=1e-6)
+    plan = kifmm.kifmm_plan_create(tree, ops, 1, kifmm.KIFMM_POTENTIAL | kifmm.KIFMM_GRADIENT | kifmm.KIFMM_VJP)
+    q, wd = torch.from_numpy(s).to(dev), torch.from_numpy(wts).to(dev)
+    pot = torch.empty(w.n, device=dev)
+    field = torch.empty(w.n, 3, device=dev)
+    gc = torch.empty(w.n, device=dev)
+    gp = torch.empty(w.n, 3, device=dev)
+    fwd = lambda: kifmm.kifmm_evaluate(plan, q, pot, field, stream.cuda_stream)  # noqa: E731
+
+    def fwd_bwd():
+        fwd()
+        kifmm.kifmm_evaluate_vjp(plan, q, wd, field, gc, gp, stream.cuda_stream)
+    for _ in range(2):
+        fwd_bwd()
+    ms_f = tm.block(fwd, steps)
+    ms_fb = tm.block(fwd_bwd, steps)
+    idx = np.sort(np.random.default_rng(4005).choice(w.n, size=64, replace=False))
+    sample = {"idx": idx, "weights": wts, "phi": pot.cpu().numpy()[idx].astype(np.float64),
+              "grad_charges": gc.cpu().numpy()[idx].astype(np.float64),
+              "grad_points": gp.cpu().numpy()[idx].astype(np.float64)}
+    kifmm.kifmm_plan_destroy(plan)
+    kifmm.kifmm_ops_destroy(ops)
+    kifmm.kifmm_tree_destroy(tree)
+    diff = {"workload": w.name, "forward_ms": ms_f, "forward_backward_ms": ms_fb,
+            "forward_mpoints_per_s": w.n / (ms_f * 1e-3) / 1e6,
+            "forward_backward_mpoints_per_s": w.n / (ms_fb * 1e-3) / 1e6}
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "d.npz")
+        np.savez(path, **sample)
+        acc = run_child("--direct-worker", path, w.name, [], 1)
+    if acc:
+        diff["rel_l2_vs_direct_sampled"] = acc
+    print(f"#   forward {ms_f:.2f} ms, forward + backward {ms_fb:.2f} ms", file=sys.stderr, flush=True)
+    rows["differentiation"] = diff
+    return rows
 
 
 def main():
@@ -129,40 +443,47 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--repeats", type=int, default=5, help="blocks of --steps evaluates for the mean and spread")
     ap.add_argument("--workload", default="cube1m_p6_d5")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (parity still checked)")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the precision, batching and differentiation workloads")
+    ap.add_argument("--next-steps", type=int, default=10)
     ap.add_argument("--serial", action="store_true",
                     help="run every kernel on one stream (no ULI overlap with the far field)")
     ap.add_argument("--m2l", choices=["fp32", "bf16x3", "bf16x6"], default="fp32",
                     help="M2L arithmetic: plain FP32, or split bfloat16 (3 or 6 matrix-core passes, FP32 accumulation)")
-    ap.add_argument("--compare-fp32", action="store_true",
-                    help="with a split-bfloat16 --m2l: also time the plain FP32 form on the same tree and operators")
     ap.add_argument("--backward", action="store_true",
                     help="time forward + backward: evaluate (potentials and field) then the vector-Jacobian "
                          "product of L = sum w_i f_i (adjoint evaluate + combination)")
     ap.add_argument("--graph", action="store_true",
                     help="capture one step in a HIP graph (torch.cuda.graph) and time its replays")
-    ap.add_argument("--m2l-form", choices=["auto", "blocked", "gathered"], default="auto",
-                    help="one-RHS FP32 M2L form (auto: the faster, timed at plan creation)")
-    ap.add_argument("--upper-stream", choices=["auto", "on", "off"], default="auto",
-                    help="levels above the leaves on the plan's second stream (auto: timed at plan creation)")
+    ap.add_argument("--m2l-form", choices=["auto", "blocked", "gathered"], default="auto")
+    ap.add_argument("--upper-stream", choices=["auto", "on", "off"], default="auto")
+    ap.add_argument("--leaf", choices=["auto", "blocks", "queue"], default="auto",
+                    help="one-RHS leaf kernel: per-parent blocks or the persistent work queue")
+    ap.add_argument("--leaf-threads", choices=["auto", "256", "320"], default="auto")
     ap.add_argument("--m2l-rank", type=int, default=None,
                     help="M2L compression rank (default: the workload's; 0: singular values above 1e-6 sigma_max)")
     ap.add_argument("--no-compare-rank", action="store_true",
-                    help="skip the second timing, at the default M2L rank, of a workload with a rank of its own")
-    ap.add_argument("--compare-single", action="store_true",
-                    help="with a multi-RHS workload: also time a one-RHS plan on the same tree and operators")
+                    help="skip the timing at the default M2L rank of a workload with a rank of its own")
     ap.add_argument("--sample-leaves", type=int, default=3000)
     ap.add_argument("--sample-seed", type=int, default=2)
+    ap.add_argument("--direct-targets", type=int, default=1024)
+    ap.add_argument("--direct-grad-targets", type=int, default=256)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (calibrates HBM byte counters) and exit")
-    ap.add_argument("--cpu-baseline-worker", action="store_true", help=argparse.SUPPRESS)
-    ap.add_argument("--accuracy-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--oracle-worker", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--direct-worker", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--timing-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--gpu-sample", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
 
-    if args.cpu_baseline_worker:
-        cpu_baseline_worker(args)
+    if args.oracle_worker:
+        oracle_worker(args)
+        return
+    if args.direct_worker:
+        direct_worker(args)
         return
     if args.copy_probe:
         import torch
@@ -193,13 +514,14 @@ def main():
     m2l_flag = {"fp32": 0, "bf16x3": kifmm.KIFMM_M2L_BF16X3, "bf16x6": kifmm.KIFMM_M2L_BF16X6}[args.m2l]
     R = w.nrhs
     if R > 1:
-        # several right-hand sides: potentials, one stream
         if args.backward:
             raise SystemExit("--backward needs a one-RHS workload")
         flags = kifmm.KIFMM_POTENTIAL
     else:
         flags = kifmm.KIFMM_POTENTIAL | kifmm.KIFMM_GRADIENT | (kifmm.KIFMM_SERIAL if args.serial else 0)
         flags |= kifmm.KIFMM_VJP if args.backward else 0
+        flags |= {"auto": 0, "blocks": kifmm.KIFMM_LEAF_BLOCKS, "queue": kifmm.KIFMM_LEAF_QUEUE}[args.leaf]
+        flags |= {"auto": 0, "256": kifmm.KIFMM_LEAF_THREADS_256, "320": kifmm.KIFMM_LEAF_THREADS_320}[args.leaf_threads]
     m2l_flag |= {"auto": 0, "blocked": kifmm.KIFMM_M2L_BLOCKED, "gathered": kifmm.KIFMM_M2L_GATHER}[args.m2l_form]
     m2l_flag |= {"auto": 0, "on": kifmm.KIFMM_UPPER_STREAM, "off": kifmm.KIFMM_NO_UPPER_STREAM}[args.upper_stream]
     rank = w.m2l_rank if args.m2l_rank is None else args.m2l_rank
@@ -219,146 +541,111 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.set_stream(torch.cuda.Stream())
     stream = torch.cuda.current_stream()
+    tm = Timer(torch, stream)
     if args.backward:
         weights = torch.from_numpy(workloads.charges("normal", w.n, w.seed + 2000)).to(dev)
         grad_charges = torch.empty(w.n, device=dev)
         grad_points = torch.empty(w.n, 3, device=dev)
 
-    io = {"charges": charges, "pot": pot}
+    def step_of(plan):
+        def step():
+            kifmm.kifmm_evaluate(plan, charges, pot, grad, stream.cuda_stream)
+            if args.backward:
+                kifmm.kifmm_evaluate_vjp(plan, charges, weights, grad, grad_charges, grad_points, stream.cuda_stream)
+        return step
 
-    def step(plan):
-        kifmm.kifmm_evaluate(plan, io["charges"], io["pot"], grad, stream.cuda_stream)
-        if args.backward:
-            kifmm.kifmm_evaluate_vjp(plan, charges, weights, grad, grad_charges, grad_points, stream.cuda_stream)
-
-    def timed(plan, label):
-        """Warm-up, then exactly args.steps steps between two events on the evaluate stream."""
-        for _ in range(args.warmup):
-            step(plan)
+    step = step_of(f.plan)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    graph = None
+    if args.graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            step()
         torch.cuda.synchronize()
-        if args.graph:
-            # one step captured on the evaluate stream; the timed region replays it
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, stream=stream):
-                step(plan)
-            torch.cuda.synchronize()
-            start = torch.cuda.Event(enable_timing=True)
-            end = torch.cuda.Event(enable_timing=True)
-            start.record(stream)
-            for _ in range(args.steps):
-                g.replay()
-            end.record(stream)
-            torch.cuda.synchronize()
-            ms_ = start.elapsed_time(end) / args.steps
-            print(f"# {label} (graph replay): {ms_:.3f} ms/step", file=sys.stderr, flush=True)
-            del g
-            kifmm.kifmm_plan_set_timing(plan, True)
-            kifmm.kifmm_plan_get_stage_times(plan, reset=True)
-            step(plan)  # one eager step for the stage breakdown
-            torch.cuda.synchronize()
-            st = kifmm.kifmm_plan_get_stage_times(plan, reset=True)
-            kifmm.kifmm_plan_set_timing(plan, False)
-            return ms_, {k_: v[0] / max(v[1], 1) for k_, v in st.items()}
-        kifmm.kifmm_plan_set_timing(plan, True)
-        kifmm.kifmm_plan_get_stage_times(plan, reset=True)
-        start = torch.cuda.Event(enable_timing=True)
-        end = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        start.record(stream)
-        for _ in range(args.steps):
-            step(plan)
-        end.record(stream)
-        torch.cuda.synchronize()
-        ms_ = start.elapsed_time(end) / args.steps
-        st = kifmm.kifmm_plan_get_stage_times(plan, reset=True)
-        kifmm.kifmm_plan_set_timing(plan, False)
-        print(f"# {label}: {ms_:.3f} ms/evaluate; stages (ms/call): "
-              + ", ".join(f"{k_}={v[0] / max(v[1], 1):.3f}" for k_, v in st.items()), file=sys.stderr, flush=True)
-        return ms_, {k_: v[0] / max(v[1], 1) for k_, v in st.items()}
-
-    idx = np.sort(np.random.default_rng(4002).choice(w.n, size=min(256, w.n), replace=False))
-    ms, stages = timed(f.plan, "m2l " + args.m2l)
-    phi_sample = pot.cpu().numpy()[idx].astype(np.float64)
-    fp32_form = None
-    single = None
-    if R > 1 and args.compare_single:
-        plan1 = kifmm.kifmm_plan_create(f.tree, f.ops, 1, kifmm.KIFMM_POTENTIAL | m2l_flag)
-        io.update(charges=charges[:, 0].contiguous(), pot=torch.empty(w.n, device=dev))
-        ms1, stages1 = timed(plan1, "one right-hand side")
-        kifmm.kifmm_plan_destroy(plan1)
-        io.update(charges=charges, pot=pot)
-        single = {"ms_per_evaluate": ms1, "stages_ms": stages1, "batching_speedup": R * ms1 / ms}
-    if bf16 and args.compare_fp32:
-        plan32 = kifmm.kifmm_plan_create(f.tree, f.ops, R, flags)
-        ms32, stages32 = timed(plan32, "m2l fp32")
-        phi32_sample = pot.cpu().numpy()[idx].astype(np.float64)
-        kifmm.kifmm_plan_destroy(plan32)
-        fp32_form = {"ms_per_step": ms32, "m2l_ms": stages32["m2l"], "stages_ms": stages32,
-                     "speedup_evaluate": ms32 / ms, "speedup_m2l": stages32["m2l"] / stages["m2l"]}
+        timed_step = graph.replay
+    else:
+        timed_step = step
+    # the timed region: exactly --steps steps, stage events off; then more blocks for the spread
+    blocks = [tm.block(timed_step, args.steps)]
+    for _ in range(max(0, args.repeats - 1)):
+        blocks.append(tm.block(timed_step, args.steps))
+    ms = blocks[0]
+    mean_ms, std_ms = mean_std(blocks)
+    rates = [w.n / (b * 1e-3) / 1e6 for b in blocks]
+    print(f"# {w.name}: {ms:.3f} ms/step (blocks: " + ", ".join(f"{b:.3f}" for b in blocks) + ")",
+          file=sys.stderr, flush=True)
+    # outputs of the timed evaluates, for the accuracy gate
+    phi_all = pot.cpu().numpy()
+    grad_all = grad.cpu().numpy() if grad is not None else None
+    del graph
+    stages = tm.stages(f.plan, step, args.steps)
+    print("# stages (ms/call): " + ", ".join(f"{k_}={v:.3f}" for k_, v in stages.items()), file=sys.stderr, flush=True)
 
     default_rank = None
-    phir_sample = None
+    extra_phi = {}
+    direct_idx = np.sort(np.random.default_rng(4000 + 2).choice(w.n, size=min(args.direct_targets, w.n),
+                                                                 replace=False))
     if w.m2l_rank and args.m2l_rank is None and not args.no_compare_rank:
         # the same evaluate with the M2L rank of the 1e-6 singular-value threshold
         fr = kifmm.FMM(x, w.depth, w.p, cube=cube, eps_pinv=1e-7, eps_svd=1e-6, rank=0, flags=flags | m2l_flag,
                        nrhs=R)
         kr = kifmm.kifmm_ops_get_info(fr.ops)["rank_m2l"]
-        msr, stagesr = timed(fr.plan, f"m2l {args.m2l}, rank {kr}")
-        phir_sample = pot.cpu().numpy()[idx].astype(np.float64)
+        stepr = step_of(fr.plan)
+        for _ in range(args.warmup):
+            stepr()
+        msr = tm.block(stepr, args.steps)
+        stagesr = tm.stages(fr.plan, stepr, args.steps)
+        extra_phi["extra_phi_default_rank"] = pot.cpu().numpy()[direct_idx].astype(np.float64)
         fr.close()
         default_rank = {"m2l_rank": kr, "ms_per_step": msr, "value": w.n / (msr * 1e-3) / 1e6,
                         "m2l_ms": stagesr["m2l"], "stages_ms": stagesr}
+        print(f"# rank {kr}: {msr:.3f} ms/step", file=sys.stderr, flush=True)
 
-    # The ULI kernel of the default layout shares the GPU with the far field, so its span says
-    # little about its own speed: the fused D2T + ULI kernel of a one-stream plan on the same
-    # tree and operators is timed alone (stage events on the evaluate stream).
+    # The U-list kernel of the default layout shares the GPU with the far field, so its span says
+    # little about its own speed: the fused D2T + ULI kernel of a one-stream plan on the same tree
+    # and operators, with the main plan's leaf kernel and workgroup size, is timed alone.
     p2p_alone = None
     if R == 1 and not args.serial and not args.graph:
         layout = kifmm.KIFMM_UPPER_STREAM | kifmm.KIFMM_NO_UPPER_STREAM
-        plan_s = kifmm.kifmm_plan_create(f.tree, f.ops, 1, (flags & ~kifmm.KIFMM_VJP) | (m2l_flag & ~layout)
-                                         | kifmm.KIFMM_SERIAL)
+        pin = kifmm.KIFMM_LEAF_QUEUE if stats["leaf_queue"] else (
+            kifmm.KIFMM_LEAF_BLOCKS | (kifmm.KIFMM_LEAF_THREADS_256 if stats["p2p_threads"] == 256
+                                       else kifmm.KIFMM_LEAF_THREADS_320))
+        fl_s = (flags & ~(kifmm.KIFMM_VJP | kifmm.KIFMM_LEAF_QUEUE | kifmm.KIFMM_LEAF_BLOCKS |
+                          kifmm.KIFMM_LEAF_THREADS_256 | kifmm.KIFMM_LEAF_THREADS_320))
+        plan_s = kifmm.kifmm_plan_create(f.tree, f.ops, 1, fl_s | (m2l_flag & ~layout) | kifmm.KIFMM_SERIAL | pin)
+        st_s = kifmm.kifmm_plan_get_stats(plan_s)
+        steps_ = step_of(plan_s)
         for _ in range(2):
-            kifmm.kifmm_evaluate(plan_s, charges, pot, grad, stream.cuda_stream)
-        torch.cuda.synchronize()
-        kifmm.kifmm_plan_set_timing(plan_s, True)
-        kifmm.kifmm_plan_get_stage_times(plan_s, reset=True)
-        for _ in range(10):
-            kifmm.kifmm_evaluate(plan_s, charges, pot, grad, stream.cuda_stream)
-        torch.cuda.synchronize()
-        st_s = kifmm.kifmm_plan_get_stage_times(plan_s, reset=True)
+            steps_()
+        stg_s = tm.stages(plan_s, steps_, 10)
         kifmm.kifmm_plan_destroy(plan_s)
-        ms_s = st_s["p2p"][0] / max(st_s["p2p"][1], 1)
+        ms_s = stg_s["p2p"]
         pairs_s = stats["p2p_pairs"] + w.n * n * (1 if w.depth >= 2 else 0)
         fpp = P2P_FLOPS_PER_PAIR if grad is not None else 9 + 2 * R
         tf_s = fpp * pairs_s / (ms_s * 1e-3) / 1e12
-        p2p_alone = {"kernel": "k_p2p<0> (fused D2T + ULI, one-stream plan, alone on the GPU)", "bound": "alu",
-                     "achieved": tf_s, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": tf_s / PEAK_FP32_TFLOPS,
-                     "ms_per_launch": ms_s, "pairs_per_launch": pairs_s, "flop_per_pair": fpp, "launches": 10}
+        p2p_alone = {"kernel": leaf_kernel_name(st_s, True, 1) + " (fused D2T + ULI, one-stream plan, alone on the GPU)",
+                     "bound": "alu", "achieved": tf_s, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tf_s / PEAK_FP32_TFLOPS, "ms_per_launch": ms_s, "pairs_per_launch": pairs_s,
+                     "flop_per_pair": fpp, "launches": 10, "p2p_threads": st_s["p2p_threads"],
+                     "leaf_queue": bool(st_s["leaf_queue"])}
         print(f"# fused D2T + ULI alone: {ms_s:.3f} ms, {tf_s:.1f} TFLOP/s", file=sys.stderr, flush=True)
 
     # M2L (dominant kernel): 2 k^2 FLOP per (target, source) V-list pair; the split-bfloat16
     # forms execute each product as 3 or 6 bfloat16 products, counted against the BF16 peak.
     m2l_ms = stages["m2l"]
-    # the pairs of the KIFMM_STAGE_M2L launch (the leaf level alone when the levels above it
-    # run beside it on the plan's second stream)
     m2l_flop = 2.0 * k * k * stats["m2l_stage_pairs"] * R
     m2l_tflops = m2l_flop / (m2l_ms * 1e-3) / 1e12
-    # the KIFMM_STAGE_M2L launch (instance 0; the levels above the leaves, when they run on the
-    # plan's second stream, are instance 1)
     m2l_kernel = (f"k_m2l_bf16<{passes // 3 + 1}, 0>" if bf16 else
                   ["k_m2l<0>", "k_m2l_gather<0>", "k_m2l_wide", "k_m2l_bf16"][stats["m2l_form"]])
     traffic = load_traffic(w.name, m2l_kernel, {"m2l_rank": k, "upper_levels_on_second_stream": bool(stats["upper_stream"])})
-    # Leaf kernels: 20 FLOP per U-list pair (ULI) and per (target, downward-equivalent point) pair (D2T).
-    # By default ULI runs on the plan's own stream beside the far field and D2T is a separate
-    # kernel; with --serial one fused kernel does both.
-    # Potentials only: 9 + 2R FLOP per pair (the geometry once, 2 per right-hand side).
     p2p_ms = stages["p2p"]
-    fused = args.serial or R > 1
+    fused = args.serial or R > 1 or w.depth < 2   # one leaf kernel does D2T and ULI
     flop_pair = P2P_FLOPS_PER_PAIR if grad is not None else 9 + 2 * R
     d2t_pairs = w.n * n * (1 if w.depth >= 2 else 0)
     p2p_pairs = stats["p2p_pairs"] + (d2t_pairs if fused else 0)
     p2p_tflops = flop_pair * p2p_pairs / (p2p_ms * 1e-3) / 1e12
-    l2p_ms = stages["l2p"]
     if bf16:
         roofline = {"kernel": m2l_kernel, "bound": "mfma", "achieved": passes * m2l_tflops,
                     "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": passes * m2l_tflops / PEAK_BF16_TFLOPS,
@@ -384,58 +671,79 @@ def main():
                        stats["m2l_form"]],
                    "upper_levels_on_second_stream": bool(stats["upper_stream"]),
                    "m2l_lds_slab": stats["m2l_lds_slab"],
+                   "leaf_kernel": leaf_kernel_name(stats, args.serial, R),
                    "p2p_threads_per_workgroup": stats["p2p_threads"],
                    "step": ("forward (potentials and field) + backward (vector-Jacobian product of "
                             "sum w_i f_i, w ~ N(0,1))") if args.backward else "evaluate"},
+        "repeats": {"blocks": len(blocks), "steps_per_block": args.steps, "ms_per_step": blocks,
+                    "mean_ms": mean_ms, "std_ms": std_ms, "mean_mpoints_per_s": mean_std(rates)[0],
+                    "std_mpoints_per_s": mean_std(rates)[1]},
         "roofline": roofline,
-        "p2p": {"kernel": (f"k_leaf_multi<{R}> (fused D2T + ULI)" if R > 1 else
-                           "k_p2p<0>" if args.serial else "k_p2p<1> (ULI, overlapped with the far field)"),
+        "p2p": {"kernel": leaf_kernel_name(stats, args.serial, R) + ("" if args.serial or R > 1 else
+                                                                      " (ULI, beside the far field)"),
                 "bound": "alu", "achieved": p2p_tflops, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": p2p_tflops / PEAK_FP32_TFLOPS, "ms_per_launch": p2p_ms,
                 "pairs_per_launch": p2p_pairs, "flop_per_pair": flop_pair,
-                "d2t_ms_per_launch": None if fused else l2p_ms, "d2t_pairs_per_launch": d2t_pairs},
+                "d2t_ms_per_launch": stages["l2p"] if stages["l2p"] > 0 else None, "d2t_pairs_per_launch": d2t_pairs},
         "p2p_alone": p2p_alone,
         "stages_ms": stages,
+        "plan_tuning_us": {key: v for key, v in stats.items() if key.startswith("tune_us_") and v},
         "setup_s": t_setup,
         "cpu_baseline": None,
     }
-    if fp32_form is not None:
-        result["fp32_form"] = fp32_form
     if default_rank is not None:
         result["default_rank"] = default_rank
     if R > 1:
         result["point_rhs_per_s"] = w.n * R / (ms * 1e-3)
-    if single is not None:
-        result["single_rhs"] = single
-
-    # The oracle leg (a child process with single-threaded BLAS): the direct sum at the sampled
-    # targets for the accuracy figures and, unless skipped, the oracle timed on a bounded sample.
-    with tempfile.TemporaryDirectory() as tmp:
-        path = os.path.join(tmp, "gpu_sample.npz")
-        extra = {"phi_fp32": phi32_sample} if fp32_form is not None else {}
-        if phir_sample is not None:
-            extra["phi_rank"] = phir_sample
-        np.savez(path, idx=idx, phi=phi_sample, **extra)
-        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-        print("# oracle leg (1 thread)...", file=sys.stderr, flush=True)
-        cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker", "--workload", w.name,
-               "--sample-leaves", str(args.sample_leaves), "--sample-seed", str(args.sample_seed),
-               "--m2l-rank", str(rank), "--gpu-sample", path] + (["--accuracy-only"] if args.no_cpu_baseline else [])
-        r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=900)
-        if r.returncode == 0:
-            cb = json.loads(r.stdout.strip().splitlines()[-1])
-            result["rel_l2_vs_direct_sampled"] = cb.pop("rel_l2_vs_direct_sampled")
-            result["direct_sample_targets"] = cb.pop("direct_sample_targets")
-            if "fp32_rel_l2_vs_direct_sampled" in cb:
-                result["fp32_form"]["rel_l2_vs_direct_sampled"] = cb.pop("fp32_rel_l2_vs_direct_sampled")
-            if "rank_rel_l2_vs_direct_sampled" in cb:
-                result["default_rank"]["rel_l2_vs_direct_sampled"] = cb.pop("rank_rel_l2_vs_direct_sampled")
-            if not args.no_cpu_baseline:
-                result["cpu_baseline"] = cb
-        else:
-            print(r.stderr[-2000:], file=sys.stderr, flush=True)
     f.close()
+    del charges, pot, grad
+
+    # further workloads (GPU), before the CPU legs so that those time an idle host
+    if not args.no_next and args.workload == "cube1m_p6_d5" and not (bf16 or args.backward or args.graph or args.serial):
+        result["next_rows"] = next_rows(args, torch, dev)
+
+    # The oracle leg (a child process with single-threaded BLAS): the oracle timed on a sample,
+    # the GPU's parity with it on the sampled leaves, and the direct sum at sampled targets;
+    # then the same timing with every core the process may use.
+    gate = {"oracle_tol": ORACLE_TOL[args.m2l], "direct_tol": DIRECT_TOL}
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "gpu.npz")
+        sample = {"phi": phi_all.astype(np.float64), "direct_idx": direct_idx}
+        if grad_all is not None:
+            sample["grad"] = grad_all.astype(np.float64)
+        sample.update(extra_phi)
+        np.savez(path, **sample)
+        print("# oracle leg (1 thread)...", file=sys.stderr, flush=True)
+        base = ["--sample-leaves", str(args.sample_leaves), "--sample-seed", str(args.sample_seed),
+                "--m2l-rank", str(rank), "--direct-grad-targets", str(args.direct_grad_targets)]
+        one = run_child("--oracle-worker", path, w.name, base, 1)
+        cores = len(os.sched_getaffinity(0))
+        allc = None
+        if one is not None and not args.no_cpu_baseline:
+            print(f"# oracle leg ({cores} threads)...", file=sys.stderr, flush=True)
+            allc = run_child("--oracle-worker", path, w.name, base + ["--timing-only"], cores)
+    if one is not None:
+        result["accuracy"] = {"oracle_parity": one["oracle_parity"], "direct": one["direct"]}
+        if not args.no_cpu_baseline:
+            result["cpu_baseline"] = one["timing"]
+            if allc is not None:
+                result["cpu_baseline_all_cores"] = allc["timing"]
+        op, dr = one["oracle_parity"], one["direct"]
+        checks = [op["rel_l2_phi"] <= gate["oracle_tol"], dr["rel_l2_phi"] <= DIRECT_TOL]
+        if "rel_l2_grad" in op:
+            checks.append(op["rel_l2_grad"] <= gate["oracle_tol"])
+        gate["passed"] = all(checks)
+        if default_rank is not None and "phi_default_rank" in dr:
+            default_rank["rel_l2_vs_direct_sampled"] = dr["phi_default_rank"]
+    else:
+        gate["passed"] = False
+        gate["reason"] = "the oracle leg did not run or failed"
+    result["accuracy_gate"] = gate
+    if not gate["passed"]:
+        result["value"] = None
     print(json.dumps(result), flush=True)
+    if not gate["passed"]:
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <utility>
 #include <string>
 
 #include "common.hpp"
@@ -68,9 +69,14 @@ Tree* build_tree(const float* xyz, int64_t n, int depth, const double* cube) {
       }
       key[i] = morton_encode(c[0], c[1], c[2], depth);
     }
-    t->order.resize(n);
-    std::iota(t->order.begin(), t->order.end(), 0);
-    std::stable_sort(t->order.begin(), t->order.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+    // Sort (key, input index) pairs: equal keys keep input order.
+    {
+      std::vector<std::pair<uint64_t, int64_t>> kv(n);
+      for (int64_t i = 0; i < n; ++i) kv[i] = {key[i], i};
+      std::sort(kv.begin(), kv.end());
+      t->order.resize(n);
+      for (int64_t s = 0; s < n; ++s) t->order[s] = kv[s].second;
+    }
 
     // Non-empty leaves and their point ranges in sorted order.
     t->keys.assign(depth + 1, {});
