@@ -203,7 +203,9 @@ kifmm_status kifmm_ops_destroy(kifmm_ops ops);
  * with FP32 accumulation, each operand split into bfloat16 pieces (split
  * bfloat16): two pieces and three products (a0 b0 + a0 b1 + a1 b0, each
  * product to about 3 * 2^-16 relative), or three pieces and six products (to
- * about 2^-24, the accuracy of the plain FP32 path).  Everything else stays
+ * about 2^-24, the accuracy of the plain FP32 path).  KIFMM_M2L_BF16X3 uses
+ * the three products at the leaf level and six above it, where the
+ * translations carry the far field of more sources.  Everything else stays
  * FP32 and the operators are still computed in FP64.
  *
  * By default the U-list sum (ULI), which does not depend on the far field
@@ -390,11 +392,13 @@ kifmm_status kifmm_plan_get_stage_times(kifmm_plan plan, double* ms, int64_t* co
  *              not timed,
  *   stats[18..19] = plan-time timing of the M2L forms in microseconds
  *              (blocked, gathered); 0 where not timed,
- *   stats[20..21] = plan-time timing of the leaf sums in microseconds
- *              (per-parent kernels, work queue); 0 where not timed.
+ *   stats[20..21] = plan-time timing of the whole evaluate in microseconds with
+ *              the per-parent leaf kernels and with the work queue (each at its
+ *              best stream layout); 0 where not timed,
+ *   stats[22] = V-list pairs whose target is at the leaf level.
  * At most `count` entries are written (KIFMM_N_STATS in all).  KIFMM_E_INVALID
  * if stats is null or count is negative. */
-#define KIFMM_N_STATS 22
+#define KIFMM_N_STATS 23
 kifmm_status kifmm_plan_get_stats(kifmm_plan plan, int64_t* stats, int count);
 
 /* Copy a level's densities to the host after the stream is idle, as float in

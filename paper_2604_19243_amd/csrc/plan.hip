@@ -451,23 +451,31 @@ void prepare(Plan* P, Staging& S) {
       // FP64 remainder.  Layout [316][row block][16-k chunk][piece][64 lanes][8],
       // lane (i, h) holding C[32 rb + i][16 c + 8 h .. + 7], so that one wave's
       // load of a piece of a chunk is 1 KiB of contiguous memory.
-      const int np = P->m2l_pieces;
       const int nchunk = kst / 16;
-      P->core_stride16 = (size_t)P->m2l_rb * nchunk * 64 * np;
-      std::vector<uint16_t> wb((size_t)kNumOffsets * P->core_stride16 * 8, 0);
-      for (int t = 0; t < kNumOffsets; ++t)
-        for (int a = 0; a < k; ++a)
-          for (int b = 0; b < k; ++b) {
-            double rem = O.cores[((size_t)t * k + a) * k + b];
-            const size_t chunk = ((size_t)t * P->m2l_rb + a / 32) * nchunk + b / 16;
-            const int lane = (a % 32) + 32 * ((b % 16) / 8);
-            for (int q = 0; q < np; ++q) {
-              const uint16_t piece = bf16_round(rem);
-              rem -= bf16_value(piece);
-              wb[((chunk * np + q) * 64 + lane) * 8 + b % 8] = piece;
+      auto split_cores = [&](int np, size_t& stride16) {
+        stride16 = (size_t)P->m2l_rb * nchunk * 64 * np;
+        std::vector<uint16_t> wb((size_t)kNumOffsets * stride16 * 8, 0);
+        for (int t = 0; t < kNumOffsets; ++t)
+          for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) {
+              double rem = O.cores[((size_t)t * k + a) * k + b];
+              const size_t chunk = ((size_t)t * P->m2l_rb + a / 32) * nchunk + b / 16;
+              const int lane = (a % 32) + 32 * ((b % 16) / 8);
+              for (int q = 0; q < np; ++q) {
+                const uint16_t piece = bf16_round(rem);
+                rem -= bf16_value(piece);
+                wb[((chunk * np + q) * 64 + lane) * 8 + b % 8] = piece;
+              }
             }
-          }
-      S.data((void**)&P->d_cores_b, std::move(wb));
+        return wb;
+      };
+      S.data((void**)&P->d_cores_b, split_cores(P->m2l_pieces, P->core_stride16));
+      // The three-product form runs the levels above the leaves with six products:
+      // their translations carry the far field of many more sources (its magnitude
+      // grows about as 2^(L-l)/2 towards the root for charges of random sign), so
+      // their product error dominates the result's while they hold about an eighth
+      // of the translations.
+      if (P->m2l_pieces == 2 && L > 2) S.data((void**)&P->d_cores_b3, split_cores(3, P->core_stride16_3));
     }
 
     // Per-level lists of non-empty boxes' slots (U2U scatter, D2D gather).
@@ -630,7 +638,11 @@ void prepare(Plan* P, Staging& S) {
     // Explicit per-target V lists (Table 1: children of the parent's colleagues,
     // not adjacent, non-empty) as (core index, source slot), for the wide and
     // the gathered M2L forms.
-    const bool want_gather = nrhs == 1 && P->m2l_pieces == 0 && !(flags & KIFMM_M2L_BLOCKED);
+    // The gathered form pays off only where most blocked columns would be empty
+    // (sparse trees); on trees whose leaf slots are mostly full it is not built.
+    const bool sparse = (double)NBL < 0.6 * (double)SL;
+    const bool want_gather = nrhs == 1 && P->m2l_pieces == 0 && !(flags & KIFMM_M2L_BLOCKED) &&
+                             ((flags & KIFMM_M2L_GATHER) || sparse);
     if (P->m2l_wide || want_gather) {
       std::vector<int> idx7(343, -1);
       for (int t = 0; t < kNumOffsets; ++t)
@@ -773,7 +785,8 @@ void check_launches(const Plan* P) {
     fail(KIFMM_E_INVALID, "leaf kernel configuration not available for this tree and order");
   if (P->far) {
     if (!p2m_supported(P->n)) fail(KIFMM_E_INVALID, "the S2U kernel supports at most 768 surface points");
-    const bool ok = P->m2l_pieces ? m2l_bf16_supported(P->m2l_pieces, P->m2l_rb, P->kst)
+    const bool ok = P->m2l_pieces ? m2l_bf16_supported(P->m2l_pieces, P->m2l_rb, P->kst) &&
+                                        m2l_bf16_supported(3, P->m2l_rb, P->kst)
                                   : m2l_supported(P->m2l_rb, P->kst, P->m2l_lds_ld);
     if (!ok) fail(KIFMM_E_INVALID, "M2L kernel configuration not available for this rank");
   }
@@ -877,7 +890,8 @@ void plan_stats(const Plan* P, int64_t* v) {
       P->nrhs == 1 ? P->p2p_threads : 0,
       P->leaf_queue ? 1 : 0, P->leaf_queue ? P->n_tiles : 0,
       us(P->tune_ms[0][0]), us(P->tune_ms[0][1]), us(P->tune_ms[1][0]), us(P->tune_ms[1][1]),
-      us(P->m2l_tune_ms[0]), us(P->m2l_tune_ms[1]), us(P->leaf_tune_ms[0]), us(P->leaf_tune_ms[1])};
+      us(P->m2l_tune_ms[0]), us(P->m2l_tune_ms[1]), us(P->leaf_tune_ms[0]), us(P->leaf_tune_ms[1]),
+      P->m2l_pairs_leaf};
   for (int i = 0; i < KIFMM_N_STATS; ++i) v[i] = vals[i];
 }
 
@@ -956,6 +970,20 @@ bool launch_m2l_form(Plan* P, hipStream_t st, int part) {
   }
   const int i0 = part == 2 ? P->n_items_leaf : 0;
   const int i1 = part == 1 ? P->n_items_leaf : P->n_items;
+  if (P->m2l_pieces == 2 && P->d_cores_b3) {
+    // three products at the leaf level, six above it
+    const int split = P->n_items_leaf;
+    bool ok = true;
+    if (i0 < split)
+      ok = launch_m2l_bf16(2, P->m2l_rb, P->d_cores_b, P->core_stride16, kst, m2l_bf16_lds_ld16(2), P->d_items + i0,
+                           std::min(i1, split) - i0, P->d_tgt_blk, P->d_src_blk, P->d_pair_offs, P->d_uhat,
+                           P->d_chat_part, R * TS * kst, R, TS * kst, st, part == 2);
+    if (ok && i1 > split)
+      ok = launch_m2l_bf16(3, P->m2l_rb, P->d_cores_b3, P->core_stride16_3, kst, m2l_bf16_lds_ld16(3),
+                           P->d_items + std::max(i0, split), i1 - std::max(i0, split), P->d_tgt_blk, P->d_src_blk,
+                           P->d_pair_offs, P->d_uhat, P->d_chat_part, R * TS * kst, R, TS * kst, st, true);
+    return ok;
+  }
   if (P->m2l_pieces)
     return launch_m2l_bf16(P->m2l_pieces, P->m2l_rb, P->d_cores_b, P->core_stride16, kst,
                            m2l_bf16_lds_ld16(P->m2l_pieces), P->d_items + i0, i1 - i0, P->d_tgt_blk, P->d_src_blk,

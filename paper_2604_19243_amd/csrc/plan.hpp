@@ -46,6 +46,8 @@ struct Plan : Object {
   int m2l_pieces = 0;                    // bfloat16 pieces per M2L operand (0: plain FP32)
   uint16_t* d_cores_b = nullptr;         // split-bfloat16 cores (lane order, all pieces)
   size_t core_stride16 = 0;              // one offset's split cores, 16-byte units
+  uint16_t* d_cores_b3 = nullptr;        // three-piece cores for the levels above the leaves of a two-piece plan
+  size_t core_stride16_3 = 0;
   std::vector<int*> d_nbslot;
   int* d_nonempty = nullptr;             // global slots of all non-empty boxes, levels 2..L
   int n_nonempty = 0;

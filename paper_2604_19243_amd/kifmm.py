@@ -39,7 +39,7 @@ KIFMM_LEAF_THREADS_256 = 1024
 KIFMM_LEAF_THREADS_320 = 2048
 KIFMM_LEAF_QUEUE = 4096
 KIFMM_LEAF_BLOCKS = 8192
-KIFMM_N_STATS = 22
+KIFMM_N_STATS = 23
 
 ALPHA_INNER = 1.05
 ALPHA_OUTER = 2.95
@@ -278,7 +278,8 @@ def kifmm_plan_get_stage_times(plan, reset=True):
 STATS_KEYS = ["p2p_pairs", "m2l_pairs", "leaf_slots", "m2l_targets", "k", "n", "nrhs", "m2l_form",
               "m2l_stage_pairs", "upper_stream", "m2l_lds_slab", "p2p_threads", "leaf_queue", "leaf_tiles",
               "tune_us_single_256", "tune_us_single_320", "tune_us_upper_256", "tune_us_upper_320",
-              "tune_us_m2l_blocked", "tune_us_m2l_gathered", "tune_us_leaf_blocks", "tune_us_leaf_queue"]
+              "tune_us_m2l_blocked", "tune_us_m2l_gathered", "tune_us_leaf_blocks", "tune_us_leaf_queue",
+              "m2l_pairs_leaf"]
 
 
 def kifmm_plan_get_stats(plan):
