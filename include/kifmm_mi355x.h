@@ -340,6 +340,24 @@ kifmm_status kifmm_evaluate(kifmm_plan plan, const float* charges, float* potent
  */
 kifmm_status kifmm_evaluate_vjp(kifmm_plan plan, const float* charges, const float* weights, const float* field,
                                 float* grad_charges, float* grad_points, void* stream);
+/*
+ * kifmm_evaluate_vjp without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The same arguments, results and stream rules as
+ * kifmm_evaluate_vjp, but the two [n][3] fields it needs live in a device array
+ * of the library (KIFMM_NOALLOC_MAX_POINTS x 6 floats = 48 MiB, held by each
+ * GPU the library runs on until the process ends) instead of plan memory, so
+ * the plan needs no KIFMM_VJP.  Plans with more than KIFMM_NOALLOC_MAX_POINTS
+ * points give KIFMM_E_INVALID, and grad_points needs KIFMM_GRADIENT
+ * (KIFMM_E_STATE).  Every call on one GPU shares that array: calls that
+ * overlap in time on one GPU (on different streams, or from different threads)
+ * race and must be ordered by the caller.  The fields are written in full by
+ * each call before they are read, so no call depends on an earlier one's
+ * contents.
+ */
+#define KIFMM_NOALLOC_MAX_POINTS 2097152
+kifmm_status kifmm_evaluate_vjp_noalloc(kifmm_plan plan, const float* charges, const float* weights,
+                                        const float* field, float* grad_charges, float* grad_points, void* stream);
 kifmm_status kifmm_plan_destroy(kifmm_plan plan);
 
 /* ------------------------------------------------- inspection, timing --- */

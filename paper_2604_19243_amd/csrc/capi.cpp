@@ -296,6 +296,14 @@ kifmm_status kifmm_evaluate_vjp(kifmm_plan plan, const float* charges, const flo
   });
 }
 
+kifmm_status kifmm_evaluate_vjp_noalloc(kifmm_plan plan, const float* charges, const float* weights,
+                                        const float* field, float* grad_charges, float* grad_points, void* stream) {
+  return guarded([&] {
+    Held<Plan> p = hold<Plan>(plan, kPlan);
+    evaluate_vjp_noalloc(p.p, charges, weights, field, grad_charges, grad_points, (hipStream_t)stream);
+  });
+}
+
 kifmm_status kifmm_plan_destroy(kifmm_plan plan) {
   return guarded([&] { drop_handle(plan, kPlan); });
 }

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <set>
@@ -102,12 +103,33 @@ struct Staging {
 std::mutex g_config_mu;
 std::set<int> g_configured;
 
-// Once per device, with the device current: kernel attributes.
+// Workspace of kifmm_evaluate_vjp_noalloc: the two [n][3] fields of the
+// derivative for n <= kNoAllocMaxPoints, in a device array of the library
+// rather than in memory a plan allocates.  Each GPU the library runs on holds
+// its own copy until the process ends.  In host code `scratch` names a host-side
+// stand-in: kernels and copies get the device address that hipGetSymbolAddress
+// gives on each device (g_scratch), never the array's name.
+constexpr int64_t kNoAllocMaxPoints = KIFMM_NOALLOC_MAX_POINTS;
+static __device__ __align__(256) float scratch[2 * 3 * kNoAllocMaxPoints];
+std::map<int, float*> g_scratch;  // device -> address of `scratch` there (under g_config_mu)
+
+// Once per device, with the device current: kernel attributes and the address
+// of the no-allocation workspace.
 void configure_device(int device) {
   std::lock_guard<std::mutex> lock(g_config_mu);
   if (g_configured.count(device)) return;
   hip_check(configure_kernels(), "kernel LDS configuration");
+  void* ptr = nullptr;
+  hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "address of the no-allocation workspace");
+  g_scratch[device] = static_cast<float*>(ptr);
   g_configured.insert(device);
+}
+
+float* scratch_address(int device) {
+  std::lock_guard<std::mutex> lock(g_config_mu);
+  auto it = g_scratch.find(device);
+  if (it == g_scratch.end()) fail(KIFMM_E_STATE, "internal: the device was not configured by a plan");
+  return it->second;
 }
 
 constexpr unsigned kAllFlags = KIFMM_POTENTIAL | KIFMM_GRADIENT | KIFMM_SERIAL | KIFMM_M2L_BF16X3 |
@@ -1208,6 +1230,20 @@ void evaluate_vjp(Plan* P, const float* charges, const float* weights, const flo
   if (grad_points && !(P->flags & KIFMM_GRADIENT))
     fail(KIFMM_E_STATE, "grad_points needs a plan with KIFMM_GRADIENT");
   vjp_enqueue(P, charges, weights, field, grad_charges, grad_points, P->d_vjp_fs, P->d_vjp_fw, st);
+}
+
+void evaluate_vjp_noalloc(Plan* P, const float* charges, const float* weights, const float* field,
+                          float* grad_charges, float* grad_points, hipStream_t st) {
+  require(charges != nullptr && weights != nullptr, "charges or weights is null");
+  require(grad_charges || grad_points, "at least one of grad_charges / grad_points must be given");
+  if (grad_points && !(P->flags & KIFMM_GRADIENT))
+    fail(KIFMM_E_STATE, "grad_points needs a plan with KIFMM_GRADIENT");
+  require(P->nrhs == 1, "the derivative needs a plan with one right-hand side");
+  require(P->N <= kNoAllocMaxPoints, "the no-allocation derivative takes at most " +
+                                         std::to_string(kNoAllocMaxPoints) + " points (the plan has " +
+                                         std::to_string(P->N) + ")");
+  float* base = scratch_address(P->device);
+  vjp_enqueue(P, charges, weights, field, grad_charges, grad_points, base, base + 3 * P->N, st);
 }
 
 // dL/ds = evaluate(w); dL/dx = w grad f_s + s grad f_w, with the two fields in fs_buf / fw_buf.

@@ -117,6 +117,10 @@ void evaluate_plan(Plan* plan, const float* charges, float* pot, float* grad, hi
 bool launch_m2l_form(Plan* plan, hipStream_t st, int part);
 void evaluate_vjp(Plan* plan, const float* charges, const float* weights, const float* field, float* grad_charges,
                   float* grad_points, hipStream_t st);
+// The same as evaluate_vjp with the two fields in the library's static device
+// workspace (no allocation; needs no KIFMM_VJP).
+void evaluate_vjp_noalloc(Plan* plan, const float* charges, const float* weights, const float* field,
+                          float* grad_charges, float* grad_points, hipStream_t st);
 void read_density(Plan* plan, int kind, int level, float* out, int64_t capacity);
 
 }  // namespace kifmm

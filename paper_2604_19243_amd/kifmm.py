@@ -40,6 +40,7 @@ KIFMM_LEAF_THREADS_320 = 2048
 KIFMM_LEAF_QUEUE = 4096
 KIFMM_LEAF_BLOCKS = 8192
 KIFMM_N_STATS = 23
+KIFMM_NOALLOC_MAX_POINTS = 2097152
 
 ALPHA_INNER = 1.05
 ALPHA_OUTER = 2.95
@@ -109,6 +110,7 @@ def library():
         "kifmm_set_device_memory_limit": (ctypes.c_int, [ctypes.c_int64]),
         "kifmm_evaluate": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
         "kifmm_evaluate_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+        "kifmm_evaluate_vjp_noalloc": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
         "kifmm_plan_destroy": (ctypes.c_int, [_VP]),
         "kifmm_plan_set_timing": (ctypes.c_int, [_VP, ctypes.c_int]),
         "kifmm_plan_get_stage_times": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int]),
@@ -258,6 +260,13 @@ def kifmm_evaluate_vjp(plan, charges, weights, field=None, grad_charges=None, gr
     """Vector-Jacobian product of the evaluate for L = sum_i w_i f_i (device arrays; see the header)."""
     _check(library().kifmm_evaluate_vjp(plan, _dev_ptr(charges), _dev_ptr(weights), _dev_ptr(field),
                                         _dev_ptr(grad_charges), _dev_ptr(grad_points), _stream(stream)))
+
+
+def kifmm_evaluate_vjp_noalloc(plan, charges, weights, field=None, grad_charges=None, grad_points=None,
+                               stream=None):
+    """kifmm_evaluate_vjp with its workspace in the library's static device array (no allocation)."""
+    _check(library().kifmm_evaluate_vjp_noalloc(plan, _dev_ptr(charges), _dev_ptr(weights), _dev_ptr(field),
+                                                _dev_ptr(grad_charges), _dev_ptr(grad_points), _stream(stream)))
 
 
 def kifmm_plan_destroy(plan):
