@@ -240,8 +240,20 @@ kifmm_status kifmm_ops_destroy(kifmm_ops ops);
  * KIFMM_LEAF_QUEUE: one-RHS plans run the U-list sum and D2T as one persistent
  * kernel over a work queue of target tiles (at most 64 targets of one leaf
  * each) instead of one workgroup per parent; for trees with uneven leaves.
- * By default plan creation times both for sparse trees (stats[12]); with
- * KIFMM_LEAF_BLOCKS the per-parent kernel is forced (at most one of the two).
+ * By default plan creation times both (stats[12]), the queue with 2, 4 and 8
+ * workgroups per CU (stats[24]); with KIFMM_LEAF_BLOCKS the per-parent kernel
+ * is forced (at most one of the two).
+ *
+ * Plan creation also times the LDS slab of the blocked FP32 M2L (stats[10],
+ * stats[25..28]).  Every timed choice is kept for the process: a later plan of
+ * the same shape (device, sizes, order, rank, flags, box and leaf occupancy)
+ * takes it without timing (stats[23]).  The leaf kernels' workgroup size and
+ * the second stream change no result bit; the M2L form, the LDS slab (the
+ * grouping of the FP32 sums over k) and the leaf kernel (blocks or queue)
+ * change results at the level of FP32 rounding.  KIFMM_NO_AUTOTUNE times
+ * nothing and takes the default of every choice no flag forces: blocked M2L
+ * with the slab that keeps the most waves resident, the second stream where it
+ * applies, per-parent leaf kernels of 320 threads.
  */
 #define KIFMM_POTENTIAL 1u
 #define KIFMM_GRADIENT 2u
@@ -259,6 +271,7 @@ kifmm_status kifmm_ops_destroy(kifmm_ops ops);
 #define KIFMM_LEAF_THREADS_320 2048u
 #define KIFMM_LEAF_QUEUE 4096u
 #define KIFMM_LEAF_BLOCKS 8192u
+#define KIFMM_NO_AUTOTUNE 16384u
 
 /*
  * Place a tree and its operators on the device of `stream` (the current
@@ -413,10 +426,16 @@ kifmm_status kifmm_plan_get_stage_times(kifmm_plan plan, double* ms, int64_t* co
  *   stats[20..21] = plan-time timing of the whole evaluate in microseconds with
  *              the per-parent leaf kernels and with the work queue (each at its
  *              best stream layout); 0 where not timed,
- *   stats[22] = V-list pairs whose target is at the leaf level.
+ *   stats[22] = V-list pairs whose target is at the leaf level,
+ *   stats[23] = 1 if the timed choices were taken from an earlier plan of the
+ *              same shape in this process (nothing was timed),
+ *   stats[24] = workgroups per CU of the persistent leaf kernel (0 if unused),
+ *   stats[25..28] = plan-time timing of the blocked FP32 M2L (all levels, with
+ *              its partial-sum reduction) in microseconds with 24, 32, 40 and 48
+ *              k per LDS slab; 0 where not timed.
  * At most `count` entries are written (KIFMM_N_STATS in all).  KIFMM_E_INVALID
  * if stats is null or count is negative. */
-#define KIFMM_N_STATS 23
+#define KIFMM_N_STATS 29
 kifmm_status kifmm_plan_get_stats(kifmm_plan plan, int64_t* stats, int count);
 
 /* Copy a level's densities to the host after the stream is idle, as float in

@@ -955,6 +955,53 @@ __device__ __forceinline__ void p2p_pair_masked(float xx, float xy, float xz, fl
   gz -= qr3 * dz;
 }
 
+// FP32 partial sums over at most this many sources, added into FP64 totals: the
+// sums over a leaf block's sources are long (hundreds of terms in dense leaves)
+// and, for charges of both signs, cancel.
+constexpr int kP2PChunk = 32;
+
+struct Sum4 {
+  double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+  __device__ __forceinline__ void add(float p, float x, float y, float z) {
+    phi += p;
+    gx += x;
+    gy += y;
+    gz += z;
+  }
+};
+
+// The pairs of one run of staged sources [a, b) (b - a a multiple of 4), eight
+// per step and a last step of four, in order, in chunks of kP2PChunk sources.
+template <bool MASKED>
+__device__ __forceinline__ void p2p_run(const float4* src, int a, int b, const float4& x, Sum4& acc) {
+  for (int c = a; c < b; c += kP2PChunk) {
+    const int e = min(c + kP2PChunk, b);  // e - c is a multiple of 4
+    float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+    int j = c;
+    for (; j + 8 <= e; j += 8) {
+      float4 y[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) y[u] = src[j + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (MASKED) p2p_pair_masked(x.x, x.y, x.z, y[u], phi, gx, gy, gz);
+        else p2p_pair(x.x, x.y, x.z, y[u], phi, gx, gy, gz);
+      }
+    }
+    if (j < e) {
+      float4 y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) y[u] = src[j + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (MASKED) p2p_pair_masked(x.x, x.y, x.z, y[u], phi, gx, gy, gz);
+        else p2p_pair(x.x, x.y, x.z, y[u], phi, gx, gy, gz);
+      }
+    }
+    acc.add(phi, gx, gy, gz);
+  }
+}
+
 // MODE 0: fused near + far field; MODE 1: near field only, written in sorted
 // order to `near` (phi, grad) for a later MODE 2 launch; MODE 2: far field only,
 // added to `near` and written to input order.
@@ -1029,50 +1076,45 @@ __global__ __launch_bounds__(kP2PMaxThreads) void k_p2p(const float4* __restrict
     while (o + 1 < group_slots && s_cs[o + 1] <= ti) ++o;
     const float4 x = pts[ti];
     const int bx = 1 + (o & 1), by = 1 + ((o >> 1) & 1), bz = 1 + ((o >> 2) & 1);
-    // Two-level summation: FP32 partial sums per source leaf and per block of 8
-    // surface points, accumulated in FP64 (the D2T sum cancels heavily).
+    // Two-level summation: FP32 partial sums over at most kP2PChunk sources and per block
+    // of 8 surface points, accumulated in FP64 (the sums cancel heavily).
     double aphi = 0.0, agx = 0.0, agy = 0.0, agz = 0.0;
     if (kNear) {
+      // The three leaves dx = -1, 0, 1 of a (dy, dz) row are consecutive in the
+      // x-fastest block order, so their staged sources form one run: nine runs
+      // per target.  The run holding the target's own leaf tests r > 0.
+      Sum4 acc;
       for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-          for (int dx = -1; dx <= 1; ++dx) {
-            const int e = (bx + dx) + 4 * (by + dy) + 16 * (bz + dz);
-            const bool self = (dx == 0) & (dy == 0) & (dz == 0);
-            float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
-            if (in_lds) {
-              const int a = s_off[e], b = s_off[e + 1];  // b - a is a multiple of 4
-              if (self) {
-                for (int j = a; j < b; j += 4) {
-                  const float4 y0 = s_src[j], y1 = s_src[j + 1], y2 = s_src[j + 2], y3 = s_src[j + 3];
-                  p2p_pair_masked(x.x, x.y, x.z, y0, phi, gx, gy, gz);
-                  p2p_pair_masked(x.x, x.y, x.z, y1, phi, gx, gy, gz);
-                  p2p_pair_masked(x.x, x.y, x.z, y2, phi, gx, gy, gz);
-                  p2p_pair_masked(x.x, x.y, x.z, y3, phi, gx, gy, gz);
-                }
-              } else {
-                for (int j = a; j < b; j += 4) {
-                  const float4 y0 = s_src[j], y1 = s_src[j + 1], y2 = s_src[j + 2], y3 = s_src[j + 3];
-                  p2p_pair(x.x, x.y, x.z, y0, phi, gx, gy, gz);
-                  p2p_pair(x.x, x.y, x.z, y1, phi, gx, gy, gz);
-                  p2p_pair(x.x, x.y, x.z, y2, phi, gx, gy, gz);
-                  p2p_pair(x.x, x.y, x.z, y3, phi, gx, gy, gz);
-                }
-              }
-            } else {
-              const int slot = s_slot[e];
-              if (slot >= 0) {
-                const int a = start[slot], b = start[slot + 1];
-                if (self)
-                  for (int j = a; j < b; ++j) p2p_pair_masked(x.x, x.y, x.z, pts[j], phi, gx, gy, gz);
+        for (int dy = -1; dy <= 1; ++dy) {
+          const int e0 = (bx - 1) + 4 * (by + dy) + 16 * (bz + dz);
+          const bool own = (dy == 0) & (dz == 0);
+          if (in_lds) {
+            const int a = s_off[e0], b = s_off[e0 + 3];  // b - a is a multiple of 4
+            if (own)
+              p2p_run<true>(s_src, a, b, x, acc);
+            else
+              p2p_run<false>(s_src, a, b, x, acc);
+          } else {
+            for (int dx = 0; dx < 3; ++dx) {
+              const int slot = s_slot[e0 + dx];
+              if (slot < 0) continue;
+              const int a = start[slot], b = start[slot + 1];
+              for (int c = a; c < b; c += kP2PChunk) {
+                float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+                const int e = min(c + kP2PChunk, b);
+                if (own)
+                  for (int j = c; j < e; ++j) p2p_pair_masked(x.x, x.y, x.z, pts[j], phi, gx, gy, gz);
                 else
-                  for (int j = a; j < b; ++j) p2p_pair(x.x, x.y, x.z, pts[j], phi, gx, gy, gz);
+                  for (int j = c; j < e; ++j) p2p_pair(x.x, x.y, x.z, pts[j], phi, gx, gy, gz);
+                acc.add(phi, gx, gy, gz);
               }
             }
-            aphi += phi;
-            agx += gx;
-            agy += gy;
-            agz += gz;
           }
+        }
+      aphi = acc.phi;
+      agx = acc.gx;
+      agy = acc.gy;
+      agz = acc.gz;
     } else {
       const float4 v = near[ti];
       aphi = v.x;
@@ -1141,18 +1183,61 @@ bool launch_p2p(int mode, const float4* pts, const int* start, const int* blk, i
 // leaf, one per lane, so all lanes of a wave share the tile's U list and D2T
 // surface: every source is read at a wave-uniform address (scalar loads) and
 // used by the whole wave, and loop bounds are wave-uniform.  Tiles are ordered
-// longest first at plan creation; each wave takes the next tile from a counter
+// longest first at plan creation; each wave takes its next tiles from a counter
 // in device memory (cleared by k_clear_queue before the launch) until none is
 // left, so the waves finish together on trees whose leaves hold very different
 // numbers of points (points on a surface).
 //
-// The sums follow k_p2p exactly: a leaf's sources in sorted order, four per
-// step (a step past the leaf's end repeats its last source with charge zero,
-// which adds exactly zero), FP32 partials per source leaf and per 8 surface
-// points accumulated in FP64 in the same order, so the two kernels give the
-// same result bits.  MODE as in k_p2p.
+// The sums are those of k_p2p: the sources of each leaf in sorted order (a step
+// past a leaf's end repeats its last source with charge zero, which adds exactly
+// zero), FP32 partials over at most kP2PChunk sources and over 8 surface points,
+// accumulated in FP64; the two kernels agree to FP32 rounding.  MODE as in k_p2p.
+constexpr int kQueueGrab = 4;  // tiles a wave takes from its counter at a time
+
 __global__ void k_clear_queue(int* queue, int n) {
-  if ((int)threadIdx.x < n) queue[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) queue[i] = 0;
+}
+
+// Sources j .. j + 3 of a leaf range ending at b (clamped to b - 1).  The index
+// is the same on every lane, but `lane0` (zero, opaque to the compiler) makes
+// them vector loads: those complete in order, so a wait for one step's sources
+// leaves the next step's loads in flight (scalar loads complete out of order,
+// and a wait for any of them is a wait for all).
+__device__ __forceinline__ void queue_load4(const float4* __restrict__ pts, int j, int b, int lane0, float4* y) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) y[u] = pts[min(j + u, b - 1) + lane0];
+}
+
+// The pairs of a target with the sources [a, b) of one leaf (a < b), four per step,
+// the next step's sources loaded while this step's are used.  A source position at
+// or past b (its load repeats the last source) gets charge zero and adds exactly
+// nothing.
+template <bool MASKED>
+__device__ __forceinline__ void queue_leaf(const float4* __restrict__ pts, int a, int b, const float4& x, Sum4& acc) {
+  int lane0;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(lane0));
+  float4 y[4];
+  queue_load4(pts, a, b, lane0, y);
+  float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+  for (int j = a; j < b; j += 4) {
+    float4 yn[4];
+    queue_load4(pts, j + 4, b, lane0, yn);  // past the end: unused
+    __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of this step's arithmetic
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      float4 yu = y[u];
+      if (j + u >= b) yu.w = 0.f;
+      if (MASKED) p2p_pair_masked(x.x, x.y, x.z, yu, phi, gx, gy, gz);
+      else p2p_pair(x.x, x.y, x.z, yu, phi, gx, gy, gz);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) y[u] = yn[u];
+    if ((j - a + 4) % kP2PChunk == 0 || j + 4 >= b) {
+      acc.add(phi, gx, gy, gz);
+      phi = gx = gy = gz = 0.f;
+    }
+  }
 }
 
 template <int MODE>
@@ -1169,18 +1254,37 @@ __global__ __launch_bounds__(256) void k_leaf_queue(const float4* __restrict__ p
   // the downward-equivalent surface alpha r S_m of a leaf (every leaf has the same
   // half-width), staged once per workgroup as k_p2p stages it
   __shared__ float4 s_de[kMaxLeafSurface];
+  // each wave's copy of its tile's downward-equivalent density (read by every lane)
+  __shared__ float s_dens[4][kMaxLeafSurface];
   const int lane = threadIdx.x & 63;
+  float* dens = s_dens[threadIdx.x >> 6];
   if (kFar && far) {
     const float sc = alpha * centers[0].w;
     for (int m = threadIdx.x; m < n; m += blockDim.x)
       s_de[m] = make_float4(sc * surf[3 * m], sc * surf[3 * m + 1], sc * surf[3 * m + 2], 0.f);
     __syncthreads();
   }
+  // The tiles t = xcd + 8 i (i < n_x) belong to the workgroups of one XCD (the
+  // hardware deals workgroups to the eight XCDs in turn), each XCD with a counter
+  // of its own, so that eight counters share the atomic traffic.  A wave takes
+  // tile i = its index among the XCD's waves first, then groups of kQueueGrab
+  // tiles from the counter; every wave leaves once its group starts past n_x.
+  const int xcd = blockIdx.x & 7;
+  const int n_x = ntiles > xcd ? (ntiles - xcd + 7) / 8 : 0;
+  const int waves_x = (int)(gridDim.x >> 3) * 4;  // the grid is a multiple of 8 workgroups
+  int i = (int)(blockIdx.x >> 3) * 4 + (int)(threadIdx.x >> 6);
+  int left = 1;
   for (;;) {
-    int mine = 0;
-    if (lane == 0) mine = atomicAdd(queue, 1);
-    const int t = __builtin_amdgcn_readfirstlane(mine);
-    if (t >= ntiles) break;  // every wave leaves once the counter has passed the last tile
+    if (left == 0) {
+      int mine = 0;
+      if (lane == 0) mine = atomicAdd(queue + 16 * xcd, 1);
+      i = waves_x + kQueueGrab * __builtin_amdgcn_readfirstlane(mine);
+      left = kQueueGrab;
+    }
+    if (i >= n_x) break;
+    const int t = xcd + 8 * i;
+    ++i;
+    --left;
     const int4 tile = tiles[t];
     const int slot = tile.x, cnt = tile.z;
     const int ti = tile.y + min(lane, cnt - 1);
@@ -1189,41 +1293,27 @@ __global__ __launch_bounds__(256) void k_leaf_queue(const float4* __restrict__ p
     const int bx = 1 + (o & 1), by = 1 + ((o >> 1) & 1), bz = 1 + ((o >> 2) & 1);
     double aphi = 0.0, agx = 0.0, agy = 0.0, agz = 0.0;
     if (kNear) {
+      // the 27 leaves of the block around the tile's leaf; a leaf's sources four per
+      // step, the next step's loaded while this one is used
+      Sum4 acc;
       for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
+        for (int dy = -1; dy <= 1; ++dy) {
+          const bool own = (dy == 0) & (dz == 0);
           for (int dx = -1; dx <= 1; ++dx) {
             const int ns = blk[(size_t)g * 64 + (bx + dx) + 4 * (by + dy) + 16 * (bz + dz)];
             if (ns < 0) continue;
             const int a = start[ns], b = start[ns + 1];
-            float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
-            if (ns == slot) {
-              for (int j = a; j < b; j += 4) {
-                float4 y[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                  y[u] = pts[min(j + u, b - 1)];
-                  if (j + u >= b) y[u].w = 0.f;
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) p2p_pair_masked(x.x, x.y, x.z, y[u], phi, gx, gy, gz);
-              }
-            } else {
-              for (int j = a; j < b; j += 4) {
-                float4 y[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                  y[u] = pts[min(j + u, b - 1)];
-                  if (j + u >= b) y[u].w = 0.f;
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) p2p_pair(x.x, x.y, x.z, y[u], phi, gx, gy, gz);
-              }
-            }
-            aphi += phi;
-            agx += gx;
-            agy += gy;
-            agz += gz;
+            if (a >= b) continue;
+            if (own)
+              queue_leaf<true>(pts, a, b, x, acc);
+            else
+              queue_leaf<false>(pts, a, b, x, acc);
           }
+        }
+      aphi = acc.phi;
+      agx = acc.gx;
+      agy = acc.gy;
+      agz = acc.gz;
     } else {
       const float4 v = near[ti];
       aphi = v.x;
@@ -1235,12 +1325,16 @@ __global__ __launch_bounds__(256) void k_leaf_queue(const float4* __restrict__ p
       const float4 ch = centers[2 * slot], cl = centers[2 * slot + 1];
       const float xx = (x.x - ch.x) - cl.x, xy = (x.y - ch.y) - cl.y, xz = (x.z - ch.z) - cl.z;
       const float* dl = d + (size_t)slot * ldd;
+      // the density through LDS: one coalesced load per 64 values instead of a
+      // scalar load per value
+      for (int m = lane; m < n; m += 64) dens[m] = dl[m];
+      __builtin_amdgcn_wave_barrier();  // LDS accesses of one wave complete in order
       for (int m0 = 0; m0 < n; m0 += 8) {
         float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
         const int m1 = min(m0 + 8, n);
         for (int m = m0; m < m1; ++m) {
           const float4 de = s_de[m];
-          p2p_pair(xx, xy, xz, make_float4(de.x, de.y, de.z, dl[m]), phi, gx, gy, gz);
+          p2p_pair(xx, xy, xz, make_float4(de.x, de.y, de.z, dens[m]), phi, gx, gy, gz);
         }
         aphi += phi;
         agx += gx;
@@ -1265,7 +1359,7 @@ __global__ __launch_bounds__(256) void k_leaf_queue(const float4* __restrict__ p
 }
 
 void launch_clear_queue(int* queue, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_clear_queue, dim3(1), dim3(64), 0, s, queue, n);
+  hipLaunchKernelGGL(k_clear_queue, dim3(1), dim3(256), 0, s, queue, n);
 }
 
 bool launch_leaf_queue(int mode, const float4* pts, const int* start, const int4* tiles, int ntiles, int* queue,
@@ -1273,7 +1367,7 @@ bool launch_leaf_queue(int mode, const float4* pts, const int* start, const int4
                        float alpha, const float* d, int ldd, int far, const int* order, float* pot, float* grad,
                        float4* near, hipStream_t s) {
   if (ntiles <= 0) return true;
-  if (grid < 1 || mode < 0 || mode > 2) return false;
+  if (grid < 8 || (grid & 7) || mode < 0 || mode > 2) return false;
 #define KIFMM_LEAF_QUEUE(M)                                                                                  \
   hipLaunchKernelGGL(k_leaf_queue<M>, dim3(grid), dim3(256), 0, s, pts, start, tiles, ntiles, queue, blk,  \
                      group_slots, centers, surf, n, alpha, d, ldd, far, order, pot, grad, near)

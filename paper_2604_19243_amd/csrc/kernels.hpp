@@ -84,9 +84,10 @@ bool launch_p2p(int mode, const float4* pts, const int* start, const int* blk, i
                 const int* order, float* pot, float* grad, float4* near, int threads, hipStream_t s);
 
 // The same sums as k_p2p (modes as there) by a persistent kernel over tiles
-// (leaf slot, first sorted point, count <= 64, 0) taken from queue[0], which
-// launch_clear_queue zeroes (n counters) and must precede each launch.  `grid`
-// workgroups of four waves.
+// (leaf slot, first sorted point, count <= 64, 0) taken with the counters
+// queue[16 x], x = 0..7 (one per XCD), which launch_clear_queue zeroes (n ints)
+// before each launch.  `grid` workgroups of four waves, a multiple of 8.
+constexpr int kQueueInts = 128;  // counters of one launch (eight, 64 bytes apart)
 void launch_clear_queue(int* queue, int n, hipStream_t s);
 bool launch_leaf_queue(int mode, const float4* pts, const int* start, const int4* tiles, int ntiles, int* queue,
                        int grid, const int* blk, int group_slots, const float4* centers, const float* surf, int n,

@@ -135,7 +135,7 @@ float* scratch_address(int device) {
 constexpr unsigned kAllFlags = KIFMM_POTENTIAL | KIFMM_GRADIENT | KIFMM_SERIAL | KIFMM_M2L_BF16X3 |
                                KIFMM_M2L_BF16X6 | KIFMM_VJP | KIFMM_M2L_BLOCKED | KIFMM_M2L_GATHER |
                                KIFMM_UPPER_STREAM | KIFMM_NO_UPPER_STREAM | KIFMM_LEAF_THREADS_256 |
-                               KIFMM_LEAF_THREADS_320 | KIFMM_LEAF_QUEUE | KIFMM_LEAF_BLOCKS;
+                               KIFMM_LEAF_THREADS_320 | KIFMM_LEAF_QUEUE | KIFMM_LEAF_BLOCKS | KIFMM_NO_AUTOTUNE;
 
 void check_plan_args(Tree* tree, Ops* ops, int nrhs, unsigned flags) {
   require(tree && ops, "null tree or ops");
@@ -376,7 +376,7 @@ void prepare(Plan* P, Staging& S) {
       if (nt) S.data((void**)&P->d_tasks, std::move(tiles));
     } else if (nt) {
       S.data((void**)&P->d_tiles, std::move(tiles));
-      S.zeros<int>((void**)&P->d_queue, 2);
+      S.zeros<int>((void**)&P->d_queue, 2 * kQueueInts);
     }
   }
 
@@ -864,12 +864,8 @@ Plan* create_plan(Tree* tree, Ops* ops, int nrhs, unsigned flags, hipStream_t st
       hip_check(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming), "hipEventCreate");
       hip_check(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming), "hipEventCreate");
     }
-    {
-      int cus = 0;
-      hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device), "hipDeviceGetAttribute");
-      // persistent leaf kernel: eight workgroups of four waves per CU, at most one per four tiles
-      P->queue_grid = std::max(1, std::min(8 * cus, (P->n_tiles + 3) / 4));
-    }
+    hip_check(hipDeviceGetAttribute(&P->n_cus, hipDeviceAttributeMultiprocessorCount, device),
+              "hipDeviceGetAttribute");
     autotune(P, st);
   } catch (...) {
     delete P;
@@ -913,7 +909,8 @@ void plan_stats(const Plan* P, int64_t* v) {
       P->leaf_queue ? 1 : 0, P->leaf_queue ? P->n_tiles : 0,
       us(P->tune_ms[0][0]), us(P->tune_ms[0][1]), us(P->tune_ms[1][0]), us(P->tune_ms[1][1]),
       us(P->m2l_tune_ms[0]), us(P->m2l_tune_ms[1]), us(P->leaf_tune_ms[0]), us(P->leaf_tune_ms[1]),
-      P->m2l_pairs_leaf};
+      P->m2l_pairs_leaf, P->tuned_from_cache ? 1 : 0, P->leaf_queue ? P->queue_per_cu : 0,
+      us(P->slab_tune_ms[0]), us(P->slab_tune_ms[1]), us(P->slab_tune_ms[2]), us(P->slab_tune_ms[3])};
   for (int i = 0; i < KIFMM_N_STATS; ++i) v[i] = vals[i];
 }
 
@@ -1037,12 +1034,19 @@ struct JoinGuard {
 
 const char* kLeafInternal = "internal: leaf kernel configuration not available";
 
+// Workgroups of the persistent leaf kernel: queue_per_cu per CU, at most one per
+// four tiles, a multiple of 8 (one counter per XCD).
+int queue_grid(const Plan* P) {
+  const int want = std::min(P->queue_per_cu * P->n_cus, (P->n_tiles + 3) / 4);
+  return std::max(8, (want + 7) / 8 * 8);
+}
+
 // The one-RHS leaf sums (U-list, D2T or both, see k_p2p) by the plan's kernel.
 void launch_leaf_sums(Plan* P, int mode, const float* d_leaf, float* pot, float* grad, hipStream_t s) {
   bool ok;
   if (P->leaf_queue)
-    ok = launch_leaf_queue(mode, P->d_pts, P->d_start, P->d_tiles, P->n_tiles, P->d_queue + (mode == 2 ? 1 : 0),
-                           P->queue_grid, P->d_blk, P->group_slots, P->d_centers, P->d_surf, P->n,
+    ok = launch_leaf_queue(mode, P->d_pts, P->d_start, P->d_tiles, P->n_tiles,
+                           P->d_queue + (mode == 2 ? kQueueInts : 0), queue_grid(P), P->d_blk, P->group_slots, P->d_centers, P->d_surf, P->n,
                            (float)P->ops->alpha_outer, d_leaf, P->nst, P->far ? 1 : 0, P->d_order, pot, grad,
                            P->d_near, s);
   else
@@ -1072,7 +1076,7 @@ void evaluate_plan(Plan* P, const float* charges, float* pot, float* grad, hipSt
   const int N = (int)P->N;
   const int L = P->L;
   const float alpha = (float)P->ops->alpha_outer;
-  if (P->leaf_queue) launch_clear_queue(P->d_queue, 2, st);
+  if (P->leaf_queue) launch_clear_queue(P->d_queue, 2 * kQueueInts, st);
   P->stage_begin(KIFMM_STAGE_PERMUTE, st);
   if (R == 1)
     launch_permute(P->d_pts, charges, P->d_order, N, st);
@@ -1262,11 +1266,80 @@ void vjp_enqueue(Plan* P, const float* charges, const float* weights, const floa
   }
 }
 
+namespace {
+
+// Choices timed at plan creation, kept per process for plans of the same shape
+// (device, sizes, order, rank, flags and the occupancy of the tree's levels and
+// leaves), so that creating such a plan again times nothing.
+struct Tuned {
+  bool m2l_gather = false;
+  int m2l_lds_ld = 0;
+  bool up_on = false, leaf_queue = false;
+  int p2p_threads = kP2PMaxThreads, queue_per_cu = 8;
+  double m2l_tune_ms[2] = {0, 0}, slab_ms[4] = {0, 0, 0, 0}, tune_ms[2][2] = {{0, 0}, {0, 0}}, leaf_tune_ms[2] = {0, 0};
+};
+std::mutex g_tuned_mu;
+std::map<std::string, Tuned> g_tuned;
+
+std::string shape_key(const Plan* P) {
+  const Tree& T = *P->tree;
+  std::string key = std::to_string(P->device) + "|" + std::to_string(P->N) + "|" + std::to_string(P->L) + "|" +
+                    std::to_string(P->n) + "|" + std::to_string(P->k) + "|" + std::to_string(P->nrhs) + "|" +
+                    std::to_string(P->flags) + "|" + std::to_string(P->ops->alpha_inner) + "|";
+  for (int l = 0; l <= P->L; ++l) key += std::to_string(T.keys[l].size()) + ",";
+  // leaf occupancy histogram in powers of two
+  int64_t hist[40] = {};
+  for (size_t i = 0; i + 1 < T.leaf_start.size(); ++i) {
+    const int64_t c = T.leaf_start[i + 1] - T.leaf_start[i];
+    int b = 0;
+    while (b < 39 && (int64_t(1) << (b + 1)) <= c) ++b;
+    ++hist[b];
+  }
+  key += "|";
+  for (int b = 0; b < 40; ++b)
+    if (hist[b]) key += std::to_string(b) + ":" + std::to_string(hist[b]) + ",";
+  return key;
+}
+
+}  // namespace
+
 // Timed choices at plan creation, each by whole launches on the plan's own
 // tables (the work does not depend on the values): one warm-up, then the
-// median of the timed repeats.
+// median of the timed repeats.  A choice leaves its default only when it is at
+// least 2 % faster, so that run-to-run noise does not flip it.
+//   1. M2L form (one right-hand side, FP32): blocked or gathered.
+//   2. M2L LDS slab of the blocked FP32 form: 24, 32, 40 or 48 k per slab (the
+//      default is the slab that keeps the most waves resident).
+//   3. Evaluate layout (one right-hand side): the second stream for the levels
+//      above the leaves, and the leaf sums by the per-parent kernel (256 or 320
+//      threads) or the persistent work queue (2, 4 or 8 workgroups per CU).
 void autotune(Plan* P, hipStream_t st) {
   const unsigned flags = P->flags;
+  if (flags & KIFMM_LEAF_QUEUE) P->leaf_queue = true;
+  if (flags & KIFMM_NO_AUTOTUNE) {
+    P->m2l_gather = (flags & KIFMM_M2L_GATHER) != 0;
+    return;  // the defaults of prepare(); the second stream on where it exists
+  }
+  const std::string key = shape_key(P);
+  {
+    std::lock_guard<std::mutex> lock(g_tuned_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      const Tuned& t = it->second;
+      P->m2l_gather = t.m2l_gather;
+      if (t.m2l_lds_ld) P->m2l_lds_ld = t.m2l_lds_ld;
+      if (P->up) P->up_on = t.up_on;
+      P->leaf_queue = t.leaf_queue;
+      P->p2p_threads = t.p2p_threads;
+      P->queue_per_cu = t.queue_per_cu;
+      std::copy(t.m2l_tune_ms, t.m2l_tune_ms + 2, P->m2l_tune_ms);
+      std::copy(t.slab_ms, t.slab_ms + 4, P->slab_tune_ms);
+      for (int i = 0; i < 2; ++i) std::copy(t.tune_ms[i], t.tune_ms[i] + 2, P->tune_ms[i]);
+      std::copy(t.leaf_tune_ms, t.leaf_tune_ms + 2, P->leaf_tune_ms);
+      P->tuned_from_cache = true;
+      return;
+    }
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hip_check(hipEventCreate(&e0), "hipEventCreate");
   hip_check(hipEventCreate(&e1), "hipEventCreate");
@@ -1290,87 +1363,118 @@ void autotune(Plan* P, hipStream_t st) {
     }
     return median(t);
   };
+  const long long n_red = (long long)P->nrhs * P->total_slots * P->kst;
+  auto m2l_all = [&] {
+    if (!launch_m2l_form(P, st, 0)) fail(KIFMM_E_DEVICE, "internal: M2L kernel configuration not available");
+    if (!P->m2l_gather && !P->m2l_wide) launch_sum_parts(P->d_chat_part, P->d_chat, n_red, n_red, st);
+  };
 
-  // The one-RHS M2L form: blocked (with its partial-sum reduction) or gathered.
+  // 1. The one-RHS M2L form.
   if (P->d_gunits && !(flags & (KIFMM_M2L_BLOCKED | KIFMM_M2L_GATHER))) {
-    const long long n_red = (long long)P->nrhs * P->total_slots * P->kst;
     for (int form = 0; form < 2; ++form) {
       P->m2l_gather = form == 1;
-      P->m2l_tune_ms[form] = time_ms(3, [&] {
-        if (!launch_m2l_form(P, st, 0)) fail(KIFMM_E_DEVICE, "internal: M2L kernel configuration not available");
-        if (!P->m2l_gather) launch_sum_parts(P->d_chat_part, P->d_chat, n_red, n_red, st);
-      });
+      P->m2l_tune_ms[form] = time_ms(3, m2l_all);
     }
-    hip_check(hipGetLastError(), "M2L timing");
-    P->m2l_gather = P->m2l_tune_ms[1] < P->m2l_tune_ms[0];
-    hip_check(hipMemsetAsync(P->d_chat, 0, sizeof(float) * (size_t)n_red, st), "chat reset");
+    P->m2l_gather = P->m2l_tune_ms[1] < 0.98 * P->m2l_tune_ms[0];
   }
+  // 2. The LDS slab of the blocked FP32 M2L.
+  if (P->far && !P->m2l_pieces && !P->m2l_gather && !P->m2l_wide) {
+    const int def = P->m2l_lds_ld;
+    double t_def = -1.0, best = -1.0;
+    int pick = def;
+    for (int i = 0; i < 4; ++i) {
+      const int ld = 24 + 8 * i + 4;
+      if (!m2l_supported(P->m2l_rb, P->kst, ld)) continue;
+      P->m2l_lds_ld = ld;
+      const double ms = time_ms(3, m2l_all);
+      P->slab_tune_ms[i] = ms;
+      if (ld == def) t_def = ms;
+      if (best < 0.0 || ms < best) {
+        best = ms;
+        pick = ld;
+      }
+    }
+    P->m2l_lds_ld = (t_def >= 0.0 && best > 0.98 * t_def) ? def : pick;
+  }
+  if (P->far && P->d_chat) hip_check(hipMemsetAsync(P->d_chat, 0, sizeof(float) * (size_t)n_red, st), "chat reset");
 
-  // The evaluate's layout: the second stream for the levels above the leaves, the
-  // per-parent leaf kernel's workgroup size, and per-parent kernel or work queue.
-  // The default is (second stream, per-parent kernel, 320 threads); another
-  // layout is kept only when it is at least 2 % faster, so that run-to-run noise
-  // does not flip the choice.
-  if (P->nrhs != 1) return;
+  // 3. The evaluate's layout.
   const bool tune_up = P->up != nullptr && !(flags & KIFMM_UPPER_STREAM);
   const bool tune_threads = P->side != nullptr && !(flags & (KIFMM_LEAF_THREADS_256 | KIFMM_LEAF_THREADS_320));
   const bool tune_queue = P->d_tiles != nullptr && !(flags & (KIFMM_LEAF_QUEUE | KIFMM_LEAF_BLOCKS));
-  if (flags & KIFMM_LEAF_QUEUE) P->leaf_queue = true;
-  if (!tune_up && !tune_threads && !tune_queue) return;
-  const int64_t n = P->N;
-  float *q = nullptr, *pot = nullptr, *grad = nullptr;
-  struct Buffers {
-    float** p[3];
-    ~Buffers() {
-      for (float** b : p)
-        if (*b) (void)hipFree(*b);
-    }
-  } buffers{{&q, &pot, &grad}};
-  hip_check(hipMalloc(&q, sizeof(float) * (size_t)n), "timing charges");
-  hip_check(hipMemsetAsync(q, 0, sizeof(float) * (size_t)n, st), "timing charges");
-  hip_check(hipMalloc(&pot, sizeof(float) * (size_t)n), "timing potentials");
-  if (flags & KIFMM_GRADIENT) hip_check(hipMalloc(&grad, 3 * sizeof(float) * (size_t)n), "timing field");
+  if (P->nrhs == 1 && (tune_up || tune_threads || tune_queue || P->leaf_queue)) {
+    const int64_t n = P->N;
+    float *q = nullptr, *pot = nullptr, *grad = nullptr;
+    struct Buffers {
+      float** p[3];
+      ~Buffers() {
+        for (float** b : p)
+          if (*b) (void)hipFree(*b);
+      }
+    } buffers{{&q, &pot, &grad}};
+    hip_check(hipMalloc(&q, sizeof(float) * (size_t)n), "timing charges");
+    hip_check(hipMemsetAsync(q, 0, sizeof(float) * (size_t)n, st), "timing charges");
+    hip_check(hipMalloc(&pot, sizeof(float) * (size_t)n), "timing potentials");
+    if (flags & KIFMM_GRADIENT) hip_check(hipMalloc(&grad, 3 * sizeof(float) * (size_t)n), "timing field");
 
-  struct Layout {
-    bool up_on, queue;
-    int threads;
-  };
-  const Layout def{P->up != nullptr, P->leaf_queue, P->p2p_threads};
-  std::vector<Layout> cands;
-  for (int on = 0; on < 2; ++on) {
-    if (on != (int)def.up_on && !tune_up) continue;
-    for (int qu = 0; qu < 2; ++qu) {
-      if (qu != (int)def.queue && !tune_queue) continue;
-      for (int th : {256, kP2PMaxThreads}) {
-        if (qu ? th != def.threads : (th != def.threads && !tune_threads)) continue;
-        cands.push_back(Layout{on == 1, qu == 1, th});
+    struct Layout {
+      bool up_on, queue;
+      int threads, per_cu;
+    };
+    const Layout def{P->up != nullptr, P->leaf_queue, P->p2p_threads, 8};
+    std::vector<Layout> cands;
+    for (int on = 0; on < 2; ++on) {
+      if (on != (int)def.up_on && !tune_up) continue;
+      for (int qu = 0; qu < 2; ++qu) {
+        if (qu != (int)def.queue && !tune_queue) continue;
+        if (qu) {
+          for (int per_cu : {2, 4, 8}) cands.push_back(Layout{on == 1, true, def.threads, per_cu});
+        } else {
+          for (int th : {256, kP2PMaxThreads})
+            if (th == def.threads || tune_threads) cands.push_back(Layout{on == 1, false, th, def.per_cu});
+        }
       }
     }
-  }
-  double best = -1.0, t_def = -1.0;
-  Layout pick = def;
-  double best_blocks = -1.0, best_queue = -1.0;
-  for (const Layout& c : cands) {
-    P->up_on = c.up_on;
-    P->leaf_queue = c.queue;
-    P->p2p_threads = c.threads;
-    const double ms = time_ms(5, [&] { evaluate_plan(P, q, pot, grad, st); });
-    if (!c.queue) P->tune_ms[c.up_on ? 1 : 0][c.threads == 256 ? 0 : 1] = ms;
-    double& slot = c.queue ? best_queue : best_blocks;
-    if (slot < 0.0 || ms < slot) slot = ms;
-    if (c.up_on == def.up_on && c.queue == def.queue && c.threads == def.threads) t_def = ms;
-    if (best < 0.0 || ms < best) {
-      best = ms;
-      pick = c;
+    double best = -1.0, t_def = -1.0, best_blocks = -1.0, best_queue = -1.0;
+    Layout pick = def;
+    for (const Layout& c : cands) {
+      P->up_on = c.up_on;
+      P->leaf_queue = c.queue;
+      P->p2p_threads = c.threads;
+      P->queue_per_cu = c.per_cu;
+      const double ms = time_ms(5, [&] { evaluate_plan(P, q, pot, grad, st); });
+      if (!c.queue) P->tune_ms[c.up_on ? 1 : 0][c.threads == 256 ? 0 : 1] = ms;
+      double& slot = c.queue ? best_queue : best_blocks;
+      if (slot < 0.0 || ms < slot) slot = ms;
+      if (c.up_on == def.up_on && c.queue == def.queue && c.threads == def.threads && c.per_cu == def.per_cu)
+        t_def = ms;
+      if (best < 0.0 || ms < best) {
+        best = ms;
+        pick = c;
+      }
     }
+    if (t_def >= 0.0 && best > 0.98 * t_def) pick = def;
+    P->up_on = pick.up_on;
+    P->leaf_queue = pick.queue;
+    P->p2p_threads = pick.threads;
+    P->queue_per_cu = pick.per_cu;
+    P->leaf_tune_ms[0] = std::max(best_blocks, 0.0);
+    P->leaf_tune_ms[1] = std::max(best_queue, 0.0);
   }
-  if (t_def >= 0.0 && best > 0.98 * t_def) pick = def;
-  P->up_on = pick.up_on;
-  P->leaf_queue = pick.queue;
-  P->p2p_threads = pick.threads;
-  P->leaf_tune_ms[0] = std::max(best_blocks, 0.0);
-  P->leaf_tune_ms[1] = std::max(best_queue, 0.0);
   hip_check(hipStreamSynchronize(st), "plan-time timing");
+  Tuned t;
+  t.m2l_gather = P->m2l_gather;
+  t.m2l_lds_ld = P->m2l_lds_ld;
+  t.up_on = P->up_on;
+  t.leaf_queue = P->leaf_queue;
+  t.p2p_threads = P->p2p_threads;
+  t.queue_per_cu = P->queue_per_cu;
+  std::copy(P->m2l_tune_ms, P->m2l_tune_ms + 2, t.m2l_tune_ms);
+  std::copy(P->slab_tune_ms, P->slab_tune_ms + 4, t.slab_ms);
+  for (int i = 0; i < 2; ++i) std::copy(P->tune_ms[i], P->tune_ms[i] + 2, t.tune_ms[i]);
+  std::copy(P->leaf_tune_ms, P->leaf_tune_ms + 2, t.leaf_tune_ms);
+  std::lock_guard<std::mutex> lock(g_tuned_mu);
+  g_tuned[key] = t;
 }
 
 void read_density(Plan* P, int kind, int level, float* out, int64_t capacity) {

@@ -71,7 +71,10 @@ struct Plan : Object {
   int4* d_tiles = nullptr;               // work-queue tiles (leaf slot, first point, count <= 64, 0), longest first
   int n_tiles = 0;
   int* d_queue = nullptr;                // work-queue counter (cleared by a kernel before each use)
-  int queue_grid = 1;                    // workgroups of the persistent leaf kernel
+  int queue_per_cu = 8;                  // workgroups of the persistent leaf kernel per CU
+  int n_cus = 1;                         // compute units of the plan's device
+  double slab_tune_ms[4] = {0, 0, 0, 0}; // blocked FP32 M2L timed with 24, 32, 40, 48 k per LDS slab (ms)
+  bool tuned_from_cache = false;         // the timed choices came from an earlier plan of the same shape
   bool want_up = false, want_side = false;  // the plan has the second stream / the U-list stream
   bool on_device = false;                // device resources were created (the destructor releases them)
   hipEvent_t ev_up0 = nullptr, ev_up1 = nullptr;

@@ -39,7 +39,8 @@ KIFMM_LEAF_THREADS_256 = 1024
 KIFMM_LEAF_THREADS_320 = 2048
 KIFMM_LEAF_QUEUE = 4096
 KIFMM_LEAF_BLOCKS = 8192
-KIFMM_N_STATS = 23
+KIFMM_NO_AUTOTUNE = 16384
+KIFMM_N_STATS = 29
 KIFMM_NOALLOC_MAX_POINTS = 2097152
 
 ALPHA_INNER = 1.05
@@ -288,7 +289,8 @@ STATS_KEYS = ["p2p_pairs", "m2l_pairs", "leaf_slots", "m2l_targets", "k", "n", "
               "m2l_stage_pairs", "upper_stream", "m2l_lds_slab", "p2p_threads", "leaf_queue", "leaf_tiles",
               "tune_us_single_256", "tune_us_single_320", "tune_us_upper_256", "tune_us_upper_320",
               "tune_us_m2l_blocked", "tune_us_m2l_gathered", "tune_us_leaf_blocks", "tune_us_leaf_queue",
-              "m2l_pairs_leaf"]
+              "m2l_pairs_leaf", "tuned_from_cache", "queue_per_cu", "tune_us_slab_24", "tune_us_slab_32",
+              "tune_us_slab_40", "tune_us_slab_48"]
 
 
 def kifmm_plan_get_stats(plan):

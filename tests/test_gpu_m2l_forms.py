@@ -78,10 +78,11 @@ def test_upper_levels_stream_flags(rank):
     s = workloads.charges("uniform11", 40_000, 72)
     out = {}
     for name, fl in (("on", kifmm.KIFMM_UPPER_STREAM), ("off", kifmm.KIFMM_NO_UPPER_STREAM)):
-        phi, g, f = gpu_evaluate(x, s, 4, 6, UNIT, rank=rank, m2l="blocked", flags=fl)
+        # no timed choices: both plans take the same LDS slab (which groups the FP32 sums)
+        phi, g, f = gpu_evaluate(x, s, 4, 6, UNIT, rank=rank, m2l="blocked", flags=fl | kifmm.KIFMM_NO_AUTOTUNE)
         st = kifmm.kifmm_plan_get_stats(f.plan)
         assert st["upper_stream"] == (1 if name == "on" else 0)
-        assert st["p2p_threads"] in (256, 320)   # timed at plan creation; no result bit depends on it
+        assert st["p2p_threads"] == 320   # the default without timing
         f.close()
         out[name] = (phi, g)
     np.testing.assert_array_equal(out["on"][0], out["off"][0])
@@ -89,3 +90,28 @@ def test_upper_levels_stream_flags(rank):
     rphi, rg, t, _ = oracle_evaluate(x, s, 4, 6, UNIT, rank=rank or None)
     assert_parity("phi", out["on"][0], rphi, leaf_groups(t), TOL)
     assert_parity("grad", out["on"][1], rg, leaf_groups(t), TOL)
+
+
+def test_plan_time_choices_are_timed_once_per_shape():
+    # The timed choices (M2L form and LDS slab, stream layout, leaf kernel) are kept for the
+    # process: a second plan of the same shape takes them without timing and gives the same
+    # bits; a plan of another shape times its own.
+    log("autotuner cache")
+    x = workloads.points("cube", 30_000, 73)
+    s = workloads.charges("uniform11", 30_000, 74)
+    p1, g1, f1 = gpu_evaluate(x, s, 4, 5, UNIT)
+    st1 = kifmm.kifmm_plan_get_stats(f1.plan)
+    p2, g2, f2 = gpu_evaluate(x, s, 4, 5, UNIT)
+    st2 = kifmm.kifmm_plan_get_stats(f2.plan)
+    f1.close()
+    f2.close()
+    assert st2["tuned_from_cache"] == 1
+    for key in ("m2l_form", "m2l_lds_slab", "upper_stream", "p2p_threads", "leaf_queue", "queue_per_cu"):
+        assert st1[key] == st2[key], key
+    np.testing.assert_array_equal(p1, p2)
+    np.testing.assert_array_equal(g1, g2)
+    if st1["m2l_form"] == 0:   # the blocked form's slab was timed
+        assert sum(st1[f"tune_us_slab_{k}"] > 0 for k in (24, 32, 40, 48)) >= 2
+    _, _, f3 = gpu_evaluate(x[:20_000], s[:20_000], 4, 5, UNIT)
+    assert kifmm.kifmm_plan_get_stats(f3.plan)["tuned_from_cache"] == 0
+    f3.close()

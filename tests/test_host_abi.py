@@ -181,7 +181,7 @@ def test_error_paths(lib):
                      (kifmm.KIFMM_M2L_BLOCKED, kifmm.KIFMM_M2L_GATHER)):
             both = kifmm.KIFMM_POTENTIAL | pair[0] | pair[1]
             assert lib.kifmm_plan_create(t, o, 1, both, None, ctypes.byref(out)) == kifmm.KIFMM_E_INVALID, pair
-        assert lib.kifmm_plan_create(t, o, 1, 1 | 16384, None, ctypes.byref(out)) == kifmm.KIFMM_E_INVALID
+        assert lib.kifmm_plan_create(t, o, 1, 1 | 32768, None, ctypes.byref(out)) == kifmm.KIFMM_E_INVALID
         assert lib.kifmm_plan_create(t, o, 4, 1 | kifmm.KIFMM_LEAF_QUEUE, None, ctypes.byref(out)) == kifmm.KIFMM_E_INVALID
     finally:
         kifmm.kifmm_ops_destroy(o)
@@ -222,6 +222,7 @@ def test_binding_constants_match_the_header():
     for name in ("KIFMM_POTENTIAL", "KIFMM_GRADIENT", "KIFMM_SERIAL", "KIFMM_M2L_BF16X3", "KIFMM_M2L_BF16X6",
                  "KIFMM_VJP", "KIFMM_M2L_BLOCKED", "KIFMM_M2L_GATHER", "KIFMM_UPPER_STREAM", "KIFMM_NO_UPPER_STREAM",
                  "KIFMM_LEAF_THREADS_256", "KIFMM_LEAF_THREADS_320", "KIFMM_LEAF_QUEUE", "KIFMM_LEAF_BLOCKS",
+                 "KIFMM_NO_AUTOTUNE",
                  "KIFMM_N_STATS", "KIFMM_E_INVALID", "KIFMM_E_DEVICE", "KIFMM_E_STATE", "KIFMM_E_NOMEM"):
         assert name in found and hasattr(kifmm, name), name
     # the interface's flag values: potentials 1, gradients 2, split-bfloat16 M2L 4
