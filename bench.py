@@ -41,7 +41,8 @@ DIRECT_TOL = 1e-5                                              # the metric's re
 
 
 def kernel_source_hash():
-    with open(os.path.join(ROOT, "paper_2604_19243_amd", "csrc", "kernels.hip"), "rb") as f:
+    """Hash of the M2L kernels' source (the kernels whose HBM traffic profiles/traffic.json records)."""
+    with open(os.path.join(ROOT, "paper_2604_19243_amd", "csrc", "m2l.hip"), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
@@ -55,7 +56,7 @@ def load_traffic(workload, kernel, config):
     except (OSError, KeyError, ValueError):
         return None
     for entry in entries if isinstance(entries, list) else [entries]:
-        if entry.get("kernels_hip_sha256_16") == kernel_source_hash() and entry.get("config") == config:
+        if entry.get("m2l_hip_sha256_16") == kernel_source_hash() and entry.get("config") == config:
             return float(entry["hbm_bytes_per_launch"])
     return None
 

@@ -18,7 +18,7 @@ SRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libkifmm_mi355x.so")
 BUILD = os.path.join(ROOT, "_build")
 
-HIP_SOURCES = ["kernels.hip", "plan.hip"]
+HIP_SOURCES = ["gemm.hip", "m2l.hip", "leaf.hip", "plan.hip"]
 CPP_SOURCES = ["capi.cpp", "tree.cpp", "ops.cpp", "linalg.cpp"]
 
 

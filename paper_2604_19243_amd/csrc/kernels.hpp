@@ -1,4 +1,4 @@
-// Launchers of the HIP kernels (kernels.hip).  All pointers are device memory;
+// Launchers of the HIP kernels (gemm.hip, m2l.hip, leaf.hip).  All pointers are device memory;
 // every launch is asynchronous on stream `s`.
 #pragma once
 
@@ -13,6 +13,7 @@ constexpr size_t kMaxDynamicLds = 156 * 1024;
 constexpr int kMaxLeafSurface = 304;
 // Sets the dynamic LDS limit of every LDS-staging kernel on the current device.
 hipError_t configure_kernels();
+hipError_t configure_m2l_kernels();
 
 // An M2L work item (see k_m2l in kernels.hip): one aligned 4x4x4 block of
 // parents at one level, target sibling position o and source position o'.
@@ -96,9 +97,11 @@ bool launch_leaf_queue(int mode, const float4* pts, const int* start, const int4
 
 // Multi-RHS leaf kernels (R = 2, 4, 8, 16, 32; potentials only).  qs: sorted
 // charges [N][R].  q: check fields [R][leaf slots][ldq], qrs = leaf slots * ldq.
-// tasks: (leaf slot, first point offset in the leaf, point count <= 64, 0).
+// tasks: (leaf slot, first point offset in the leaf, point count, 0), at most
+// kMultiTile(R) points.
 // d: leaf-level downward densities, slot row `slot` at d + slot * ldd, right-hand
 // side r at + r * drs.  Return false for an unsupported R.
+constexpr int kMultiTile(int R) { return R == 32 ? 32 : 64; }
 void launch_permute_multi(float* qs, const float* charges, const int* order, int n, int R, hipStream_t s);
 bool launch_p2m_multi(int R, const float4* pts, const float* qs, const int* start, const int* leaves,
                       const float4* centers, const float* surf, int n, float alpha, float* q, int ldq, long long qrs,

@@ -1,0 +1,943 @@
+// Leaf and point kernels of the kiFMM evaluate for gfx950: the charge
+// permutation, the S2U check fields (P2M), the fused D2T and U-list sums (L2P
+// and P2P) per parent or over a work queue (vector ALUs), their multi-RHS forms
+// (32 right-hand sides on the matrix cores), and the derivative's combination.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "mfma.hpp"
+
+namespace kifmm {
+
+// ----------------------------------------------------------------- VJP ---
+// dL/dx_k = w_k grad f_s(x_k) + s_k grad f_w(x_k), elementwise over [n][3].
+__global__ void k_vjp_combine(const float* __restrict__ s, const float* __restrict__ w, const float* __restrict__ fs,
+                              const float* __restrict__ fw, float* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * n) return;
+  const int k = i / 3;
+  out[i] = w[k] * fs[i] + s[k] * fw[i];
+}
+
+void launch_vjp_combine(const float* s, const float* w, const float* fs, const float* fw, float* out, int n,
+                        hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_vjp_combine, dim3((3 * n + 255) / 256), dim3(256), 0, st, s, w, fs, fw, out, n);
+}
+
+// ------------------------------------------------------------- permute ---
+// Sorted sources: pts[i].w = charges[order[i]] (xyz are set at plan creation).
+__global__ void k_permute(float4* __restrict__ pts, const float* __restrict__ charges, const int* __restrict__ order,
+                          int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) pts[i].w = charges[order[i]];
+}
+
+void launch_permute(float4* pts, const float* charges, const int* order, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_permute, dim3((n + 255) / 256), dim3(256), 0, s, pts, charges, order, n);
+}
+
+// ----------------------------------------------------------------- P2M ---
+// S2U, first half: field of each non-empty leaf's sources on its upward-check
+// surface c + alpha_outer r S_m.  One wave per leaf; lane l owns the check
+// points l, l + 64, ... (NR = ceil(n / 64) of them, in registers), and the
+// sources are read uniformly by the whole wave, so that a source's position
+// relative to the leaf centre is formed once for all of the lane's check
+// points.  Geometry is relative to the leaf centre c = c_hi + c_lo (two
+// floats), so rounding is relative to the box size rather than to |c|.
+template <int NR>
+__global__ __launch_bounds__(256) void k_p2m(const float4* __restrict__ pts, const int* __restrict__ start,
+                                             const int* __restrict__ leaves, const float4* __restrict__ centers,
+                                             const float* __restrict__ surf, int n, float alpha, float* __restrict__ q,
+                                             int ldq, int nleaves) {
+  // the leaf, and with it every source address, is wave-uniform: scalar loads
+  const int leaf = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (leaf >= nleaves) return;
+  const int lane = threadIdx.x & 63;
+  const int slot = leaves[leaf];
+  const float4 ch = centers[2 * slot], cl = centers[2 * slot + 1];
+  const float sc = alpha * ch.w;
+  const int s0 = start[slot], s1 = start[slot + 1];  // s1 > s0: the leaf is not empty
+  float px[NR], py[NR], pz[NR], acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int m = min(lane + 64 * r, n - 1);  // lanes past n repeat the last point, not stored
+    px[r] = sc * surf[3 * m];
+    py[r] = sc * surf[3 * m + 1];
+    pz[r] = sc * surf[3 * m + 2];
+    acc[r] = 0.f;
+  }
+  // four sources per step, their loads issued together; past the end the last
+  // source repeats with charge 0 (it lies inside the leaf, away from the check
+  // surface, so its term is exactly 0)
+  for (int j = s0; j < s1; j += 4) {
+    float4 y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      y[u] = pts[min(j + u, s1 - 1)];
+      if (j + u >= s1) y[u].w = 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float rx = (y[u].x - ch.x) - cl.x, ry = (y[u].y - ch.y) - cl.y, rz = (y[u].z - ch.z) - cl.z;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const float dx = px[r] - rx, dy = py[r] - ry, dz = pz[r] - rz;
+        acc[r] += y[u].w * __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int m = lane + 64 * r;
+    if (m < n) q[(size_t)slot * ldq + m] = acc[r];
+  }
+}
+
+bool p2m_supported(int n) { return n >= 1 && n <= 768; }
+
+bool launch_p2m(const float4* pts, const int* start, const int* leaves, const float4* centers, const float* surf, int n,
+                float alpha, float* q, int ldq, int nleaves, hipStream_t s) {
+  if (nleaves <= 0) return true;
+  const dim3 grid((nleaves + 3) / 4);
+  switch ((n + 63) / 64) {
+#define KIFMM_P2M_CASE(R)                                                                                    \
+  case R:                                                                                                    \
+    hipLaunchKernelGGL(k_p2m<R>, grid, dim3(256), 0, s, pts, start, leaves, centers, surf, n, alpha, q, ldq, \
+                       nleaves);                                                                             \
+    break;
+    KIFMM_P2M_CASE(1)
+    KIFMM_P2M_CASE(2)
+    KIFMM_P2M_CASE(3)
+    KIFMM_P2M_CASE(4)
+    KIFMM_P2M_CASE(5)
+    KIFMM_P2M_CASE(6)
+    KIFMM_P2M_CASE(7)
+    KIFMM_P2M_CASE(8)
+    KIFMM_P2M_CASE(9)
+    KIFMM_P2M_CASE(10)
+    KIFMM_P2M_CASE(11)
+    KIFMM_P2M_CASE(12)
+#undef KIFMM_P2M_CASE
+    default:
+      return false;  // more than 768 check points
+  }
+  return true;
+}
+
+// ----------------------------------------------------------------- P2P ---
+// Fused D2T and ULI (Algorithm 1 steps 3b, 3c) for the leaves of one parent
+// (up to 8 siblings) per workgroup, written straight to input order.
+//
+// The siblings' U lists together cover the 4 x 4 x 4 block of leaves around
+// the parent; `blk` lists their slots (x fastest, -1 = none).  Their sources
+// are staged once in LDS, each leaf's range padded to a multiple of 4 with
+// zero-charge dummies at (FLT_MAX, FLT_MAX, FLT_MAX): r^2 overflows to +inf,
+// rsqrt gives 0 and the dummy adds exactly zero.  Each thread owns one target
+// and walks the 27 block entries around its own leaf, 4 sources per step.  Only
+// the leaf's own entry can hold a source at zero distance, so only that loop
+// tests r > 0.  D2T evaluates the downward-equivalent surface (alpha_outer r S_m
+// relative to the leaf centre, density d[m]) as n more sources, in
+// centre-relative coordinates.  A block whose padded sources exceed `cap` reads
+// them from global memory instead.
+//
+// Dynamic LDS: [cap] float4 sources, [n] float4 surface points, [8 n] floats d.
+//
+// Four or five waves per workgroup (the plan's choice).  At 30.5 points per
+// leaf a parent's siblings hold 244 targets on average (Poisson): 320 threads
+// take nearly every parent in one pass, where 256 leave about a fifth of the
+// workgroups a second pass on a few lanes while the workgroup keeps its LDS.
+// Each target's sums do not depend on the choice.
+extern __shared__ float4 s_p2p[];
+
+__device__ __forceinline__ void p2p_pair(float xx, float xy, float xz, float4 y, float& phi, float& gx, float& gy,
+                                         float& gz) {
+  const float dx = xx - y.x, dy = xy - y.y, dz = xz - y.z;
+  const float rinv = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+  const float qr = y.w * rinv;
+  const float qr3 = qr * rinv * rinv;
+  phi += qr;
+  gx -= qr3 * dx;
+  gy -= qr3 * dy;
+  gz -= qr3 * dz;
+}
+
+__device__ __forceinline__ void p2p_pair_masked(float xx, float xy, float xz, float4 y, float& phi, float& gx,
+                                                float& gy, float& gz) {
+  const float dx = xx - y.x, dy = xy - y.y, dz = xz - y.z;
+  const float r2 = dx * dx + dy * dy + dz * dz;
+  const float rinv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+  const float qr = y.w * rinv;
+  const float qr3 = qr * rinv * rinv;
+  phi += qr;
+  gx -= qr3 * dx;
+  gy -= qr3 * dy;
+  gz -= qr3 * dz;
+}
+
+// FP32 partial sums over at most this many sources, added into FP64 totals: the
+// sums over a leaf block's sources are long (hundreds of terms in dense leaves)
+// and, for charges of both signs, cancel.
+constexpr int kP2PChunk = 32;
+
+struct Sum4 {
+  double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+  __device__ __forceinline__ void add(float p, float x, float y, float z) {
+    phi += p;
+    gx += x;
+    gy += y;
+    gz += z;
+  }
+};
+
+// The pairs of one run of staged sources [a, b) (b - a a multiple of 4), eight
+// per step and a last step of four, in order, in chunks of kP2PChunk sources.
+template <bool MASKED>
+__device__ __forceinline__ void p2p_run(const float4* src, int a, int b, const float4& x, Sum4& acc) {
+  for (int c = a; c < b; c += kP2PChunk) {
+    const int e = min(c + kP2PChunk, b);  // e - c is a multiple of 4
+    float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+    int j = c;
+    for (; j + 8 <= e; j += 8) {
+      float4 y[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) y[u] = src[j + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (MASKED) p2p_pair_masked(x.x, x.y, x.z, y[u], phi, gx, gy, gz);
+        else p2p_pair(x.x, x.y, x.z, y[u], phi, gx, gy, gz);
+      }
+    }
+    if (j < e) {
+      float4 y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) y[u] = src[j + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (MASKED) p2p_pair_masked(x.x, x.y, x.z, y[u], phi, gx, gy, gz);
+        else p2p_pair(x.x, x.y, x.z, y[u], phi, gx, gy, gz);
+      }
+    }
+    acc.add(phi, gx, gy, gz);
+  }
+}
+
+// MODE 0: fused near + far field; MODE 1: near field only, written in sorted
+// order to `near` (phi, grad) for a later MODE 2 launch; MODE 2: far field only,
+// added to `near` and written to input order.
+template <int MODE>
+__global__ __launch_bounds__(kP2PMaxThreads) void k_p2p(const float4* __restrict__ pts, const int* __restrict__ start,
+                                             const int* __restrict__ blk, int group_slots, int cap,
+                                             const float4* __restrict__ centers, const float* __restrict__ surf,
+                                             int n, float alpha, const float* __restrict__ d, int ldd, int far,
+                                             const int* __restrict__ order, float* __restrict__ pot,
+                                             float* __restrict__ grad, float4* __restrict__ near) {
+  constexpr bool kNear = MODE != 2;
+  constexpr bool kFar = MODE != 1;
+  float4* s_src = s_p2p;
+  float4* s_de = s_p2p + cap;
+  float* s_d = reinterpret_cast<float*>(s_p2p + cap + n);
+  __shared__ int s_off[65];
+  __shared__ int s_slot[64];
+  __shared__ int s_cnt[64];
+  __shared__ int s_cs[9];
+
+  const int g = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int c0 = group_slots * g;  // first leaf slot of this parent
+
+  if (kNear && tid < 64) {
+    const int slot = blk[(size_t)g * 64 + tid];
+    const int cnt = slot >= 0 ? start[slot + 1] - start[slot] : 0;
+    int incl = (cnt + 3) & ~3;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o);
+      if (tid >= o) incl += v;
+    }
+    s_slot[tid] = slot;
+    s_cnt[tid] = cnt;
+    s_off[tid + 1] = incl;
+    if (tid == 0) s_off[0] = 0;
+  }
+  if (tid <= group_slots) s_cs[tid] = start[c0 + tid];
+  __syncthreads();
+  const int total = kNear ? s_off[64] : 0;
+  const bool in_lds = total <= cap;
+  if (kNear && in_lds) {
+    const float big = 3.402823466e38f;
+    for (int i = tid; i < total; i += (int)blockDim.x) {
+      int lo = 0, hi = 64;  // entry e with s_off[e] <= i < s_off[e + 1]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_off[mid] <= i) lo = mid;
+        else hi = mid;
+      }
+      const int r = i - s_off[lo];
+      s_src[i] = r < s_cnt[lo] ? pts[start[s_slot[lo]] + r] : make_float4(big, big, big, 0.f);
+    }
+  }
+  const float sc = alpha * centers[2 * c0].w;
+  if (kFar && far) {
+    for (int m = tid; m < n; m += (int)blockDim.x)
+      s_de[m] = make_float4(sc * surf[3 * m], sc * surf[3 * m + 1], sc * surf[3 * m + 2], 0.f);
+    for (int i = tid; i < group_slots * n; i += (int)blockDim.x) {
+      const int o = i / n, m = i - o * n;
+      s_d[o * n + m] = d[(size_t)(c0 + o) * ldd + m];
+    }
+  }
+  __syncthreads();
+
+  const int t0 = s_cs[0], t1 = s_cs[group_slots];
+  for (int tb = t0; tb < t1; tb += (int)blockDim.x) {
+    const int ti = tb + tid;
+    if (ti >= t1) break;
+    int o = 0;
+    while (o + 1 < group_slots && s_cs[o + 1] <= ti) ++o;
+    const float4 x = pts[ti];
+    const int bx = 1 + (o & 1), by = 1 + ((o >> 1) & 1), bz = 1 + ((o >> 2) & 1);
+    // Two-level summation: FP32 partial sums over at most kP2PChunk sources and per block
+    // of 8 surface points, accumulated in FP64 (the sums cancel heavily).
+    double aphi = 0.0, agx = 0.0, agy = 0.0, agz = 0.0;
+    if (kNear) {
+      // The three leaves dx = -1, 0, 1 of a (dy, dz) row are consecutive in the
+      // x-fastest block order, so their staged sources form one run: nine runs
+      // per target.  The run holding the target's own leaf tests r > 0.
+      Sum4 acc;
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy) {
+          const int e0 = (bx - 1) + 4 * (by + dy) + 16 * (bz + dz);
+          const bool own = (dy == 0) & (dz == 0);
+          if (in_lds) {
+            const int a = s_off[e0], b = s_off[e0 + 3];  // b - a is a multiple of 4
+            if (own)
+              p2p_run<true>(s_src, a, b, x, acc);
+            else
+              p2p_run<false>(s_src, a, b, x, acc);
+          } else {
+            for (int dx = 0; dx < 3; ++dx) {
+              const int slot = s_slot[e0 + dx];
+              if (slot < 0) continue;
+              const int a = start[slot], b = start[slot + 1];
+              for (int c = a; c < b; c += kP2PChunk) {
+                float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+                const int e = min(c + kP2PChunk, b);
+                if (own)
+                  for (int j = c; j < e; ++j) p2p_pair_masked(x.x, x.y, x.z, pts[j], phi, gx, gy, gz);
+                else
+                  for (int j = c; j < e; ++j) p2p_pair(x.x, x.y, x.z, pts[j], phi, gx, gy, gz);
+                acc.add(phi, gx, gy, gz);
+              }
+            }
+          }
+        }
+      aphi = acc.phi;
+      agx = acc.gx;
+      agy = acc.gy;
+      agz = acc.gz;
+    } else {
+      const float4 v = near[ti];
+      aphi = v.x;
+      agx = v.y;
+      agy = v.z;
+      agz = v.w;
+    }
+    if (kFar && far) {
+      const float4 ch = centers[2 * (c0 + o)], cl = centers[2 * (c0 + o) + 1];
+      const float xx = (x.x - ch.x) - cl.x, xy = (x.y - ch.y) - cl.y, xz = (x.z - ch.z) - cl.z;
+      const float* dl = s_d + o * n;
+      for (int m0 = 0; m0 < n; m0 += 8) {
+        float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        const int m1 = min(m0 + 8, n);
+        for (int m = m0; m < m1; ++m) {
+          const float4 de = s_de[m];
+          p2p_pair(xx, xy, xz, make_float4(de.x, de.y, de.z, dl[m]), phi, gx, gy, gz);
+        }
+        aphi += phi;
+        agx += gx;
+        agy += gy;
+        agz += gz;
+      }
+    }
+    if (MODE == 1) {
+      near[ti] = make_float4((float)aphi, (float)agx, (float)agy, (float)agz);
+    } else {
+      const int oi = order[ti];
+      if (pot) pot[oi] = (float)aphi;
+      if (grad) {
+        grad[3 * (size_t)oi] = (float)agx;
+        grad[3 * (size_t)oi + 1] = (float)agy;
+        grad[3 * (size_t)oi + 2] = (float)agz;
+      }
+    }
+  }
+}
+
+size_t p2p_lds_bytes(int cap, int n) { return (size_t)cap * 16 + (size_t)n * 16 + (size_t)8 * n * 4; }
+
+bool p2p_supported(int threads, int cap, int n) {
+  return (threads == 256 || threads == kP2PMaxThreads) && cap >= 0 && p2p_lds_bytes(cap, n) <= kMaxDynamicLds;
+}
+
+bool launch_p2p(int mode, const float4* pts, const int* start, const int* blk, int ngroups, int group_slots, int cap,
+                const float4* centers, const float* surf, int n, float alpha, const float* d, int ldd, int far,
+                const int* order, float* pot, float* grad, float4* near, int threads, hipStream_t s) {
+  if (ngroups <= 0) return true;
+  if (!p2p_supported(threads, cap, n) || mode < 0 || mode > 2) return false;
+  const int c = mode == 2 ? 0 : cap;
+  const size_t lds = mode == 1 ? (size_t)cap * 16 : p2p_lds_bytes(c, n);  // near-only: sources alone
+  const dim3 grid(ngroups), block(threads);
+#define KIFMM_P2P(M)                                                                                            \
+  hipLaunchKernelGGL(k_p2p<M>, grid, block, lds, s, pts, start, blk, group_slots, c, centers, surf, n, alpha, d, \
+                     ldd, far, order, pot, grad, near)
+  if (mode == 0) KIFMM_P2P(0);
+  else if (mode == 1) KIFMM_P2P(1);
+  else KIFMM_P2P(2);
+#undef KIFMM_P2P
+  return true;
+}
+
+// ---------------------------------------------------- leaf work queue ---
+// Fused D2T and ULI (Algorithm 1 steps 3b, 3c) as a persistent kernel over a
+// work queue of target tiles.  A tile is up to 64 consecutive targets of one
+// leaf, one per lane, so all lanes of a wave share the tile's U list and D2T
+// surface: every source is read at a wave-uniform address (scalar loads) and
+// used by the whole wave, and loop bounds are wave-uniform.  Tiles are ordered
+// longest first at plan creation; each wave takes its next tiles from a counter
+// in device memory (cleared by k_clear_queue before the launch) until none is
+// left, so the waves finish together on trees whose leaves hold very different
+// numbers of points (points on a surface).
+//
+// The sums are those of k_p2p: the sources of each leaf in sorted order (a step
+// past a leaf's end repeats its last source with charge zero, which adds exactly
+// zero), FP32 partials over at most kP2PChunk sources and over 8 surface points,
+// accumulated in FP64; the two kernels agree to FP32 rounding.  MODE as in k_p2p.
+constexpr int kQueueGrab = 4;  // tiles a wave takes from its counter at a time
+
+__global__ void k_clear_queue(int* queue, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) queue[i] = 0;
+}
+
+// Sources j .. j + 3 of a leaf range ending at b (clamped to b - 1).  The index
+// is the same on every lane, but `lane0` (zero, opaque to the compiler) makes
+// them vector loads: those complete in order, so a wait for one step's sources
+// leaves the next step's loads in flight (scalar loads complete out of order,
+// and a wait for any of them is a wait for all).
+__device__ __forceinline__ void queue_load4(const float4* __restrict__ pts, int j, int b, int lane0, float4* y) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) y[u] = pts[min(j + u, b - 1) + lane0];
+}
+
+// The pairs of a target with the sources [a, b) of one leaf (a < b), four per step,
+// the next step's sources loaded while this step's are used.  A source position at
+// or past b (its load repeats the last source) gets charge zero and adds exactly
+// nothing.
+template <bool MASKED>
+__device__ __forceinline__ void queue_leaf(const float4* __restrict__ pts, int a, int b, const float4& x, Sum4& acc) {
+  int lane0;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(lane0));
+  float4 y[4];
+  queue_load4(pts, a, b, lane0, y);
+  float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+  for (int j = a; j < b; j += 4) {
+    float4 yn[4];
+    queue_load4(pts, j + 4, b, lane0, yn);  // past the end: unused
+    __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of this step's arithmetic
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      float4 yu = y[u];
+      if (j + u >= b) yu.w = 0.f;
+      if (MASKED) p2p_pair_masked(x.x, x.y, x.z, yu, phi, gx, gy, gz);
+      else p2p_pair(x.x, x.y, x.z, yu, phi, gx, gy, gz);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) y[u] = yn[u];
+    if ((j - a + 4) % kP2PChunk == 0 || j + 4 >= b) {
+      acc.add(phi, gx, gy, gz);
+      phi = gx = gy = gz = 0.f;
+    }
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_leaf_queue(const float4* __restrict__ pts, const int* __restrict__ start,
+                                                    const int4* __restrict__ tiles, int ntiles, int* queue,
+                                                    const int* __restrict__ blk, int group_slots,
+                                                    const float4* __restrict__ centers,
+                                                    const float* __restrict__ surf, int n, float alpha,
+                                                    const float* __restrict__ d, int ldd, int far,
+                                                    const int* __restrict__ order, float* __restrict__ pot,
+                                                    float* __restrict__ grad, float4* __restrict__ near) {
+  constexpr bool kNear = MODE != 2;
+  constexpr bool kFar = MODE != 1;
+  // the downward-equivalent surface alpha r S_m of a leaf (every leaf has the same
+  // half-width), staged once per workgroup as k_p2p stages it
+  __shared__ float4 s_de[kMaxLeafSurface];
+  // each wave's copy of its tile's downward-equivalent density (read by every lane)
+  __shared__ float s_dens[4][kMaxLeafSurface];
+  const int lane = threadIdx.x & 63;
+  float* dens = s_dens[threadIdx.x >> 6];
+  if (kFar && far) {
+    const float sc = alpha * centers[0].w;
+    for (int m = threadIdx.x; m < n; m += blockDim.x)
+      s_de[m] = make_float4(sc * surf[3 * m], sc * surf[3 * m + 1], sc * surf[3 * m + 2], 0.f);
+    __syncthreads();
+  }
+  // The tiles t = xcd + 8 i (i < n_x) belong to the workgroups of one XCD (the
+  // hardware deals workgroups to the eight XCDs in turn), each XCD with a counter
+  // of its own, so that eight counters share the atomic traffic.  A wave takes
+  // tile i = its index among the XCD's waves first, then groups of kQueueGrab
+  // tiles from the counter; every wave leaves once its group starts past n_x.
+  const int xcd = blockIdx.x & 7;
+  const int n_x = ntiles > xcd ? (ntiles - xcd + 7) / 8 : 0;
+  const int waves_x = (int)(gridDim.x >> 3) * 4;  // the grid is a multiple of 8 workgroups
+  int i = (int)(blockIdx.x >> 3) * 4 + (int)(threadIdx.x >> 6);
+  int left = 1;
+  for (;;) {
+    if (left == 0) {
+      int mine = 0;
+      if (lane == 0) mine = atomicAdd(queue + 16 * xcd, 1);
+      i = waves_x + kQueueGrab * __builtin_amdgcn_readfirstlane(mine);
+      left = kQueueGrab;
+    }
+    if (i >= n_x) break;
+    const int t = xcd + 8 * i;
+    ++i;
+    --left;
+    const int4 tile = tiles[t];
+    const int slot = tile.x, cnt = tile.z;
+    const int ti = tile.y + min(lane, cnt - 1);
+    const float4 x = pts[ti];
+    const int g = slot / group_slots, o = slot - g * group_slots;
+    const int bx = 1 + (o & 1), by = 1 + ((o >> 1) & 1), bz = 1 + ((o >> 2) & 1);
+    double aphi = 0.0, agx = 0.0, agy = 0.0, agz = 0.0;
+    if (kNear) {
+      // the 27 leaves of the block around the tile's leaf; a leaf's sources four per
+      // step, the next step's loaded while this one is used
+      Sum4 acc;
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy) {
+          const bool own = (dy == 0) & (dz == 0);
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int ns = blk[(size_t)g * 64 + (bx + dx) + 4 * (by + dy) + 16 * (bz + dz)];
+            if (ns < 0) continue;
+            const int a = start[ns], b = start[ns + 1];
+            if (a >= b) continue;
+            if (own)
+              queue_leaf<true>(pts, a, b, x, acc);
+            else
+              queue_leaf<false>(pts, a, b, x, acc);
+          }
+        }
+      aphi = acc.phi;
+      agx = acc.gx;
+      agy = acc.gy;
+      agz = acc.gz;
+    } else {
+      const float4 v = near[ti];
+      aphi = v.x;
+      agx = v.y;
+      agy = v.z;
+      agz = v.w;
+    }
+    if (kFar && far) {
+      const float4 ch = centers[2 * slot], cl = centers[2 * slot + 1];
+      const float xx = (x.x - ch.x) - cl.x, xy = (x.y - ch.y) - cl.y, xz = (x.z - ch.z) - cl.z;
+      const float* dl = d + (size_t)slot * ldd;
+      // the density through LDS: one coalesced load per 64 values instead of a
+      // scalar load per value
+      for (int m = lane; m < n; m += 64) dens[m] = dl[m];
+      __builtin_amdgcn_wave_barrier();  // LDS accesses of one wave complete in order
+      for (int m0 = 0; m0 < n; m0 += 8) {
+        float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        const int m1 = min(m0 + 8, n);
+        for (int m = m0; m < m1; ++m) {
+          const float4 de = s_de[m];
+          p2p_pair(xx, xy, xz, make_float4(de.x, de.y, de.z, dens[m]), phi, gx, gy, gz);
+        }
+        aphi += phi;
+        agx += gx;
+        agy += gy;
+        agz += gz;
+      }
+    }
+    if (lane < cnt) {
+      if (MODE == 1) {
+        near[ti] = make_float4((float)aphi, (float)agx, (float)agy, (float)agz);
+      } else {
+        const int oi = order[ti];
+        if (pot) pot[oi] = (float)aphi;
+        if (grad) {
+          grad[3 * (size_t)oi] = (float)agx;
+          grad[3 * (size_t)oi + 1] = (float)agy;
+          grad[3 * (size_t)oi + 2] = (float)agz;
+        }
+      }
+    }
+  }
+}
+
+void launch_clear_queue(int* queue, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_queue, dim3(1), dim3(256), 0, s, queue, n);
+}
+
+bool launch_leaf_queue(int mode, const float4* pts, const int* start, const int4* tiles, int ntiles, int* queue,
+                       int grid, const int* blk, int group_slots, const float4* centers, const float* surf, int n,
+                       float alpha, const float* d, int ldd, int far, const int* order, float* pot, float* grad,
+                       float4* near, hipStream_t s) {
+  if (ntiles <= 0) return true;
+  if (grid < 8 || (grid & 7) || mode < 0 || mode > 2) return false;
+#define KIFMM_LEAF_QUEUE(M)                                                                                  \
+  hipLaunchKernelGGL(k_leaf_queue<M>, dim3(grid), dim3(256), 0, s, pts, start, tiles, ntiles, queue, blk,  \
+                     group_slots, centers, surf, n, alpha, d, ldd, far, order, pot, grad, near)
+  if (mode == 0) KIFMM_LEAF_QUEUE(0);
+  else if (mode == 1) KIFMM_LEAF_QUEUE(1);
+  else KIFMM_LEAF_QUEUE(2);
+#undef KIFMM_LEAF_QUEUE
+  return true;
+}
+
+// ---------------------------------------------------- multi-RHS leaves ---
+// R right-hand sides (R = 2, 4, ..., 32), potentials only.  Sorted charges are
+// [N][R] (a point's R charges contiguous) and every leaf kernel runs one wave
+// per leaf (or per 64 of its points) with the sources of a step common to the
+// whole wave, so that a source's position and charges are wave-uniform loads
+// and the geometry and reciprocal distance of a pair serve all R sums.
+
+// qs[i][r] = charges[order[i]][r].
+__global__ void k_permute_multi(float* __restrict__ qs, const float* __restrict__ charges,
+                                const int* __restrict__ order, int n, int R) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)n * R) return;
+  const long long p = i / R;
+  qs[i] = charges[(long long)order[p] * R + (i - p * R)];
+}
+
+void launch_permute_multi(float* qs, const float* charges, const int* order, int n, int R, hipStream_t s) {
+  const long long total = (long long)n * R;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_permute_multi, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, qs, charges, order, n,
+                     R);
+}
+
+// S2U first half for R right-hand sides: q[r][slot][m] for the check points m
+// (lanes) of one leaf per wave; sources in the leaf's order, centre-relative.
+template <int R>
+__global__ __launch_bounds__(256) void k_p2m_multi(const float4* __restrict__ pts, const float* __restrict__ qs,
+                                                   const int* __restrict__ start, const int* __restrict__ leaves,
+                                                   const float4* __restrict__ centers, const float* __restrict__ surf,
+                                                   int n, float alpha, float* __restrict__ q, int ldq, long long qrs,
+                                                   int nleaves) {
+  const int leaf = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (leaf >= nleaves) return;
+  const int lane = threadIdx.x & 63;
+  const int slot = leaves[leaf];
+  const float4 ch = centers[2 * slot], cl = centers[2 * slot + 1];
+  const float sc = alpha * ch.w;
+  const int s0 = start[slot], s1 = start[slot + 1];
+  for (int m0 = 0; m0 < n; m0 += 64) {
+    const int m = m0 + lane;
+    const int mc = min(m, n - 1);  // lanes past n repeat the last point and store nothing
+    const float px = sc * surf[3 * mc], py = sc * surf[3 * mc + 1], pz = sc * surf[3 * mc + 2];
+    float acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.f;
+#pragma unroll 1
+    for (int j = s0; j < s1; ++j) {
+      const float4 y = pts[j];
+      const float dx = px - ((y.x - ch.x) - cl.x);
+      const float dy = py - ((y.y - ch.y) - cl.y);
+      const float dz = pz - ((y.z - ch.z) - cl.z);
+      const float rinv = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+      const float* qj = qs + (size_t)j * R;
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += qj[r] * rinv;
+    }
+    if (m < n) {
+      float* out = q + (size_t)slot * ldq + m;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        *out = acc[r];
+        out += qrs;
+      }
+    }
+  }
+}
+
+bool launch_p2m_multi(int R, const float4* pts, const float* qs, const int* start, const int* leaves,
+                      const float4* centers, const float* surf, int n, float alpha, float* q, int ldq, long long qrs,
+                      int nleaves, hipStream_t s) {
+  if (nleaves <= 0) return true;
+  const dim3 grid((nleaves + 3) / 4), block(256);
+  switch (R) {
+    case 2: hipLaunchKernelGGL(k_p2m_multi<2>, grid, block, 0, s, pts, qs, start, leaves, centers, surf, n, alpha, q, ldq, qrs, nleaves); return true;
+    case 4: hipLaunchKernelGGL(k_p2m_multi<4>, grid, block, 0, s, pts, qs, start, leaves, centers, surf, n, alpha, q, ldq, qrs, nleaves); return true;
+    case 8: hipLaunchKernelGGL(k_p2m_multi<8>, grid, block, 0, s, pts, qs, start, leaves, centers, surf, n, alpha, q, ldq, qrs, nleaves); return true;
+    case 16: hipLaunchKernelGGL(k_p2m_multi<16>, grid, block, 0, s, pts, qs, start, leaves, centers, surf, n, alpha, q, ldq, qrs, nleaves); return true;
+    case 32: hipLaunchKernelGGL(k_p2m_multi<32>, grid, block, 0, s, pts, qs, start, leaves, centers, surf, n, alpha, q, ldq, qrs, nleaves); return true;
+    default: return false;
+  }
+}
+
+// D2T + ULI for R right-hand sides, potentials, written to input order
+// (pot[i][r]).  A task is up to 64 consecutive points of one leaf, one wave
+// each; lanes are targets.  The leaf's 27 neighbours come from the 4 x 4 x 4
+// leaf block of its parent group (as in k_p2p).  A neighbour's sources are
+// taken kMultiChunk at a time: the wave copies their positions and R charges
+// ([N][R], contiguous) into its own LDS with coalesced loads, then every lane
+// reads each source back at one address (a broadcast), so a pair's geometry and
+// reciprocal distance serve all R sums: 9 + 2R FLOP per pair.  The far field
+// treats the n downward-equivalent points (centre-relative) as sources with
+// densities d[r][slot][m], staged 8 points at a time the same way.  FP32
+// partial sums per source leaf and per 8 surface points are accumulated in
+// FP64.
+constexpr int kMultiChunk = 32;
+
+template <int R>
+__global__ __launch_bounds__(256) void k_leaf_multi(const float4* __restrict__ pts, const float* __restrict__ qs,
+                                                    const int* __restrict__ start, const int4* __restrict__ tasks,
+                                                    int ntasks, const int* __restrict__ blk, int group_slots,
+                                                    const float4* __restrict__ centers,
+                                                    const float* __restrict__ surf, int n, float alpha,
+                                                    const float* __restrict__ d, int ldd, long long drs, int far,
+                                                    const int* __restrict__ order, float* __restrict__ pot) {
+  // per wave: kMultiChunk source positions and their R charges
+  __shared__ float4 s_pos[4][kMultiChunk];
+  __shared__ float4 s_q[4][kMultiChunk * R / 4 + (R < 4 ? 1 : 0)];
+  const int wv = threadIdx.x >> 6;
+  const int t = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);
+  if (t >= ntasks) return;
+  const int lane = threadIdx.x & 63;
+  float4* pos = s_pos[wv];
+  float* q = reinterpret_cast<float*>(s_q[wv]);
+  const int4 task = tasks[t];
+  const int slot = task.x, cnt = task.z;
+  const int ti = start[slot] + task.y + min(lane, cnt - 1);
+  const float4 x = pts[ti];
+  const int g = slot / group_slots, o = slot - g * group_slots;
+  const int bx = 1 + (o & 1), by = 1 + ((o >> 1) & 1), bz = 1 + ((o >> 2) & 1);
+  double acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int ns = blk[(size_t)g * 64 + (bx + dx) + 4 * (by + dy) + 16 * (bz + dz)];
+        if (ns < 0) continue;
+        const int a = start[ns], b = start[ns + 1];
+        const bool self = ns == slot;
+        float part[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) part[r] = 0.f;
+        for (int c = a; c < b; c += kMultiChunk) {
+          const int m = min(kMultiChunk, b - c);
+          __builtin_amdgcn_wave_barrier();  // the previous chunk's reads come first
+          if (lane < m) pos[lane] = pts[c + lane];
+          for (int f = lane; f < m * R; f += 64) q[f] = qs[(size_t)c * R + f];
+          __builtin_amdgcn_wave_barrier();  // LDS accesses of one wave complete in order
+          for (int j = 0; j < m; ++j) {
+            const float4 y = pos[j];
+            const float ex = x.x - y.x, ey = x.y - y.y, ez = x.z - y.z;
+            const float r2 = ex * ex + ey * ey + ez * ez;
+            float rinv = __builtin_amdgcn_rsqf(r2);
+            if (self) rinv = r2 > 0.f ? rinv : 0.f;  // the target itself
+            const float* qj = q + j * R;
+            if constexpr (R % 4 == 0) {
+#pragma unroll
+              for (int r = 0; r < R; r += 4) {
+                const float4 q4 = *reinterpret_cast<const float4*>(qj + r);
+                part[r] += q4.x * rinv;
+                part[r + 1] += q4.y * rinv;
+                part[r + 2] += q4.z * rinv;
+                part[r + 3] += q4.w * rinv;
+              }
+            } else {
+#pragma unroll
+              for (int r = 0; r < R; ++r) part[r] += qj[r] * rinv;
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] += part[r];
+      }
+  if (far) {
+    const float4 ch = centers[2 * slot], cl = centers[2 * slot + 1];
+    const float xx = (x.x - ch.x) - cl.x, xy = (x.y - ch.y) - cl.y, xz = (x.z - ch.z) - cl.z;
+    const float sc = alpha * ch.w;
+    const float* dl = d + (size_t)slot * ldd;
+    for (int m0 = 0; m0 < n; m0 += 8) {
+      const int mc = min(8, n - m0);
+      __builtin_amdgcn_wave_barrier();
+      if (lane < mc) {
+        const int mm = m0 + lane;
+        pos[lane] = make_float4(sc * surf[3 * mm], sc * surf[3 * mm + 1], sc * surf[3 * mm + 2], 0.f);
+      }
+      // densities of the 8 points for every right-hand side, [point][r]
+      for (int f = lane; f < mc * R; f += 64) {
+        const int pt = f / R, r = f - pt * R;
+        q[f] = dl[r * drs + m0 + pt];
+      }
+      __builtin_amdgcn_wave_barrier();
+      float part[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) part[r] = 0.f;
+      for (int j = 0; j < mc; ++j) {
+        const float4 y = pos[j];
+        const float fx = xx - y.x, fy = xy - y.y, fz = xz - y.z;
+        const float rinv = __builtin_amdgcn_rsqf(fx * fx + fy * fy + fz * fz);
+        const float* qj = q + j * R;
+        if constexpr (R % 4 == 0) {
+#pragma unroll
+          for (int r = 0; r < R; r += 4) {
+            const float4 q4 = *reinterpret_cast<const float4*>(qj + r);
+            part[r] += q4.x * rinv;
+            part[r + 1] += q4.y * rinv;
+            part[r + 2] += q4.z * rinv;
+            part[r + 3] += q4.w * rinv;
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) part[r] += qj[r] * rinv;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += part[r];
+    }
+  }
+  if (lane < cnt) {
+    float* out = pot + (size_t)order[ti] * R;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[r] = (float)acc[r];
+  }
+}
+
+// D2T + ULI for 32 right-hand sides on the matrix cores.  For a tile of up to
+// 32 targets of one leaf, the potentials of 32 right-hand sides are the product
+// of the kernel matrix K[target][source] with the charges Q[source][rhs]: a
+// dense contraction over the sources, computed two sources per
+// v_mfma_f32_32x32x2_f32 step.  Lane (i, h) = (l % 32, l / 32) computes the
+// A operand K(x_i, y_{j+h}) of target i and source j + h on the vector ALUs
+// (the geometry and reciprocal distance, once per pair) and loads the B
+// operand Q[j + h][i] (right-hand side i, 32 consecutive charges per source);
+// the accumulator holds D[8 (v / 4) + 4 h + v % 4][i], 16 targets of right-hand
+// side i per lane.  FP32 accumulation per source leaf and per 16 surface points,
+// added into FP64 totals.  Sources past a leaf's end have charge zero;
+// coincident points (only in the target's own leaf) have K = 0.
+__global__ __launch_bounds__(256) void k_leaf_r32(const float4* __restrict__ pts, const float* __restrict__ qs,
+                                                  const int* __restrict__ start, const int4* __restrict__ tasks,
+                                                  int ntasks, const int* __restrict__ blk, int group_slots,
+                                                  const float4* __restrict__ centers, const float* __restrict__ surf,
+                                                  int n, float alpha, const float* __restrict__ d, int ldd,
+                                                  long long drs, int far, const int* __restrict__ order,
+                                                  float* __restrict__ pot) {
+  const int t = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (t >= ntasks) return;
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 31, h = lane >> 5;
+  const int4 task = tasks[t];
+  const int slot = task.x, cnt = task.z;
+  const int t0 = start[slot] + task.y;  // sorted index of the tile's first target
+  const float4 x = pts[t0 + min(i, cnt - 1)];
+  const int g = slot / group_slots, o = slot - g * group_slots;
+  const int bx = 1 + (o & 1), by = 1 + ((o >> 1) & 1), bz = 1 + ((o >> 2) & 1);
+  double tot[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) tot[v] = 0.0;
+  auto flush = [&](v16f& acc) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      tot[v] += acc[v];
+      acc[v] = 0.f;
+    }
+  };
+  v16f acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int ns = blk[(size_t)g * 64 + (bx + dx) + 4 * (by + dy) + 16 * (bz + dz)];
+        if (ns < 0) continue;
+        const int a = start[ns], b = start[ns + 1];
+        if (a >= b) continue;
+        const bool self = ns == slot;
+        // this lane's source of the step and its charge of right-hand side i, one step ahead
+        int js = a + h;
+        float4 y = pts[min(js, b - 1)];
+        float q = js < b ? qs[(size_t)js * 32 + i] : 0.f;
+        for (int j = a; j < b; j += 2) {
+          const int jn = j + 2 + h;
+          const float4 yn = pts[min(jn, b - 1)];
+          const float qn = jn < b ? qs[(size_t)min(jn, b - 1) * 32 + i] : 0.f;
+          const float ex = x.x - y.x, ey = x.y - y.y, ez = x.z - y.z;
+          const float r2 = ex * ex + ey * ey + ez * ez;
+          float k = __builtin_amdgcn_rsqf(r2);
+          if (self) k = r2 > 0.f ? k : 0.f;  // the target itself
+          acc = mfma32(k, q, acc);
+          y = yn;
+          q = qn;
+        }
+        flush(acc);
+      }
+  if (far) {
+    const float4 ch = centers[2 * slot], cl = centers[2 * slot + 1];
+    const float xx = (x.x - ch.x) - cl.x, xy = (x.y - ch.y) - cl.y, xz = (x.z - ch.z) - cl.z;
+    const float sc = alpha * ch.w;
+    const float* dl = d + (size_t)i * drs + (size_t)slot * ldd;  // density of right-hand side i
+    for (int m0 = 0; m0 < n; m0 += 16) {
+      for (int m = m0; m < min(m0 + 16, n); m += 2) {
+        const int mm = min(m + h, n - 1);
+        const float fx = xx - sc * surf[3 * mm], fy = xy - sc * surf[3 * mm + 1], fz = xz - sc * surf[3 * mm + 2];
+        const float k = __builtin_amdgcn_rsqf(fx * fx + fy * fy + fz * fz);
+        const float dm = m + h < n ? dl[mm] : 0.f;
+        acc = mfma32(k, dm, acc);
+      }
+      flush(acc);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int row = 8 * (v >> 2) + 4 * h + (v & 3);  // target of the tile
+    if (row < cnt) pot[(size_t)order[t0 + row] * 32 + i] = (float)tot[v];
+  }
+}
+
+bool launch_leaf_multi(int R, const float4* pts, const float* qs, const int* start, const int4* tasks, int ntasks,
+                       const int* blk, int group_slots, const float4* centers, const float* surf, int n, float alpha,
+                       const float* d, int ldd, long long drs, int far, const int* order, float* pot, hipStream_t s) {
+  if (ntasks <= 0) return true;
+  const dim3 grid((ntasks + 3) / 4), block(256);
+#define KIFMM_LEAF_MULTI(RR)                                                                                        \
+  hipLaunchKernelGGL(k_leaf_multi<RR>, grid, block, 0, s, pts, qs, start, tasks, ntasks, blk, group_slots, centers, \
+                     surf, n, alpha, d, ldd, drs, far, order, pot)
+  switch (R) {
+    case 2: KIFMM_LEAF_MULTI(2); return true;
+    case 4: KIFMM_LEAF_MULTI(4); return true;
+    case 8: KIFMM_LEAF_MULTI(8); return true;
+    case 16: KIFMM_LEAF_MULTI(16); return true;
+    case 32:
+      hipLaunchKernelGGL(k_leaf_r32, grid, block, 0, s, pts, qs, start, tasks, ntasks, blk, group_slots, centers, surf,
+                         n, alpha, d, ldd, drs, far, order, pot);
+      return true;
+    default: return false;
+  }
+#undef KIFMM_LEAF_MULTI
+}
+
+// Dynamic LDS limit of every kernel that stages data in LDS, for the current
+// device.  Plans call this once per device (under a lock) before their first
+// launch; the launchers then only check their sizes against kMaxDynamicLds.
+hipError_t configure_kernels() {
+  const hipError_t e = configure_m2l_kernels();
+  if (e != hipSuccess) return e;
+  const void* kernels[] = {reinterpret_cast<const void*>(&k_p2p<0>), reinterpret_cast<const void*>(&k_p2p<1>),
+                           reinterpret_cast<const void*>(&k_p2p<2>)};
+  for (const void* k : kernels) {
+    const hipError_t e2 = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynamicLds);
+    if (e2 != hipSuccess) return e2;
+  }
+  return hipSuccess;
+}
+
+}  // namespace kifmm

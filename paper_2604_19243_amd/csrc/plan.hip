@@ -343,16 +343,17 @@ void prepare(Plan* P, Staging& S) {
   S.data((void**)&P->d_blk, std::move(blk));
 
   // Target tiles of the leaf sums: up to 64 consecutive points of one non-empty
-  // leaf, as (slot, first sorted point, count, 0).  The work queue takes them
-  // longest first (U-list sources plus surface points per target); the
-  // multi-RHS kernels take them in leaf order.
+  // leaf (32 for the 32-right-hand-side kernel), as (slot, first sorted point,
+  // count, 0).  The work queue takes them longest first (U-list sources plus
+  // surface points per target); the multi-RHS kernels take them in leaf order.
   std::vector<int> tk;
   std::vector<int64_t> cost;
+  const int tile = nrhs > 1 ? kMultiTile(nrhs) : 64;
   for (int64_t i = 0; i < NBL; ++i) {
     const int s = leaves[i];
     const int c = start[s + 1] - start[s];
-    for (int t0 = 0; t0 < c; t0 += 64) {
-      tk.insert(tk.end(), {s, start[s] + t0, std::min(64, c - t0), 0});
+    for (int t0 = 0; t0 < c; t0 += tile) {
+      tk.insert(tk.end(), {s, start[s] + t0, std::min(tile, c - t0), 0});
       cost.push_back(leaf_sources[s] + (P->far ? O.n : 0));
     }
   }

@@ -39,7 +39,7 @@ def test_traffic_entries_are_consistent_and_matched_by_source_and_config(monkeyp
                                    + e["write_kib_per_dispatch"] * e["write_scale"])
                 assert abs(e["hbm_bytes_per_launch"] - expect) <= 1e-9 * expect
                 assert os.path.exists(os.path.join(ROOT, e["source"]))
-                monkeypatch.setattr(bench, "kernel_source_hash", lambda h=e["kernels_hip_sha256_16"]: h)
+                monkeypatch.setattr(bench, "kernel_source_hash", lambda h=e["m2l_hip_sha256_16"]: h)
                 assert bench.load_traffic(workload, kernel, e["config"]) == e["hbm_bytes_per_launch"]
                 other = dict(e["config"], m2l_rank=e["config"]["m2l_rank"] + 1)
                 assert bench.load_traffic(workload, kernel, other) is None
