@@ -132,6 +132,38 @@ __device__ __forceinline__ void m2l_slab(v16f* acc, v16f* tot, const float* alan
   }
 }
 
+// Staging of one k-slab of an item's 216 source rows into LDS.  The rows' box
+// slots (-1 for none) are read once per item into s_src.  Each thread takes a
+// fixed column unit of the slab and every rpp-th row, and issues the global
+// loads of kStageBatch rows before it waits for any of them (a missing box
+// reads row 0 and stores zeros), so that a slab costs a few memory latencies
+// rather than one dependent pair of loads per row.
+constexpr int kStageBatch = 8;
+
+__device__ __forceinline__ void m2l_load_src(int* s_src, const int* __restrict__ srcs) {
+  for (int r = threadIdx.x; r < 216; r += blockDim.x) s_src[r] = srcs[r];
+  __syncthreads();
+}
+
+// units: column units per row in this slab; load(slot, u) returns unit u of the
+// row of box slot; store(r, u, v) writes it to LDS.
+template <int B, typename Load, typename Store>
+__device__ __forceinline__ void m2l_stage(const int* s_src, int units, Load load, Store store) {
+  const int rpp = blockDim.x / units;  // rows per pass
+  const int r0 = threadIdx.x / units, u = threadIdx.x - r0 * units;
+  if (r0 >= rpp) return;
+  for (int rb = r0; rb < 216; rb += B * rpp) {
+    decltype(load(0, 0)) v[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) v[j] = load(max(s_src[min(rb + j * rpp, 215)], 0), u);
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int r = rb + j * rpp;
+      if (r < 216) store(r, u, v[j], s_src[r] >= 0);
+    }
+  }
+}
+
 // UPPER = 1 for the launch of the levels above the leaves that runs on a
 // second stream beside the leaf level's (same code; a name of its own in traces).
 template <int UPPER>
@@ -166,20 +198,17 @@ __global__ __launch_bounds__(512) void k_m2l(const float* __restrict__ cores, in
   // this lane's float4 in the wave's row block of the lane-ordered operators
   const float* ablk = cores + (size_t)wave * 32 * ldk + 4 * lane;
   const size_t core_stride = (size_t)core_rows * ldk;
-  const int* srcs = src_blk + it.src_base;
+  __shared__ int s_src[216];
+  m2l_load_src(s_src, src_blk + it.src_base);
 
   const int slab = 4 * (ld4 - 1);
   for (int k0 = 0; k0 < ldk; k0 += slab) {
     const int kw = min(slab, ldk - k0);  // slab width, a multiple of 8
-    const int w4 = kw >> 2;
     if (k0) __syncthreads();  // previous slab fully consumed
-    for (int idx = tid; idx < 216 * w4; idx += blockDim.x) {
-      const int r = idx / w4, c4 = idx - r * w4;
-      const int slot = srcs[r];
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (slot >= 0) v = *reinterpret_cast<const float4*>(uhat + (size_t)slot * ldk + k0 + 4 * c4);
-      s_m2l[r * ld4 + c4] = v;
-    }
+    m2l_stage<kStageBatch>(
+        s_src, kw >> 2,
+        [&](int slot, int c4) { return *reinterpret_cast<const float4*>(uhat + (size_t)slot * ldk + k0 + 4 * c4); },
+        [&](int r, int c4, float4 v, bool live) { s_m2l[r * ld4 + c4] = live ? v : make_float4(0.f, 0.f, 0.f, 0.f); });
     __syncthreads();
     m2l_slab(acc, tot, ablk + 32 * k0, core_stride, po_reg, it.noffs, bq, kw >> 3, ld4);
   }
@@ -451,6 +480,11 @@ __device__ __forceinline__ void m2lb_slab(v16f* acc, v16f* tot, const uint4* ala
   }
 }
 
+struct Float4x2 {
+  float4 a, b;
+};
+__device__ __forceinline__ Float4x2 make_float4x2(const float4& a, const float4& b) { return Float4x2{a, b}; }
+
 __device__ __forceinline__ uint32_t bf16_bits(__bf16 x) { return __builtin_bit_cast(uint16_t, x); }
 
 // Eight FP32 values split into NP bfloat16 pieces each (piece p of value e in
@@ -505,26 +539,26 @@ __global__ __launch_bounds__(512) void k_m2l_bf16(const uint4* __restrict__ core
   const int po_reg = pair_offs[it.pair * 27 + min(lane, 26)];
   // this lane's piece-0 unit in the wave's row block of the lane-ordered operators
   const uint4* ablk = cores + (size_t)wave * nchunk * 64 * NP + lane;
-  const int* srcs = src_blk + it.src_base;
+  __shared__ int s_src[216];
+  m2l_load_src(s_src, src_blk + it.src_base);
 
   for (int k0 = 0; k0 < ldk; k0 += kM2LSlabB) {
     const int kw = min(kM2LSlabB, ldk - k0);  // a multiple of 16
-    const int ng = kw >> 3;                    // groups of 8 k
     if (k0) __syncthreads();
-    for (int idx = tid; idx < 216 * ng; idx += blockDim.x) {
-      const int r = idx / ng, g = idx - r * ng;
-      const int slot = srcs[r];
-      float4 u = make_float4(0.f, 0.f, 0.f, 0.f), v = u;
-      if (slot >= 0) {
-        const float4* src = reinterpret_cast<const float4*>(uhat + (size_t)slot * ldk + k0 + 8 * g);
-        u = src[0];
-        v = src[1];
-      }
-      uint4 pcs[NP];
-      split8<NP>(u, v, pcs);
+    // column units of 8 k (two float4), split into NP pieces as they are stored
+    m2l_stage<kStageBatch / 2>(
+        s_src, kw >> 3,
+        [&](int slot, int g) {
+          const float4* src = reinterpret_cast<const float4*>(uhat + (size_t)slot * ldk + k0 + 8 * g);
+          return make_float4x2(src[0], src[1]);
+        },
+        [&](int r, int g, Float4x2 v, bool live) {
+          const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+          uint4 pcs[NP];
+          split8<NP>(live ? v.a : z, live ? v.b : z, pcs);
 #pragma unroll
-      for (int p = 0; p < NP; ++p) s_m2lb[r * ld16 + NP * g + p] = pcs[p];
-    }
+          for (int p = 0; p < NP; ++p) s_m2lb[r * ld16 + NP * g + p] = pcs[p];
+        });
     __syncthreads();
     m2lb_slab<NP>(acc, tot, ablk + (size_t)(k0 >> 4) * 64 * NP, core_stride, po_reg, it.noffs, bq, kw >> 4, ld16);
   }
