@@ -287,7 +287,7 @@ def bf16_products(stats, passes):
 
 def leaf_kernel_name(stats, serial, R):
     if R > 1:
-        return f"k_leaf_multi<{R}>"
+        return "k_leaf_r32" if R == 32 else f"k_leaf_multi<{R}>"
     if stats["leaf_queue"]:
         return "k_leaf_queue<0>" if serial else "k_leaf_queue<1>"
     return "k_p2p<0>" if serial else "k_p2p<1>"
@@ -387,7 +387,7 @@ def next_rows(args, torch, dev):
            "point_rhs_per_s": w.n * 32 / (ms32 * 1e-3), "stages_ms": stg,
            "m2l_roofline": {"kernel": "k_m2l_wide", "achieved": m2l_flop / (stg["m2l"] * 1e-3) / 1e12,
                             "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"},
-           "leaf": {"kernel": "k_leaf_multi<32>", "achieved": leaf_flop / (stg["p2p"] * 1e-3) / 1e12,
+           "leaf": {"kernel": "k_leaf_r32", "achieved": leaf_flop / (stg["p2p"] * 1e-3) / 1e12,
                     "flop_per_pair": 9 + 2 * 32, "unit": "TFLOP/s"},
            "one_rhs": {"ms_per_evaluate": ms1, "stages_ms": stg1,
                        "leaf_kernel": "k_leaf_queue" if st1["leaf_queue"] else "k_p2p",
@@ -456,6 +456,8 @@ def main():
     ap.add_argument("--repeats", type=int, default=5, help="blocks of --steps evaluates for the mean and spread")
     ap.add_argument("--workload", default="cube1m_p6_d5")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (parity still checked)")
+    ap.add_argument("--no-parity", action="store_true",
+                    help="profiling runs: no oracle or direct-sum legs; value is null (accuracy not shown)")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the precision, batching and differentiation workloads")
     ap.add_argument("--next-steps", type=int, default=10)
@@ -626,7 +628,7 @@ def main():
                           kifmm.KIFMM_LEAF_THREADS_256 | kifmm.KIFMM_LEAF_THREADS_320))
         plan_s = kifmm.kifmm_plan_create(f.tree, f.ops, 1, fl_s | (m2l_flag & ~layout) | kifmm.KIFMM_SERIAL | pin)
         st_s = kifmm.kifmm_plan_get_stats(plan_s)
-        steps_ = step_of(plan_s)
+        steps_ = lambda: kifmm.kifmm_evaluate(plan_s, charges, pot, grad, stream.cuda_stream)  # noqa: E731
         for _ in range(2):
             steps_()
         stg_s = tm.stages(plan_s, steps_, 10)
@@ -718,6 +720,11 @@ def main():
     # the GPU's parity with it on the sampled leaves, and the direct sum at sampled targets;
     # then the same timing with every core the process may use.
     gate = {"oracle_tol": ORACLE_TOL[args.m2l], "direct_tol": DIRECT_TOL}
+    if args.no_parity:
+        gate.update(passed=False, reason="not checked (--no-parity)")
+        result.update(value=None, accuracy_gate=gate)
+        print(json.dumps(result), flush=True)
+        return
     with tempfile.TemporaryDirectory() as tmp:
         path = os.path.join(tmp, "gpu.npz")
         sample = {"phi": phi_all.astype(np.float64), "direct_idx": direct_idx}
