@@ -325,18 +325,22 @@ void launch_m2l_gather(const float* cores, long long core_stride, int ldk, const
 // The compressed VLI for 32 right-hand sides as wide products: per target box
 // and V-list entry (offset t, source box), chat[:, target] += C_t uhat[:, source]
 // with the 32 right-hand sides as the 32 columns of v_mfma_f32_32x32x2_f32.
-// One wave per (target box, 32-row block of C) walks the target's V list.
+// One wave per (target box, 32-row block of C) walks the target's V list; the
+// row blocks of one target are the waves of one workgroup, so that each
+// source's uhat chunk, read by all of them in the same order, comes from HBM
+// once (the kernel is bound by the traffic of uhat and the operators).
 // Operators are in the lane order of k_m2l; uhat is [box][k / 8][32][8], so
 // that lane (j, h) reads B[8c + 4h .. +3][right-hand side j] as one float4 and
 // a wave's read of one chunk is 1 KiB of contiguous memory.  No partial sums:
 // the wave writes chat[r][target][rows] once.  The accumulators restart every
 // kM2LFlush entries and are added into a running total (short FP32 chains).
-__global__ __launch_bounds__(64) void k_m2l_wide(const float* __restrict__ cores, long long core_stride, int nch,
-                                                 const int4* __restrict__ units, const int2* __restrict__ vlist,
-                                                 const float* __restrict__ uhat, float* __restrict__ chat,
-                                                 long long chat_rs, int ldk) {
-  const int4 u = units[blockIdx.x];  // (target slot, row block, first entry, end entry)
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(512) void k_m2l_wide(const float* __restrict__ cores, long long core_stride, int nch,
+                                                  const int4* __restrict__ units, const int2* __restrict__ vlist,
+                                                  const float* __restrict__ uhat, float* __restrict__ chat,
+                                                  long long chat_rs, int ldk) {
+  // (target slot, row block, first entry, end entry) of wave threadIdx.x / 64
+  const int4 u = units[blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)];
+  const int lane = threadIdx.x & 63;
   const int j = lane & 31, h = lane >> 5;
   const float* alane = cores + (size_t)u.y * nch * 256 + 4 * lane;
   const float* blane = uhat + 8 * j + 4 * h;
@@ -381,11 +385,13 @@ __global__ __launch_bounds__(64) void k_m2l_wide(const float* __restrict__ cores
   }
 }
 
-void launch_m2l_wide(const float* cores, long long core_stride, int ldk, const int4* units, int nunits,
-                     const int2* vlist, const float* uhat, float* chat, long long chat_rs, hipStream_t s) {
-  if (nunits <= 0) return;
-  hipLaunchKernelGGL(k_m2l_wide, dim3(nunits), dim3(64), 0, s, cores, core_stride, ldk / 8, units, vlist, uhat, chat,
-                     chat_rs, ldk);
+bool launch_m2l_wide(int row_blocks, const float* cores, long long core_stride, int ldk, const int4* units,
+                     int nunits, const int2* vlist, const float* uhat, float* chat, long long chat_rs, hipStream_t s) {
+  if (nunits <= 0) return true;
+  if (row_blocks < 1 || row_blocks > 8 || nunits % row_blocks) return false;
+  hipLaunchKernelGGL(k_m2l_wide, dim3(nunits / row_blocks), dim3(64 * row_blocks), 0, s, cores, core_stride, ldk / 8,
+                     units, vlist, uhat, chat, chat_rs, ldk);
+  return true;
 }
 
 // ------------------------------------------------- M2L, split bfloat16 ---

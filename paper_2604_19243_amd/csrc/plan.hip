@@ -705,25 +705,30 @@ void prepare(Plan* P, Staging& S) {
         }
       }
       require(vl.size() / 2 < (size_t)INT32_MAX, "V lists too long for the M2L tables");
-      // Units are dealt to XCDs by the target's position among its siblings, row
-      // block by row block: an XCD then works through the ~189 cores of one
-      // position and one row block at a time (its L2 holds them).
-      auto deal = [&](std::vector<std::vector<int>>& ux) {
+      // Units (4 ints each) are dealt to XCDs by the target's position among its
+      // siblings, in groups of g consecutive units (one workgroup): an XCD then
+      // works through the ~189 cores of one position.  The gathered form deals
+      // row block by row block (the L2 holds one row block of those cores); the
+      // wide form deals all row blocks of a target as one workgroup (its uhat
+      // rows are read once for all of them).
+      auto deal = [&](std::vector<std::vector<int>>& ux, int g) {
         std::vector<int> units;
         size_t most = 0;
-        for (auto& v : ux) most = std::max(most, v.size() / 4);
+        for (auto& v : ux) most = std::max(most, v.size() / (4 * g));
         for (size_t i = 0; i < most; ++i)
           for (int x = 0; x < 8; ++x)
-            if (i < ux[x].size() / 4) units.insert(units.end(), ux[x].begin() + 4 * i, ux[x].begin() + 4 * i + 4);
+            if (i < ux[x].size() / (4 * g))
+              units.insert(units.end(), ux[x].begin() + 4 * g * i, ux[x].begin() + 4 * g * (i + 1));
         return units;
       };
       if (P->m2l_wide) {
         std::vector<std::vector<int>> ux(8);
         for (int x = 0; x < 8; ++x)
-          for (int rb = 0; rb < P->m2l_rb; ++rb)
-            for (size_t i = 0; i < tgt_slot.size(); ++i)
-              if (tgt_pos[i] == x) ux[x].insert(ux[x].end(), {tgt_slot[i], rb, (int)tgt_first[i], (int)tgt_end[i]});
-        std::vector<int> units = deal(ux);
+          for (size_t i = 0; i < tgt_slot.size(); ++i)
+            if (tgt_pos[i] == x)
+              for (int rb = 0; rb < P->m2l_rb; ++rb)
+                ux[x].insert(ux[x].end(), {tgt_slot[i], rb, (int)tgt_first[i], (int)tgt_end[i]});
+        std::vector<int> units = deal(ux, P->m2l_rb);
         P->n_units = (int)(units.size() / 4);
         S.data((void**)&P->d_vlist, std::move(vl));
         S.data((void**)&P->d_units, std::move(units));
@@ -767,9 +772,9 @@ void prepare(Plan* P, Staging& S) {
               for (int rb = 0; rb < P->m2l_rb; ++rb) ux[x].insert(ux[x].end(), {g, rb, first, end});
             }
           }
-        std::vector<int> units = deal(ux_leaf);
+        std::vector<int> units = deal(ux_leaf, 1);
         P->n_gunits_leaf = (int)(units.size() / 4);
-        const std::vector<int> upper = deal(ux_upper);
+        const std::vector<int> upper = deal(ux_upper, 1);
         units.insert(units.end(), upper.begin(), upper.end());
         P->n_gunits = (int)(units.size() / 4);
         S.data((void**)&P->d_gent_core, std::move(ent_core));
@@ -812,6 +817,8 @@ void check_launches(const Plan* P) {
                                         m2l_bf16_supported(3, P->m2l_rb, P->kst)
                                   : m2l_supported(P->m2l_rb, P->kst, P->m2l_lds_ld);
     if (!ok) fail(KIFMM_E_INVALID, "M2L kernel configuration not available for this rank");
+    if (P->m2l_wide && (P->m2l_rb > 8 || P->n_units % P->m2l_rb))
+      fail(KIFMM_E_INVALID, "internal: wide M2L units not in whole workgroups");
   }
 }
 
@@ -977,9 +984,8 @@ bool launch_m2l_form(Plan* P, hipStream_t st, int part) {
   const long long TS = P->total_slots;
   if (P->m2l_wide) {
     if (part == 2) return true;
-    launch_m2l_wide(P->d_cores, (long long)P->core_rows * kst, kst, P->d_units, P->n_units, P->d_vlist, P->d_uhat,
-                    P->d_chat, TS * kst, st);
-    return true;
+    return launch_m2l_wide(P->m2l_rb, P->d_cores, (long long)P->core_rows * kst, kst, P->d_units, P->n_units,
+                           P->d_vlist, P->d_uhat, P->d_chat, TS * kst, st);
   }
   if (P->m2l_gather) {
     const int u0 = part == 2 ? P->n_gunits_leaf : 0;
