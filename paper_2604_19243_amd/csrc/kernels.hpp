@@ -50,12 +50,12 @@ bool launch_m2l_bf16(int pieces, int row_blocks, const uint16_t* cores, size_t c
                      const M2LItem* items, int nitems, const int* tgt_blk, const int* src_blk, const int* pair_offs,
                      const float* uhat, float* chat_part, long long part_stride, int nrhs, long long rhs_stride,
                      hipStream_t s, bool upper = false);
-// M2L for 32 right-hand sides: units (target slot, row block, first, end V-list entry),
-// the row_blocks units of one target consecutive (one workgroup; false unless nunits is a
-// multiple of row_blocks <= 8); vlist entries (core index, source slot); uhat in the lane
-// order written by launch_gemm_nt(ywide); chat [32][slots][ldk] (chat_rs = slots * ldk).
+// M2L for 32 right-hand sides: one workgroup of row_blocks waves (<= 8, false otherwise)
+// per unit (slot of target 0, slot of target 1 or -1, first, end merged entry); merged
+// entries (core index, source slot of target 0 or -1, of target 1 or -1, 0); uhat in the
+// lane order written by launch_gemm_nt(ywide); chat [32][slots][ldk] (chat_rs = slots * ldk).
 bool launch_m2l_wide(int row_blocks, const float* cores, long long core_stride, int ldk, const int4* units,
-                     int nunits, const int2* vlist, const float* uhat, float* chat, long long chat_rs, hipStream_t s);
+                     int nunits, const int4* ents, const float* uhat, float* chat, long long chat_rs, hipStream_t s);
 // M2L with gathered sources, one right-hand side: units (group, row block, first, end entry);
 // per entry the core index and 32 source rows of uhat (zero row where none); grp_tgt: 32
 // target slots per group (-1 = none); chat [slots][ldk].

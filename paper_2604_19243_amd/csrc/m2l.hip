@@ -325,72 +325,120 @@ void launch_m2l_gather(const float* cores, long long core_stride, int ldk, const
 // The compressed VLI for 32 right-hand sides as wide products: per target box
 // and V-list entry (offset t, source box), chat[:, target] += C_t uhat[:, source]
 // with the 32 right-hand sides as the 32 columns of v_mfma_f32_32x32x2_f32.
-// One wave per (target box, 32-row block of C) walks the target's V list; the
-// row blocks of one target are the waves of one workgroup, so that each
-// source's uhat chunk, read by all of them in the same order, comes from HBM
-// once (the kernel is bound by the traffic of uhat and the operators).
+// The kernel is bound by its fetches of the operator slices and of uhat, not
+// by the matrix cores, so it is arranged to fetch each of them fewer times:
+// * two targets of one level and one position among siblings (neighbours in
+//   Morton order, so their V lists hold mostly the same offsets) share a
+//   workgroup, whose merged list holds each offset once with the source of each
+//   target (or none): one fetch of C_t's chunk serves both targets' products;
+// * the workgroup's waves are the 32-row blocks of C, walking the same list in
+//   the same order, so that each uhat chunk is fetched once for all of them.
 // Operators are in the lane order of k_m2l; uhat is [box][k / 8][32][8], so
 // that lane (j, h) reads B[8c + 4h .. +3][right-hand side j] as one float4 and
 // a wave's read of one chunk is 1 KiB of contiguous memory.  No partial sums:
-// the wave writes chat[r][target][rows] once.  The accumulators restart every
-// kM2LFlush entries and are added into a running total (short FP32 chains).
-__global__ __launch_bounds__(512) void k_m2l_wide(const float* __restrict__ cores, long long core_stride, int nch,
-                                                  const int4* __restrict__ units, const int2* __restrict__ vlist,
-                                                  const float* __restrict__ uhat, float* __restrict__ chat,
-                                                  long long chat_rs, int ldk) {
-  // (target slot, row block, first entry, end entry) of wave threadIdx.x / 64
-  const int4 u = units[blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)];
-  const int lane = threadIdx.x & 63;
-  const int j = lane & 31, h = lane >> 5;
-  const float* alane = cores + (size_t)u.y * nch * 256 + 4 * lane;
-  const float* blane = uhat + 8 * j + 4 * h;
-  const size_t box_stride = (size_t)nch * 256;
-  v16f acc, tot;
-#pragma unroll
-  for (int e = 0; e < 16; ++e) acc[e] = tot[e] = 0.f;
-  for (int e0 = u.z; e0 < u.w; e0 += kM2LFlush) {
-    const int e1 = min(e0 + kM2LFlush, u.w);
-    for (int e = e0; e < e1; ++e) {
-      const int2 pr = vlist[e];
-      const float* ap = alane + (size_t)pr.x * core_stride;
-      const float* bp = blane + (size_t)pr.y * box_stride;
-      float4 a = *reinterpret_cast<const float4*>(ap);
-      float4 b = *reinterpret_cast<const float4*>(bp);
-      for (int c = 0; c < nch; ++c) {
-        const int cn = min(c + 1, nch - 1);  // next chunk (the last one repeats, unused)
-        const float4 an = *reinterpret_cast<const float4*>(ap + 256 * cn);
-        const float4 bn = *reinterpret_cast<const float4*>(bp + 256 * cn);
-        acc = mfma32(a.x, b.x, acc);
-        acc = mfma32(a.y, b.y, acc);
-        acc = mfma32(a.z, b.z, acc);
-        acc = mfma32(a.w, b.w, acc);
-        a = an;
-        b = bn;
-      }
-    }
-    // a group of kM2LFlush entries: into the running total, restart
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      tot[e] += acc[e];
-      acc[e] = 0.f;
-    }
+// each wave writes chat[r][target][rows] once per target.  The accumulators
+// restart every kM2LFlush entries and are added into running totals (short
+// FP32 chains).
+
+// One entry's products for one target: C_t's chunks from ap, the source's from bp.
+__device__ __forceinline__ void wide_entry(const float* ap, const float* bp, int nch, v16f& acc) {
+  float4 a = *reinterpret_cast<const float4*>(ap);
+  float4 b = *reinterpret_cast<const float4*>(bp);
+  for (int c = 0; c < nch; ++c) {
+    const int cn = min(c + 1, nch - 1);  // next chunk (the last one repeats, unused)
+    const float4 an = *reinterpret_cast<const float4*>(ap + 256 * cn);
+    const float4 bn = *reinterpret_cast<const float4*>(bp + 256 * cn);
+    acc = mfma32(a.x, b.x, acc);
+    acc = mfma32(a.y, b.y, acc);
+    acc = mfma32(a.z, b.z, acc);
+    acc = mfma32(a.w, b.w, acc);
+    a = an;
+    b = bn;
   }
-  // tot[v]: row 32 u.y + 8 (v / 4) + 4 h + v % 4 of right-hand side j
-  float* out = chat + j * chat_rs + (size_t)u.x * ldk;
+}
+
+// Both targets' products of one entry: each C_t chunk loaded once.
+__device__ __forceinline__ void wide_entry2(const float* ap, const float* bpa, const float* bpb, int nch, v16f& acc0,
+                                            v16f& acc1) {
+  float4 a = *reinterpret_cast<const float4*>(ap);
+  float4 b0 = *reinterpret_cast<const float4*>(bpa);
+  float4 b1 = *reinterpret_cast<const float4*>(bpb);
+  for (int c = 0; c < nch; ++c) {
+    const int cn = min(c + 1, nch - 1);
+    const float4 an = *reinterpret_cast<const float4*>(ap + 256 * cn);
+    const float4 bn0 = *reinterpret_cast<const float4*>(bpa + 256 * cn);
+    const float4 bn1 = *reinterpret_cast<const float4*>(bpb + 256 * cn);
+    acc0 = mfma32(a.x, b0.x, acc0);
+    acc1 = mfma32(a.x, b1.x, acc1);
+    acc0 = mfma32(a.y, b0.y, acc0);
+    acc1 = mfma32(a.y, b1.y, acc1);
+    acc0 = mfma32(a.z, b0.z, acc0);
+    acc1 = mfma32(a.z, b1.z, acc1);
+    acc0 = mfma32(a.w, b0.w, acc0);
+    acc1 = mfma32(a.w, b1.w, acc1);
+    a = an;
+    b0 = bn0;
+    b1 = bn1;
+  }
+}
+
+__device__ __forceinline__ void wide_store(const v16f& tot, float* chat, long long chat_rs, int slot, int rb, int ldk,
+                                           int j, int h) {
+  // tot[v]: row 32 rb + 8 (v / 4) + 4 h + v % 4 of right-hand side j
+  float* out = chat + j * chat_rs + (size_t)slot * ldk;
 #pragma unroll
   for (int b4 = 0; b4 < 4; ++b4) {
-    const int row = 32 * u.y + 8 * b4 + 4 * h;
+    const int row = 32 * rb + 8 * b4 + 4 * h;
     if (row < ldk)
       *reinterpret_cast<float4*>(out + row) = make_float4(tot[4 * b4], tot[4 * b4 + 1], tot[4 * b4 + 2], tot[4 * b4 + 3]);
   }
 }
 
+__global__ __launch_bounds__(512) void k_m2l_wide(const float* __restrict__ cores, long long core_stride, int nch,
+                                                  const int4* __restrict__ units, const int4* __restrict__ ents,
+                                                  const float* __restrict__ uhat, float* __restrict__ chat,
+                                                  long long chat_rs, int ldk) {
+  // (slot of target 0, slot of target 1 or -1, first entry, end entry); wave = row block
+  const int4 u = units[blockIdx.x];
+  const int rb = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int j = lane & 31, h = lane >> 5;
+  const float* alane = cores + (size_t)rb * nch * 256 + 4 * lane;
+  const float* blane = uhat + 8 * j + 4 * h;
+  const size_t box_stride = (size_t)nch * 256;
+  v16f acc0, acc1, tot0, tot1;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc0[e] = acc1[e] = tot0[e] = tot1[e] = 0.f;
+  for (int e0 = u.z; e0 < u.w; e0 += kM2LFlush) {
+    const int e1 = min(e0 + kM2LFlush, u.w);
+    for (int e = e0; e < e1; ++e) {
+      const int4 en = ents[e];  // (core index, source of target 0 or -1, source of target 1 or -1, 0)
+      const float* ap = alane + (size_t)en.x * core_stride;
+      if (en.y >= 0 && en.z >= 0)
+        wide_entry2(ap, blane + (size_t)en.y * box_stride, blane + (size_t)en.z * box_stride, nch, acc0, acc1);
+      else if (en.y >= 0)
+        wide_entry(ap, blane + (size_t)en.y * box_stride, nch, acc0);
+      else
+        wide_entry(ap, blane + (size_t)en.z * box_stride, nch, acc1);
+    }
+    // a group of kM2LFlush entries: into the running totals, restart
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      tot0[e] += acc0[e];
+      tot1[e] += acc1[e];
+      acc0[e] = acc1[e] = 0.f;
+    }
+  }
+  wide_store(tot0, chat, chat_rs, u.x, rb, ldk, j, h);
+  if (u.y >= 0) wide_store(tot1, chat, chat_rs, u.y, rb, ldk, j, h);
+}
+
 bool launch_m2l_wide(int row_blocks, const float* cores, long long core_stride, int ldk, const int4* units,
-                     int nunits, const int2* vlist, const float* uhat, float* chat, long long chat_rs, hipStream_t s) {
+                     int nunits, const int4* ents, const float* uhat, float* chat, long long chat_rs, hipStream_t s) {
   if (nunits <= 0) return true;
-  if (row_blocks < 1 || row_blocks > 8 || nunits % row_blocks) return false;
-  hipLaunchKernelGGL(k_m2l_wide, dim3(nunits / row_blocks), dim3(64 * row_blocks), 0, s, cores, core_stride, ldk / 8,
-                     units, vlist, uhat, chat, chat_rs, ldk);
+  if (row_blocks < 1 || row_blocks > 8) return false;
+  hipLaunchKernelGGL(k_m2l_wide, dim3(nunits), dim3(64 * row_blocks), 0, s, cores, core_stride, ldk / 8, units, ents,
+                     uhat, chat, chat_rs, ldk);
   return true;
 }
 

@@ -706,31 +706,57 @@ void prepare(Plan* P, Staging& S) {
       }
       require(vl.size() / 2 < (size_t)INT32_MAX, "V lists too long for the M2L tables");
       // Units (4 ints each) are dealt to XCDs by the target's position among its
-      // siblings, in groups of g consecutive units (one workgroup): an XCD then
-      // works through the ~189 cores of one position.  The gathered form deals
-      // row block by row block (the L2 holds one row block of those cores); the
-      // wide form deals all row blocks of a target as one workgroup (its uhat
-      // rows are read once for all of them).
-      auto deal = [&](std::vector<std::vector<int>>& ux, int g) {
+      // siblings: an XCD then works through the ~189 cores of one position.
+      auto deal = [&](std::vector<std::vector<int>>& ux) {
         std::vector<int> units;
         size_t most = 0;
-        for (auto& v : ux) most = std::max(most, v.size() / (4 * g));
+        for (auto& v : ux) most = std::max(most, v.size() / 4);
         for (size_t i = 0; i < most; ++i)
           for (int x = 0; x < 8; ++x)
-            if (i < ux[x].size() / (4 * g))
-              units.insert(units.end(), ux[x].begin() + 4 * g * i, ux[x].begin() + 4 * g * (i + 1));
+            if (i < ux[x].size() / 4) units.insert(units.end(), ux[x].begin() + 4 * i, ux[x].begin() + 4 * i + 4);
         return units;
       };
       if (P->m2l_wide) {
-        std::vector<std::vector<int>> ux(8);
-        for (int x = 0; x < 8; ++x)
-          for (size_t i = 0; i < tgt_slot.size(); ++i)
-            if (tgt_pos[i] == x)
-              for (int rb = 0; rb < P->m2l_rb; ++rb)
-                ux[x].insert(ux[x].end(), {tgt_slot[i], rb, (int)tgt_first[i], (int)tgt_end[i]});
-        std::vector<int> units = deal(ux, P->m2l_rb);
+        // Wide form: targets of one level and position paired in Morton order, each
+        // pair's V lists merged by core index into entries (core, source of the first
+        // target or -1, source of the second or -1, 0); one unit (workgroup) per pair.
+        std::vector<int> ents, ux_all[8];
+        std::vector<std::pair<int, int>> la, lb;
+        auto sorted_list = [&](size_t i, std::vector<std::pair<int, int>>& out) {
+          out.clear();
+          for (int64_t e = tgt_first[i]; e < tgt_end[i]; ++e) out.push_back({vl[2 * e], vl[2 * e + 1]});
+          std::sort(out.begin(), out.end());
+        };
+        for (int l = 2; l <= L; ++l)
+          for (int x = 0; x < 8; ++x) {
+            std::vector<size_t> members;
+            for (size_t i = 0; i < tgt_slot.size(); ++i)
+              if (tgt_level[i] == l && tgt_pos[i] == x) members.push_back(i);
+            for (size_t m = 0; m < members.size(); m += 2) {
+              const bool two = m + 1 < members.size();
+              sorted_list(members[m], la);
+              if (two) sorted_list(members[m + 1], lb);
+              else lb.clear();
+              const int first = (int)(ents.size() / 4);
+              size_t ia = 0, ib = 0;
+              while (ia < la.size() || ib < lb.size()) {
+                const int ta = ia < la.size() ? la[ia].first : INT32_MAX;
+                const int tb = ib < lb.size() ? lb[ib].first : INT32_MAX;
+                const int t = std::min(ta, tb);
+                ents.insert(ents.end(), {t, ta == t ? la[ia].second : -1, tb == t ? lb[ib].second : -1, 0});
+                ia += ta == t;
+                ib += tb == t;
+              }
+              ux_all[x].insert(ux_all[x].end(), {tgt_slot[members[m]], two ? tgt_slot[members[m + 1]] : -1, first,
+                                                 (int)(ents.size() / 4)});
+            }
+          }
+        require(ents.size() / 4 < (size_t)INT32_MAX, "V lists too long for the M2L tables");
+        std::vector<std::vector<int>> ux(ux_all, ux_all + 8);
+        std::vector<int> units = deal(ux);
         P->n_units = (int)(units.size() / 4);
-        S.data((void**)&P->d_vlist, std::move(vl));
+        P->n_wide_entries = (int64_t)(ents.size() / 4);
+        S.data((void**)&P->d_wents, std::move(ents));
         S.data((void**)&P->d_units, std::move(units));
       } else {
         // Gathered form: groups of up to 32 targets of one level and position; per
@@ -772,9 +798,9 @@ void prepare(Plan* P, Staging& S) {
               for (int rb = 0; rb < P->m2l_rb; ++rb) ux[x].insert(ux[x].end(), {g, rb, first, end});
             }
           }
-        std::vector<int> units = deal(ux_leaf, 1);
+        std::vector<int> units = deal(ux_leaf);
         P->n_gunits_leaf = (int)(units.size() / 4);
-        const std::vector<int> upper = deal(ux_upper, 1);
+        const std::vector<int> upper = deal(ux_upper);
         units.insert(units.end(), upper.begin(), upper.end());
         P->n_gunits = (int)(units.size() / 4);
         S.data((void**)&P->d_gent_core, std::move(ent_core));
@@ -817,8 +843,7 @@ void check_launches(const Plan* P) {
                                         m2l_bf16_supported(3, P->m2l_rb, P->kst)
                                   : m2l_supported(P->m2l_rb, P->kst, P->m2l_lds_ld);
     if (!ok) fail(KIFMM_E_INVALID, "M2L kernel configuration not available for this rank");
-    if (P->m2l_wide && (P->m2l_rb > 8 || P->n_units % P->m2l_rb))
-      fail(KIFMM_E_INVALID, "internal: wide M2L units not in whole workgroups");
+    if (P->m2l_wide && P->m2l_rb > 8) fail(KIFMM_E_INVALID, "M2L rank too large for the wide M2L kernel");
   }
 }
 
@@ -985,7 +1010,7 @@ bool launch_m2l_form(Plan* P, hipStream_t st, int part) {
   if (P->m2l_wide) {
     if (part == 2) return true;
     return launch_m2l_wide(P->m2l_rb, P->d_cores, (long long)P->core_rows * kst, kst, P->d_units, P->n_units,
-                           P->d_vlist, P->d_uhat, P->d_chat, TS * kst, st);
+                           P->d_wents, P->d_uhat, P->d_chat, TS * kst, st);
   }
   if (P->m2l_gather) {
     const int u0 = part == 2 ? P->n_gunits_leaf : 0;
