@@ -155,10 +155,125 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const float* __restrict__ W, in
   }
 }
 
+// ------------------------------------------------ GEMM, 32 batch entries ---
+// The same product for a batch of exactly 32 (the 32 right-hand sides) and
+// K <= 256, with
+// the batch entries as the 32 columns of v_mfma_f32_32x32x2_f32: per box, the
+// 32 entries' rows of X form the B operand, so that a chunk of W staged in LDS
+// serves 32 x kR32Boxes columns and every X row is fetched once.  A workgroup
+// is nrb waves (32-row blocks of W: rows o_base .. o_base + 32 nrb - 1) over
+// kR32Boxes boxes; W is staged in LDS kR32Slab k at a time (row stride
+// kR32Slab / 4 + 1 float4, odd), zero beyond nout and K.  Lane (j, h) = (l % 32,
+// l / 32) reads A[row j][8c + 4h .. +3] from LDS and B[8c + 4h .. +3][entry j]
+// (entry j's row of the box) from global memory, one chunk ahead; the
+// accumulator of a box holds D[8 (v / 4) + 4 h + v % 4][entry j].  With ywide
+// a lane's four outputs of one box are 16 contiguous bytes of a 1 KiB block.
+constexpr int kR32Boxes = 4;
+constexpr int kR32Slab = 64;
+
+__global__ __launch_bounds__(512) void k_gemm_r32(const float* __restrict__ W, int ldw, const float* __restrict__ X,
+                                                  int ldx, const int* __restrict__ xrow, float* __restrict__ Y,
+                                                  int ldy, const int* __restrict__ yrow, int nbox, int nout, int K,
+                                                  float alpha, int beta, long long xbs, long long ybs, int ywide) {
+  extern __shared__ float4 s_wr[];  // [32 nrb][kR32Slab / 4 + 1]
+  constexpr int ld4 = kR32Slab / 4 + 1;
+  const int nrb = blockDim.x >> 6;
+  const int o_base = blockIdx.y * 32 * nrb;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = lane & 31, h = lane >> 5;
+  const int b0 = blockIdx.x * kR32Boxes;
+  const float* xp[kR32Boxes];  // entry j's row of each box, at this lane's k offset 4 h
+#pragma unroll
+  for (int bb = 0; bb < kR32Boxes; ++bb) {
+    const int b = min(b0 + bb, nbox - 1);
+    xp[bb] = X + j * xbs + (size_t)(xrow ? xrow[b] : b) * ldx + 4 * h;
+  }
+  v16f acc[kR32Boxes];
+#pragma unroll
+  for (int bb = 0; bb < kR32Boxes; ++bb)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[bb][e] = 0.f;
+  const int nch_all = (K + 7) >> 3;  // 8-k chunks over the whole K (the last may hold 4)
+  auto load_b = [&](float4* b, int g) {
+    const int k = 8 * g + 4 * h;  // this lane's first k of chunk g
+#pragma unroll
+    for (int bb = 0; bb < kR32Boxes; ++bb)
+      b[bb] = k < K ? *reinterpret_cast<const float4*>(xp[bb] + 8 * g) : make_float4(0.f, 0.f, 0.f, 0.f);
+  };
+  float4 bc[kR32Boxes], bn[kR32Boxes];
+  load_b(bc, 0);
+  for (int k0 = 0; k0 < K; k0 += kR32Slab) {
+    const int kw = min(kR32Slab, K - k0);  // a multiple of 4
+    const int w4 = ((kw + 7) >> 3) * 2;    // float4 columns staged (whole chunks)
+    if (k0) __syncthreads();               // the previous slab fully read
+    for (int idx = threadIdx.x; idx < 32 * nrb * w4; idx += blockDim.x) {
+      const int r = idx / w4, c4 = idx - r * w4;
+      const int o = o_base + r;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (o < nout && 4 * c4 < kw) v = *reinterpret_cast<const float4*>(W + (size_t)o * ldw + k0 + 4 * c4);
+      s_wr[r * ld4 + c4] = v;
+    }
+    __syncthreads();
+    const float4* arow = s_wr + (32 * wave + j) * ld4 + h;
+    const int g0 = k0 >> 3, nch = (kw + 7) >> 3;
+    for (int c = 0; c < nch; ++c) {
+      load_b(bn, min(g0 + c + 1, nch_all - 1));  // next chunk (past the end: the last again, unused)
+      const float4 a = arow[2 * c];
+#pragma unroll
+      for (int bb = 0; bb < kR32Boxes; ++bb) {
+        acc[bb] = mfma32(a.x, bc[bb].x, acc[bb]);
+        acc[bb] = mfma32(a.y, bc[bb].y, acc[bb]);
+        acc[bb] = mfma32(a.z, bc[bb].z, acc[bb]);
+        acc[bb] = mfma32(a.w, bc[bb].w, acc[bb]);
+      }
+#pragma unroll
+      for (int bb = 0; bb < kR32Boxes; ++bb) bc[bb] = bn[bb];
+    }
+  }
+  const int ob = o_base + 32 * wave;
+#pragma unroll
+  for (int bb = 0; bb < kR32Boxes; ++bb) {
+    const int b = b0 + bb;
+    if (b >= nbox) continue;
+    const int r = yrow ? yrow[b] : b;
+#pragma unroll
+    for (int b4 = 0; b4 < 4; ++b4) {
+      const int o = ob + 8 * b4 + 4 * h;
+      if (o >= nout) continue;
+      float* yp = ywide ? Y + (((size_t)r * (nout >> 3) + (o >> 3)) * 32 + j) * 8 + (o & 7)
+                        : Y + j * ybs + (size_t)r * ldy + o;
+      float4 v = make_float4(alpha * acc[bb][4 * b4], alpha * acc[bb][4 * b4 + 1], alpha * acc[bb][4 * b4 + 2],
+                             alpha * acc[bb][4 * b4 + 3]);
+      if (beta) {
+        const float4 old = *reinterpret_cast<const float4*>(yp);
+        v.x += old.x;
+        v.y += old.y;
+        v.z += old.z;
+        v.w += old.w;
+      }
+      *reinterpret_cast<float4*>(yp) = v;
+    }
+  }
+}
+
+size_t gemm_r32_lds_bytes(int nrb) { return (size_t)32 * nrb * (kR32Slab / 4 + 1) * 16; }
+
 void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int* xrow, float* Y, int ldy,
                     const int* yrow, int nbox, int nout, int K, float alpha, int beta, hipStream_t s, int batch,
                     long long xbs, long long ybs, int ywide) {
   if (nbox <= 0 || batch <= 0) return;
+  if (batch == 32 && K <= 256) {
+    // (long K keeps k_gemm_nt, whose accumulators add four k per step: its FP32
+    // chains are half as long)
+    // row blocks of 32 outputs, at most 8 per workgroup, spread evenly over the row tiles
+    const int rb_all = (nout + 31) / 32;
+    const int tiles = (rb_all + 7) / 8;
+    const int nrb = (rb_all + tiles - 1) / tiles;
+    hipLaunchKernelGGL(k_gemm_r32, dim3((nbox + kR32Boxes - 1) / kR32Boxes, tiles), dim3(64 * nrb),
+                       gemm_r32_lds_bytes(nrb), s, W, ldw, X, ldx, xrow, Y, ldy, yrow, nbox, nout, K, alpha, beta,
+                       xbs, ybs, ywide);
+    return;
+  }
   const long long tiles64 = (long long)((nbox + 63) / 64) * ((nout + 63) / 64) * batch;
   if (tiles64 < 512 && K >= 256) {
     dim3 grid((nbox + 31) / 32, (nout + 31) / 32, batch);
@@ -169,6 +284,13 @@ void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int*
     hipLaunchKernelGGL(k_gemm_nt<1>, grid, dim3(256), 0, s, W, ldw, X, ldx, xrow, Y, ldy, yrow, nbox, nout, K, alpha,
                        beta, xbs, ybs, ywide);
   }
+}
+
+// Dynamic LDS limit of the 32-entry GEMM on the current device (see
+// configure_kernels).
+hipError_t configure_gemm_kernels() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_r32), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)kMaxDynamicLds);
 }
 
 }  // namespace kifmm

@@ -929,7 +929,8 @@ bool launch_leaf_multi(int R, const float4* pts, const float* qs, const int* sta
 // device.  Plans call this once per device (under a lock) before their first
 // launch; the launchers then only check their sizes against kMaxDynamicLds.
 hipError_t configure_kernels() {
-  const hipError_t e = configure_m2l_kernels();
+  hipError_t e = configure_m2l_kernels();
+  if (e == hipSuccess) e = configure_gemm_kernels();
   if (e != hipSuccess) return e;
   const void* kernels[] = {reinterpret_cast<const void*>(&k_p2p<0>), reinterpret_cast<const void*>(&k_p2p<1>),
                            reinterpret_cast<const void*>(&k_p2p<2>)};
