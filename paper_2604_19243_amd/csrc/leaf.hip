@@ -397,6 +397,31 @@ bool launch_p2p(int mode, const float4* pts, const int* start, const int* blk, i
   return true;
 }
 
+// The source ranges [a, b) of the 27 leaves around leaf slot o of parent group g
+// (its 4 x 4 x 4 leaf block, x fastest; neighbour nb = (dx + 1) + 3 (dy + 1) +
+// 9 (dz + 1), the leaf itself nb = 13), one per lane of lanes 0..26 (a = b for
+// a missing or empty leaf).  All 27 are loaded at once, so that a kernel walking
+// the neighbours reads each range with readlane instead of waiting on two
+// dependent loads per neighbour.
+struct NbRange {
+  int a, b;
+};
+
+__device__ __forceinline__ NbRange neighbour_ranges(const int* __restrict__ blk, const int* __restrict__ start, int g,
+                                                    int o, int lane) {
+  NbRange r{0, 0};
+  if (lane < 27) {
+    const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
+    const int bx = 1 + (o & 1), by = 1 + ((o >> 1) & 1), bz = 1 + ((o >> 2) & 1);
+    const int ns = blk[(size_t)g * 64 + (bx + dx) + 4 * (by + dy) + 16 * (bz + dz)];
+    if (ns >= 0) {
+      r.a = start[ns];
+      r.b = start[ns + 1];
+    }
+  }
+  return r;
+}
+
 // ---------------------------------------------------- leaf work queue ---
 // Fused D2T and ULI (Algorithm 1 steps 3b, 3c) as a persistent kernel over a
 // work queue of target tiles.  A tile is up to 64 consecutive targets of one
@@ -510,26 +535,20 @@ __global__ __launch_bounds__(256) void k_leaf_queue(const float4* __restrict__ p
     const int ti = tile.y + min(lane, cnt - 1);
     const float4 x = pts[ti];
     const int g = slot / group_slots, o = slot - g * group_slots;
-    const int bx = 1 + (o & 1), by = 1 + ((o >> 1) & 1), bz = 1 + ((o >> 2) & 1);
     double aphi = 0.0, agx = 0.0, agy = 0.0, agz = 0.0;
     if (kNear) {
       // the 27 leaves of the block around the tile's leaf; a leaf's sources four per
       // step, the next step's loaded while this one is used
       Sum4 acc;
-      for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy) {
-          const bool own = (dy == 0) & (dz == 0);
-          for (int dx = -1; dx <= 1; ++dx) {
-            const int ns = blk[(size_t)g * 64 + (bx + dx) + 4 * (by + dy) + 16 * (bz + dz)];
-            if (ns < 0) continue;
-            const int a = start[ns], b = start[ns + 1];
-            if (a >= b) continue;
-            if (own)
-              queue_leaf<true>(pts, a, b, x, acc);
-            else
-              queue_leaf<false>(pts, a, b, x, acc);
-          }
-        }
+      const NbRange nr = neighbour_ranges(blk, start, g, o, lane);
+      for (int nb = 0; nb < 27; ++nb) {
+        const int a = __builtin_amdgcn_readlane(nr.a, nb), b = __builtin_amdgcn_readlane(nr.b, nb);
+        if (a >= b) continue;
+        if (nb / 3 == 4)  // the row (dy = dz = 0) that holds the tile's own leaf
+          queue_leaf<true>(pts, a, b, x, acc);
+        else
+          queue_leaf<false>(pts, a, b, x, acc);
+      }
       aphi = acc.phi;
       agx = acc.gx;
       agy = acc.gy;
@@ -716,51 +735,47 @@ __global__ __launch_bounds__(256) void k_leaf_multi(const float4* __restrict__ p
   const int ti = start[slot] + task.y + min(lane, cnt - 1);
   const float4 x = pts[ti];
   const int g = slot / group_slots, o = slot - g * group_slots;
-  const int bx = 1 + (o & 1), by = 1 + ((o >> 1) & 1), bz = 1 + ((o >> 2) & 1);
   double acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = 0.0;
-  for (int dz = -1; dz <= 1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int ns = blk[(size_t)g * 64 + (bx + dx) + 4 * (by + dy) + 16 * (bz + dz)];
-        if (ns < 0) continue;
-        const int a = start[ns], b = start[ns + 1];
-        const bool self = ns == slot;
-        float part[R];
+  const NbRange nr = neighbour_ranges(blk, start, g, o, lane);
+  for (int nb = 0; nb < 27; ++nb) {
+    const int a = __builtin_amdgcn_readlane(nr.a, nb), b = __builtin_amdgcn_readlane(nr.b, nb);
+    const bool self = nb == 13;
+    float part[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) part[r] = 0.f;
-        for (int c = a; c < b; c += kMultiChunk) {
-          const int m = min(kMultiChunk, b - c);
-          __builtin_amdgcn_wave_barrier();  // the previous chunk's reads come first
-          if (lane < m) pos[lane] = pts[c + lane];
-          for (int f = lane; f < m * R; f += 64) q[f] = qs[(size_t)c * R + f];
-          __builtin_amdgcn_wave_barrier();  // LDS accesses of one wave complete in order
-          for (int j = 0; j < m; ++j) {
-            const float4 y = pos[j];
-            const float ex = x.x - y.x, ey = x.y - y.y, ez = x.z - y.z;
-            const float r2 = ex * ex + ey * ey + ez * ez;
-            float rinv = __builtin_amdgcn_rsqf(r2);
-            if (self) rinv = r2 > 0.f ? rinv : 0.f;  // the target itself
-            const float* qj = q + j * R;
-            if constexpr (R % 4 == 0) {
+    for (int r = 0; r < R; ++r) part[r] = 0.f;
+    for (int c = a; c < b; c += kMultiChunk) {
+      const int m = min(kMultiChunk, b - c);
+      __builtin_amdgcn_wave_barrier();  // the previous chunk's reads come first
+      if (lane < m) pos[lane] = pts[c + lane];
+      for (int f = lane; f < m * R; f += 64) q[f] = qs[(size_t)c * R + f];
+      __builtin_amdgcn_wave_barrier();  // LDS accesses of one wave complete in order
+      for (int j = 0; j < m; ++j) {
+        const float4 y = pos[j];
+        const float ex = x.x - y.x, ey = x.y - y.y, ez = x.z - y.z;
+        const float r2 = ex * ex + ey * ey + ez * ez;
+        float rinv = __builtin_amdgcn_rsqf(r2);
+        if (self) rinv = r2 > 0.f ? rinv : 0.f;  // the target itself
+        const float* qj = q + j * R;
+        if constexpr (R % 4 == 0) {
 #pragma unroll
-              for (int r = 0; r < R; r += 4) {
-                const float4 q4 = *reinterpret_cast<const float4*>(qj + r);
-                part[r] += q4.x * rinv;
-                part[r + 1] += q4.y * rinv;
-                part[r + 2] += q4.z * rinv;
-                part[r + 3] += q4.w * rinv;
-              }
-            } else {
-#pragma unroll
-              for (int r = 0; r < R; ++r) part[r] += qj[r] * rinv;
-            }
+          for (int r = 0; r < R; r += 4) {
+            const float4 q4 = *reinterpret_cast<const float4*>(qj + r);
+            part[r] += q4.x * rinv;
+            part[r + 1] += q4.y * rinv;
+            part[r + 2] += q4.z * rinv;
+            part[r + 3] += q4.w * rinv;
           }
-        }
+        } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] += part[r];
+          for (int r = 0; r < R; ++r) part[r] += qj[r] * rinv;
+        }
       }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] += part[r];
+  }
   if (far) {
     const float4 ch = centers[2 * slot], cl = centers[2 * slot + 1];
     const float xx = (x.x - ch.x) - cl.x, xy = (x.y - ch.y) - cl.y, xz = (x.z - ch.z) - cl.z;
@@ -824,6 +839,8 @@ __global__ __launch_bounds__(256) void k_leaf_multi(const float4* __restrict__ p
 // side i per lane.  FP32 accumulation per source leaf and per 16 surface points,
 // added into FP64 totals.  Sources past a leaf's end have charge zero;
 // coincident points (only in the target's own leaf) have K = 0.
+constexpr int kR32Ahead = 4;  // source steps in flight per lane in k_leaf_r32
+
 __global__ __launch_bounds__(256) void k_leaf_r32(const float4* __restrict__ pts, const float* __restrict__ qs,
                                                   const int* __restrict__ start, const int4* __restrict__ tasks,
                                                   int ntasks, const int* __restrict__ blk, int group_slots,
@@ -840,7 +857,6 @@ __global__ __launch_bounds__(256) void k_leaf_r32(const float4* __restrict__ pts
   const int t0 = start[slot] + task.y;  // sorted index of the tile's first target
   const float4 x = pts[t0 + min(i, cnt - 1)];
   const int g = slot / group_slots, o = slot - g * group_slots;
-  const int bx = 1 + (o & 1), by = 1 + ((o >> 1) & 1), bz = 1 + ((o >> 2) & 1);
   double tot[16];
 #pragma unroll
   for (int v = 0; v < 16; ++v) tot[v] = 0.0;
@@ -854,32 +870,38 @@ __global__ __launch_bounds__(256) void k_leaf_r32(const float4* __restrict__ pts
   v16f acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-  for (int dz = -1; dz <= 1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int ns = blk[(size_t)g * 64 + (bx + dx) + 4 * (by + dy) + 16 * (bz + dz)];
-        if (ns < 0) continue;
-        const int a = start[ns], b = start[ns + 1];
-        if (a >= b) continue;
-        const bool self = ns == slot;
-        // this lane's source of the step and its charge of right-hand side i, one step ahead
-        int js = a + h;
-        float4 y = pts[min(js, b - 1)];
-        float q = js < b ? qs[(size_t)js * 32 + i] : 0.f;
-        for (int j = a; j < b; j += 2) {
-          const int jn = j + 2 + h;
-          const float4 yn = pts[min(jn, b - 1)];
-          const float qn = jn < b ? qs[(size_t)min(jn, b - 1) * 32 + i] : 0.f;
-          const float ex = x.x - y.x, ey = x.y - y.y, ez = x.z - y.z;
-          const float r2 = ex * ex + ey * ey + ez * ez;
-          float k = __builtin_amdgcn_rsqf(r2);
-          if (self) k = r2 > 0.f ? k : 0.f;  // the target itself
-          acc = mfma32(k, q, acc);
-          y = yn;
-          q = qn;
-        }
-        flush(acc);
+  const NbRange nr = neighbour_ranges(blk, start, g, o, lane);
+  for (int nb = 0; nb < 27; ++nb) {
+    const int a = __builtin_amdgcn_readlane(nr.a, nb), b = __builtin_amdgcn_readlane(nr.b, nb);
+    if (a >= b) continue;
+    const bool self = nb == 13;
+    // this lane's source of a step (2 sources per step) and its charge of
+    // right-hand side i, loaded kR32Ahead steps before its use
+    // (loads clamped to the leaf's last source; a lane past the end gets k = 0)
+    float4 y[kR32Ahead];
+    float q[kR32Ahead];
+    auto fetch = [&](int u, int jstep) {
+      const int js = min(jstep + h, b - 1);
+      y[u] = pts[js];
+      q[u] = qs[js * 32 + i];
+    };
+#pragma unroll
+    for (int u = 0; u < kR32Ahead; ++u) fetch(u, a + 2 * u);
+    for (int j = a; j < b; j += 2 * kR32Ahead) {
+#pragma unroll
+      for (int u = 0; u < kR32Ahead; ++u) {
+        if (j + 2 * u >= b) break;  // wave-uniform
+        const float ex = x.x - y[u].x, ey = x.y - y[u].y, ez = x.z - y[u].z;
+        const float r2 = ex * ex + ey * ey + ez * ez;
+        float k = __builtin_amdgcn_rsqf(r2);
+        if (self) k = r2 > 0.f ? k : 0.f;  // the target itself
+        k = j + 2 * u + h < b ? k : 0.f;
+        acc = mfma32(k, q[u], acc);
+        fetch(u, j + 2 * u + 2 * kR32Ahead);
       }
+    }
+    flush(acc);
+  }
   if (far) {
     const float4 ch = centers[2 * slot], cl = centers[2 * slot + 1];
     const float xx = (x.x - ch.x) - cl.x, xy = (x.y - ch.y) - cl.y, xz = (x.z - ch.z) - cl.z;
