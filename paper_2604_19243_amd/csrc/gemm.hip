@@ -168,8 +168,8 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const float* __restrict__ W, in
 // (entry j's row of the box) from global memory, one chunk ahead; the
 // accumulator of a box holds D[8 (v / 4) + 4 h + v % 4][entry j].  With ywide
 // a lane's four outputs of one box are 16 contiguous bytes of a 1 KiB block.
-constexpr int kR32Boxes = 4;
-constexpr int kR32Slab = 64;
+constexpr int kR32Boxes = 2;
+constexpr int kR32Slab = 32;
 
 __global__ __launch_bounds__(512) void k_gemm_r32(const float* __restrict__ W, int ldw, const float* __restrict__ X,
                                                   int ldx, const int* __restrict__ xrow, float* __restrict__ Y,
