@@ -16,7 +16,7 @@ hipError_t configure_kernels();
 hipError_t configure_m2l_kernels();
 hipError_t configure_gemm_kernels();
 
-// An M2L work item (see k_m2l in kernels.hip): one aligned 4x4x4 block of
+// An M2L work item (see k_m2l in m2l.hip): one aligned 4x4x4 block of
 // parents at one level, target sibling position o and source position o'.
 struct M2LItem {
   int pair;      // 8 o + o'

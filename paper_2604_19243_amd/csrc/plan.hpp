@@ -92,7 +92,7 @@ struct Plan : Object {
   int4* d_units = nullptr;               // wide: (slot 0, slot 1 or -1, first, end entry); gathered: (group, row block, first, end)
   int n_units = 0;
   float* d_qs = nullptr;                 // nrhs > 1: sorted charges [N][nrhs]
-  int4* d_tasks = nullptr;               // nrhs > 1: leaf tasks (slot, first point, count <= 64, 0)
+  int4* d_tasks = nullptr;               // nrhs > 1: leaf tasks (slot, first point in the leaf, count <= 64 or 32, 0)
   int n_tasks = 0;
   float* d_vjp_fs = nullptr;             // KIFMM_VJP: grad f of the charges, [n][3], input order
   float* d_vjp_fw = nullptr;             // KIFMM_VJP: grad f of the weights, [n][3], input order
