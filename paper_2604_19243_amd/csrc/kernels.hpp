@@ -53,9 +53,11 @@ bool launch_m2l_bf16(int pieces, int row_blocks, const uint16_t* cores, size_t c
                      const float* uhat, float* chat_part, long long part_stride, int nrhs, long long rhs_stride,
                      hipStream_t s, bool upper = false);
 // M2L for 32 right-hand sides: one workgroup of row_blocks waves (<= 8, false otherwise)
-// per unit (slot of target 0, slot of target 1 or -1, first, end merged entry); merged
-// entries (core index, source slot of target 0 or -1, of target 1 or -1, 0); uhat in the
-// lane order written by launch_gemm_nt(ywide); chat [32][slots][ldk] (chat_rs = slots * ldk).
+// per unit, two int4 each: (slot of target 0, slot of target 1 or -1, first, end entry)
+// and (end of the entries of both targets, end of those of target 0 alone, 0, 0), those
+// of target 1 alone last; entries (core index, source slot of target 0 or -1, of target
+// 1 or -1, 0); uhat in the lane order written by launch_gemm_nt(ywide); chat
+// [32][slots][ldk] (chat_rs = slots * ldk).
 bool launch_m2l_wide(int row_blocks, const float* cores, long long core_stride, int ldk, const int4* units,
                      int nunits, const int4* ents, const float* uhat, float* chat, long long chat_rs, hipStream_t s);
 // M2L with gathered sources, one right-hand side: units (group, row block, first, end entry);

@@ -325,62 +325,24 @@ void launch_m2l_gather(const float* cores, long long core_stride, int ldk, const
 // The compressed VLI for 32 right-hand sides as wide products: per target box
 // and V-list entry (offset t, source box), chat[:, target] += C_t uhat[:, source]
 // with the 32 right-hand sides as the 32 columns of v_mfma_f32_32x32x2_f32.
-// The kernel is bound by its fetches of the operator slices and of uhat, not
-// by the matrix cores, so it is arranged to fetch each of them fewer times:
-// * two targets of one level and one position among siblings (neighbours in
-//   Morton order, so their V lists hold mostly the same offsets) share a
-//   workgroup, whose merged list holds each offset once with the source of each
-//   target (or none): one fetch of C_t's chunk serves both targets' products;
-// * the workgroup's waves are the 32-row blocks of C, walking the same list in
-//   the same order, so that each uhat chunk is fetched once for all of them.
+// * Two targets of one level and one position among siblings (neighbours in
+//   Morton order, so their V lists hold many of the same offsets) share a
+//   workgroup.  Its entries come in three runs: the offsets both targets have
+//   (one fetch of C_t's chunk serves both products), then those of the first
+//   target alone, then those of the second alone.  Each run is a loop with one
+//   fixed set of products, so the accumulators stay in place across entries.
+// * The workgroup's waves are the 32-row blocks of C, walking the same entries
+//   in the same order, so that each uhat chunk is fetched once for all of them.
+// * Within a run the chunk steps of successive entries form one sequence; two
+//   register sets take turns, so each step's loads are in flight while the
+//   previous step's products run.  The loads are buffer loads (wave-uniform
+//   base in the resource, the lane's offset in a VGPR).
 // Operators are in the lane order of k_m2l; uhat is [box][k / 8][32][8], so
 // that lane (j, h) reads B[8c + 4h .. +3][right-hand side j] as one float4 and
 // a wave's read of one chunk is 1 KiB of contiguous memory.  No partial sums:
 // each wave writes chat[r][target][rows] once per target.  The accumulators
-// restart every kM2LFlush entries and are added into running totals (short
-// FP32 chains).
-
-// One entry's products for one target: C_t's chunks from ap, the source's from bp.
-__device__ __forceinline__ void wide_entry(const float* ap, const float* bp, int nch, v16f& acc) {
-  float4 a = *reinterpret_cast<const float4*>(ap);
-  float4 b = *reinterpret_cast<const float4*>(bp);
-  for (int c = 0; c < nch; ++c) {
-    const int cn = min(c + 1, nch - 1);  // next chunk (the last one repeats, unused)
-    const float4 an = *reinterpret_cast<const float4*>(ap + 256 * cn);
-    const float4 bn = *reinterpret_cast<const float4*>(bp + 256 * cn);
-    acc = mfma32(a.x, b.x, acc);
-    acc = mfma32(a.y, b.y, acc);
-    acc = mfma32(a.z, b.z, acc);
-    acc = mfma32(a.w, b.w, acc);
-    a = an;
-    b = bn;
-  }
-}
-
-// Both targets' products of one entry: each C_t chunk loaded once.
-__device__ __forceinline__ void wide_entry2(const float* ap, const float* bpa, const float* bpb, int nch, v16f& acc0,
-                                            v16f& acc1) {
-  float4 a = *reinterpret_cast<const float4*>(ap);
-  float4 b0 = *reinterpret_cast<const float4*>(bpa);
-  float4 b1 = *reinterpret_cast<const float4*>(bpb);
-  for (int c = 0; c < nch; ++c) {
-    const int cn = min(c + 1, nch - 1);
-    const float4 an = *reinterpret_cast<const float4*>(ap + 256 * cn);
-    const float4 bn0 = *reinterpret_cast<const float4*>(bpa + 256 * cn);
-    const float4 bn1 = *reinterpret_cast<const float4*>(bpb + 256 * cn);
-    acc0 = mfma32(a.x, b0.x, acc0);
-    acc1 = mfma32(a.x, b1.x, acc1);
-    acc0 = mfma32(a.y, b0.y, acc0);
-    acc1 = mfma32(a.y, b1.y, acc1);
-    acc0 = mfma32(a.z, b0.z, acc0);
-    acc1 = mfma32(a.z, b1.z, acc1);
-    acc0 = mfma32(a.w, b0.w, acc0);
-    acc1 = mfma32(a.w, b1.w, acc1);
-    a = an;
-    b0 = bn0;
-    b1 = bn1;
-  }
-}
+// restart every kM2LFlush entries of a run and are added into running totals
+// (short FP32 chains).
 
 __device__ __forceinline__ void wide_store(const v16f& tot, float* chat, long long chat_rs, int slot, int rb, int ldk,
                                            int j, int h) {
@@ -394,40 +356,143 @@ __device__ __forceinline__ void wide_store(const v16f& tot, float* chat, long lo
   }
 }
 
-__global__ __launch_bounds__(512) void k_m2l_wide(const float* __restrict__ cores, long long core_stride, int nch,
-                                                  const int4* __restrict__ units, const int4* __restrict__ ents,
-                                                  const float* __restrict__ uhat, float* __restrict__ chat,
-                                                  long long chat_rs, int ldk) {
-  // (slot of target 0, slot of target 1 or -1, first entry, end entry); wave = row block
-  const int4 u = units[blockIdx.x];
-  const int rb = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int j = lane & 31, h = lane >> 5;
-  const float* alane = cores + (size_t)rb * nch * 256 + 4 * lane;
-  const float* blane = uhat + 8 * j + 4 * h;
-  const size_t box_stride = (size_t)nch * 256;
-  v16f acc0, acc1, tot0, tot1;
-#pragma unroll
-  for (int e = 0; e < 16; ++e) acc0[e] = acc1[e] = tot0[e] = tot1[e] = 0.f;
-  for (int e0 = u.z; e0 < u.w; e0 += kM2LFlush) {
-    const int e1 = min(e0 + kM2LFlush, u.w);
-    for (int e = e0; e < e1; ++e) {
-      const int4 en = ents[e];  // (core index, source of target 0 or -1, source of target 1 or -1, 0)
-      const float* ap = alane + (size_t)en.x * core_stride;
-      if (en.y >= 0 && en.z >= 0)
-        wide_entry2(ap, blane + (size_t)en.y * box_stride, blane + (size_t)en.z * box_stride, nch, acc0, acc1);
-      else if (en.y >= 0)
-        wide_entry(ap, blane + (size_t)en.y * box_stride, nch, acc0);
-      else
-        wide_entry(ap, blane + (size_t)en.z * box_stride, nch, acc1);
+// Buffer-resource loads: a wave-uniform base in the resource (an operator's row
+// block or a source box, so offsets stay within a few KiB), the lane's byte
+// offset in a VGPR; 0x00020000 is the raw 32-bit data format word of gfx9.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t wide_rsrc(const float* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, 0x7fffffff, 0x00020000);
+}
+__device__ __forceinline__ float4 bload(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
+// Position (entry e, 8-k chunk c) in a run's sequence of chunk steps, with
+// the entry's fields and the next entry's.  Stepping past the end stays on the
+// last chunk, so the loads it drives remain unconditional.
+struct WideCursor {
+  int e, c, end, nch;
+  int4 en, nx;
+  const int4* ents;
+  __device__ __forceinline__ void next() {
+    if (++c == nch) {
+      if (e + 1 < end) {
+        c = 0;
+        ++e;
+        en = nx;
+        nx = ents[min(e + 1, end - 1)];
+      } else {
+        c = nch - 1;
+      }
     }
-    // a group of kM2LFlush entries: into the running totals, restart
+  }
+};
+
+struct WideRegs {
+  float4 a, b0, b1;
+  bool first;
+};
+
+struct WideCtx {
+  const float* ablk;   // the wave's row block of core 0
+  const float* uhat;
+  size_t core_stride, box_stride;
+  int oa, ob;          // the lane's byte offsets in an operator chunk and in a source chunk
+};
+
+// P: 0 both targets, 1 target 0 only, 2 target 1 only.
+template <int P>
+__device__ __forceinline__ void wide_load(WideRegs& r, const WideCtx& x, int e0, const WideCursor& cu) {
+  r.a = bload(wide_rsrc(x.ablk + (size_t)cu.en.x * x.core_stride), x.oa + 1024 * cu.c);
+  if (P != 2) r.b0 = bload(wide_rsrc(x.uhat + (size_t)cu.en.y * x.box_stride), x.ob + 1024 * cu.c);
+  if (P != 1) r.b1 = bload(wide_rsrc(x.uhat + (size_t)cu.en.z * x.box_stride), x.ob + 1024 * cu.c);
+  r.first = cu.c == 0 && (cu.e - e0) % kM2LFlush == 0;
+}
+
+template <int P>
+__device__ __forceinline__ void wide_compute(const WideRegs& r, v16f& acc0, v16f& acc1, v16f& tot0, v16f& tot1) {
+  if (r.first) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       tot0[e] += acc0[e];
       tot1[e] += acc1[e];
       acc0[e] = acc1[e] = 0.f;
     }
+  }
+  if (P == 0) {
+    acc0 = mfma32(r.a.x, r.b0.x, acc0);
+    acc1 = mfma32(r.a.x, r.b1.x, acc1);
+    acc0 = mfma32(r.a.y, r.b0.y, acc0);
+    acc1 = mfma32(r.a.y, r.b1.y, acc1);
+    acc0 = mfma32(r.a.z, r.b0.z, acc0);
+    acc1 = mfma32(r.a.z, r.b1.z, acc1);
+    acc0 = mfma32(r.a.w, r.b0.w, acc0);
+    acc1 = mfma32(r.a.w, r.b1.w, acc1);
+  } else if (P == 1) {
+    acc0 = mfma32(r.a.x, r.b0.x, acc0);
+    acc0 = mfma32(r.a.y, r.b0.y, acc0);
+    acc0 = mfma32(r.a.z, r.b0.z, acc0);
+    acc0 = mfma32(r.a.w, r.b0.w, acc0);
+  } else {
+    acc1 = mfma32(r.a.x, r.b1.x, acc1);
+    acc1 = mfma32(r.a.y, r.b1.y, acc1);
+    acc1 = mfma32(r.a.z, r.b1.z, acc1);
+    acc1 = mfma32(r.a.w, r.b1.w, acc1);
+  }
+}
+
+// The chunk steps of the run of entries [e0, e1), all of kind P, two register
+// sets taking turns: each step's loads are issued one step ahead of its
+// products, across entry boundaries.  The accumulators restart every
+// kM2LFlush entries.
+template <int P>
+__device__ __forceinline__ void wide_run(const WideCtx& x, const int4* ents, int e0, int e1, int nch, v16f& acc0,
+                                         v16f& acc1, v16f& tot0, v16f& tot1) {
+  if (e0 >= e1) return;
+  const int nv = (e1 - e0) * nch;
+  WideCursor cu{e0, 0, e1, nch, ents[e0], ents[min(e0 + 1, e1 - 1)], ents};
+  WideRegs r0, r1;
+  wide_load<P>(r0, x, e0, cu);
+  cu.next();
+  int v = 0;
+  for (; v + 1 < nv; v += 2) {
+    wide_load<P>(r1, x, e0, cu);
+    cu.next();
+    __builtin_amdgcn_sched_barrier(0);
+    wide_compute<P>(r0, acc0, acc1, tot0, tot1);
+    __builtin_amdgcn_sched_barrier(0);
+    wide_load<P>(r0, x, e0, cu);
+    cu.next();
+    __builtin_amdgcn_sched_barrier(0);
+    wide_compute<P>(r1, acc0, acc1, tot0, tot1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (v < nv) wide_compute<P>(r0, acc0, acc1, tot0, tot1);
+}
+
+__global__ __launch_bounds__(512) void k_m2l_wide(const float* __restrict__ cores, long long core_stride, int nch,
+                                                  const int4* __restrict__ units, const int4* __restrict__ ents,
+                                                  const float* __restrict__ uhat, float* __restrict__ chat,
+                                                  long long chat_rs, int ldk) {
+  // units[2 b]: (slot of target 0, slot of target 1 or -1, first entry, end entry);
+  // units[2 b + 1]: (end of the entries of both targets, end of those of target 0 alone, 0, 0),
+  // then those of target 1 alone up to the end.  Wave = row block.
+  const int4 u = units[2 * blockIdx.x];
+  const int4 sg = units[2 * blockIdx.x + 1];
+  const int rb = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int j = lane & 31, h = lane >> 5;
+  const WideCtx x{cores + (size_t)rb * nch * 256, uhat, (size_t)core_stride, (size_t)nch * 256, 16 * lane,
+                  4 * (8 * j + 4 * h)};
+  v16f acc0, acc1, tot0, tot1;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc0[e] = acc1[e] = tot0[e] = tot1[e] = 0.f;
+  wide_run<0>(x, ents, u.z, sg.x, nch, acc0, acc1, tot0, tot1);
+  wide_run<1>(x, ents, sg.x, sg.y, nch, acc0, acc1, tot0, tot1);
+  wide_run<2>(x, ents, sg.y, u.w, nch, acc0, acc1, tot0, tot1);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    tot0[e] += acc0[e];
+    tot1[e] += acc1[e];
   }
   wide_store(tot0, chat, chat_rs, u.x, rb, ldk, j, h);
   if (u.y >= 0) wide_store(tot1, chat, chat_rs, u.y, rb, ldk, j, h);

@@ -705,21 +705,24 @@ void prepare(Plan* P, Staging& S) {
         }
       }
       require(vl.size() / 2 < (size_t)INT32_MAX, "V lists too long for the M2L tables");
-      // Units (4 ints each) are dealt to XCDs by the target's position among its
+      // Units (w ints each) are dealt to XCDs by the target's position among its
       // siblings: an XCD then works through the ~189 cores of one position.
-      auto deal = [&](std::vector<std::vector<int>>& ux) {
+      auto deal = [&](const std::vector<std::vector<int>>& ux, size_t w = 4) {
         std::vector<int> units;
         size_t most = 0;
-        for (auto& v : ux) most = std::max(most, v.size() / 4);
+        for (auto& v : ux) most = std::max(most, v.size() / w);
         for (size_t i = 0; i < most; ++i)
           for (int x = 0; x < 8; ++x)
-            if (i < ux[x].size() / 4) units.insert(units.end(), ux[x].begin() + 4 * i, ux[x].begin() + 4 * i + 4);
+            if (i < ux[x].size() / w) units.insert(units.end(), ux[x].begin() + w * i, ux[x].begin() + w * (i + 1));
         return units;
       };
       if (P->m2l_wide) {
-        // Wide form: targets of one level and position paired in Morton order, each
-        // pair's V lists merged by core index into entries (core, source of the first
-        // target or -1, source of the second or -1, 0); one unit (workgroup) per pair.
+        // Wide form: targets of one level and position paired in Morton order; per
+        // pair the entries (core, source of the first target or -1, source of the
+        // second or -1, 0) of the offsets both have, then of those of the first
+        // alone, then of those of the second alone, each run in core order; one
+        // unit (workgroup) per pair: (slot 0, slot 1 or -1, first, end entry) and
+        // (end of the first run, end of the second run, 0, 0).
         std::vector<int> ents, ux_all[8];
         std::vector<std::pair<int, int>> la, lb;
         auto sorted_list = [&](size_t i, std::vector<std::pair<int, int>>& out) {
@@ -737,24 +740,36 @@ void prepare(Plan* P, Staging& S) {
               sorted_list(members[m], la);
               if (two) sorted_list(members[m + 1], lb);
               else lb.clear();
+              // entries of both targets, then of target 0 alone, then of target 1 alone
               const int first = (int)(ents.size() / 4);
+              std::vector<int> only0, only1;
               size_t ia = 0, ib = 0;
               while (ia < la.size() || ib < lb.size()) {
                 const int ta = ia < la.size() ? la[ia].first : INT32_MAX;
                 const int tb = ib < lb.size() ? lb[ib].first : INT32_MAX;
-                const int t = std::min(ta, tb);
-                ents.insert(ents.end(), {t, ta == t ? la[ia].second : -1, tb == t ? lb[ib].second : -1, 0});
-                ia += ta == t;
-                ib += tb == t;
+                if (ta == tb) {
+                  ents.insert(ents.end(), {ta, la[ia].second, lb[ib].second, 0});
+                  ++ia;
+                  ++ib;
+                } else if (ta < tb) {
+                  only0.insert(only0.end(), {ta, la[ia].second, -1, 0});
+                  ++ia;
+                } else {
+                  only1.insert(only1.end(), {tb, -1, lb[ib].second, 0});
+                  ++ib;
+                }
               }
+              const int pair_end = (int)(ents.size() / 4);
+              ents.insert(ents.end(), only0.begin(), only0.end());
+              const int t0_end = (int)(ents.size() / 4);
+              ents.insert(ents.end(), only1.begin(), only1.end());
               ux_all[x].insert(ux_all[x].end(), {tgt_slot[members[m]], two ? tgt_slot[members[m + 1]] : -1, first,
-                                                 (int)(ents.size() / 4)});
+                                                 (int)(ents.size() / 4), pair_end, t0_end, 0, 0});
             }
           }
         require(ents.size() / 4 < (size_t)INT32_MAX, "V lists too long for the M2L tables");
-        std::vector<std::vector<int>> ux(ux_all, ux_all + 8);
-        std::vector<int> units = deal(ux);
-        P->n_units = (int)(units.size() / 4);
+        std::vector<int> units = deal(std::vector<std::vector<int>>(ux_all, ux_all + 8), 8);
+        P->n_units = (int)(units.size() / 8);
         P->n_wide_entries = (int64_t)(ents.size() / 4);
         S.data((void**)&P->d_wents, std::move(ents));
         S.data((void**)&P->d_units, std::move(units));

@@ -87,9 +87,9 @@ struct Plan : Object {
   int4* d_gunits = nullptr;              //   (group, row block, first entry, end entry)
   int n_gunits = 0, n_gunits_leaf = 0;   //   the first n_gunits_leaf units target the leaf level
   double m2l_tune_ms[2] = {0.0, 0.0};    // autotuned M2L forms: blocked, gathered (ms per launch)
-  int4* d_wents = nullptr;               // wide M2L: merged V-list entries of target pairs (core, src0, src1, 0)
+  int4* d_wents = nullptr;               // wide M2L: V-list entries of target pairs (core, src0 or -1, src1 or -1, 0)
   int64_t n_wide_entries = 0;
-  int4* d_units = nullptr;               // wide: (slot 0, slot 1 or -1, first, end entry); gathered: (group, row block, first, end)
+  int4* d_units = nullptr;               // wide: two per unit (see launch_m2l_wide); gathered: (group, row block, first, end)
   int n_units = 0;
   float* d_qs = nullptr;                 // nrhs > 1: sorted charges [N][nrhs]
   int4* d_tasks = nullptr;               // nrhs > 1: leaf tasks (slot, first point in the leaf, count <= 64 or 32, 0)
