@@ -165,11 +165,16 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const float* __restrict__ W, in
 // kR32Boxes boxes; W is staged in LDS kR32Slab k at a time (row stride
 // kR32Slab / 4 + 1 float4, odd), zero beyond nout and K.  Lane (j, h) = (l % 32,
 // l / 32) reads A[row j][8c + 4h .. +3] from LDS and B[8c + 4h .. +3][entry j]
-// (entry j's row of the box) from global memory, one chunk ahead; the
-// accumulator of a box holds D[8 (v / 4) + 4 h + v % 4][entry j].  With ywide
-// a lane's four outputs of one box are 16 contiguous bytes of a 1 KiB block.
+// (entry j's row of the box) from global memory; the accumulator of a box holds
+// D[8 (v / 4) + 4 h + v % 4][entry j].  With ywide a lane's four outputs of one
+// box are 16 contiguous bytes of a 1 KiB block.
+// The X chunks go to two register sets that take turns, so that each chunk's
+// loads are in flight while the previous chunk's products run (with one set
+// refilled by a copy, the compiler waits for each load before the products).
+// Past K (the upper half of a last 4-k chunk) a lane reads the row's last four
+// values again, which meet zeros of the staged W.
 constexpr int kR32Boxes = 2;
-constexpr int kR32Slab = 32;
+constexpr int kR32Slab = 32;  // four 8-k chunks: slab boundaries fall on even chunks
 
 __global__ __launch_bounds__(512) void k_gemm_r32(const float* __restrict__ W, int ldw, const float* __restrict__ X,
                                                   int ldx, const int* __restrict__ xrow, float* __restrict__ Y,
@@ -182,11 +187,11 @@ __global__ __launch_bounds__(512) void k_gemm_r32(const float* __restrict__ W, i
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = lane & 31, h = lane >> 5;
   const int b0 = blockIdx.x * kR32Boxes;
-  const float* xp[kR32Boxes];  // entry j's row of each box, at this lane's k offset 4 h
+  const float* xp[kR32Boxes];  // entry j's row of each box
 #pragma unroll
   for (int bb = 0; bb < kR32Boxes; ++bb) {
     const int b = min(b0 + bb, nbox - 1);
-    xp[bb] = X + j * xbs + (size_t)(xrow ? xrow[b] : b) * ldx + 4 * h;
+    xp[bb] = X + j * xbs + (size_t)(xrow ? xrow[b] : b) * ldx;
   }
   v16f acc[kR32Boxes];
 #pragma unroll
@@ -195,17 +200,15 @@ __global__ __launch_bounds__(512) void k_gemm_r32(const float* __restrict__ W, i
     for (int e = 0; e < 16; ++e) acc[bb][e] = 0.f;
   const int nch_all = (K + 7) >> 3;  // 8-k chunks over the whole K (the last may hold 4)
   auto load_b = [&](float4* b, int g) {
-    const int k = 8 * g + 4 * h;  // this lane's first k of chunk g
+    const int k = min(8 * g + 4 * h, K - 4);  // this lane's first k of chunk g
 #pragma unroll
-    for (int bb = 0; bb < kR32Boxes; ++bb)
-      b[bb] = k < K ? *reinterpret_cast<const float4*>(xp[bb] + 8 * g) : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int bb = 0; bb < kR32Boxes; ++bb) b[bb] = *reinterpret_cast<const float4*>(xp[bb] + k);
   };
-  float4 bc[kR32Boxes], bn[kR32Boxes];
-  load_b(bc, 0);
-  for (int k0 = 0; k0 < K; k0 += kR32Slab) {
+  auto stage = [&](int slab) {
+    const int k0 = slab * kR32Slab;
     const int kw = min(kR32Slab, K - k0);  // a multiple of 4
     const int w4 = ((kw + 7) >> 3) * 2;    // float4 columns staged (whole chunks)
-    if (k0) __syncthreads();               // the previous slab fully read
+    if (slab) __syncthreads();             // the previous slab fully read
     for (int idx = threadIdx.x; idx < 32 * nrb * w4; idx += blockDim.x) {
       const int r = idx / w4, c4 = idx - r * w4;
       const int o = o_base + r;
@@ -214,21 +217,35 @@ __global__ __launch_bounds__(512) void k_gemm_r32(const float* __restrict__ W, i
       s_wr[r * ld4 + c4] = v;
     }
     __syncthreads();
-    const float4* arow = s_wr + (32 * wave + j) * ld4 + h;
-    const int g0 = k0 >> 3, nch = (kw + 7) >> 3;
-    for (int c = 0; c < nch; ++c) {
-      load_b(bn, min(g0 + c + 1, nch_all - 1));  // next chunk (past the end: the last again, unused)
-      const float4 a = arow[2 * c];
+  };
+  const float4* arow = s_wr + (32 * wave + j) * ld4 + h;
+  auto compute = [&](const float4* b, int g) {
+    const float4 a = arow[2 * (g & 3)];
 #pragma unroll
-      for (int bb = 0; bb < kR32Boxes; ++bb) {
-        acc[bb] = mfma32(a.x, bc[bb].x, acc[bb]);
-        acc[bb] = mfma32(a.y, bc[bb].y, acc[bb]);
-        acc[bb] = mfma32(a.z, bc[bb].z, acc[bb]);
-        acc[bb] = mfma32(a.w, bc[bb].w, acc[bb]);
-      }
-#pragma unroll
-      for (int bb = 0; bb < kR32Boxes; ++bb) bc[bb] = bn[bb];
+    for (int bb = 0; bb < kR32Boxes; ++bb) {
+      acc[bb] = mfma32(a.x, b[bb].x, acc[bb]);
+      acc[bb] = mfma32(a.y, b[bb].y, acc[bb]);
+      acc[bb] = mfma32(a.z, b[bb].z, acc[bb]);
+      acc[bb] = mfma32(a.w, b[bb].w, acc[bb]);
     }
+  };
+  float4 bA[kR32Boxes], bB[kR32Boxes];
+  load_b(bA, 0);
+  int g = 0;
+  for (; g + 1 < nch_all; g += 2) {
+    if ((g & 3) == 0) stage(g >> 2);
+    load_b(bB, g + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(bA, g);
+    __builtin_amdgcn_sched_barrier(0);
+    load_b(bA, g + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(bB, g + 1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (g < nch_all) {
+    if ((g & 3) == 0) stage(g >> 2);
+    compute(bA, g);
   }
   const int ob = o_base + 32 * wave;
 #pragma unroll

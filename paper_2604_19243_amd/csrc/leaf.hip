@@ -4,6 +4,8 @@
 // (32 right-hand sides on the matrix cores), and the derivative's combination.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "kernels.hpp"
 #include "mfma.hpp"
 
@@ -837,9 +839,48 @@ __global__ __launch_bounds__(256) void k_leaf_multi(const float4* __restrict__ p
 // operand Q[j + h][i] (right-hand side i, 32 consecutive charges per source);
 // the accumulator holds D[8 (v / 4) + 4 h + v % 4][i], 16 targets of right-hand
 // side i per lane.  FP32 accumulation per source leaf and per 16 surface points,
-// added into FP64 totals.  Sources past a leaf's end have charge zero;
-// coincident points (only in the target's own leaf) have K = 0.
+// added into FP64 totals.  The U-list steps of all 27 neighbour leaves form one
+// sequence with kR32Ahead steps in flight; a lane past its leaf's end (it reads
+// the leaf's last source again) and coincident points (only in the target's own
+// leaf) have K = 0.
 constexpr int kR32Ahead = 4;  // source steps in flight per lane in k_leaf_r32
+
+// One 2-source step of k_leaf_r32: first source j, range end lim (INT_MIN past
+// the last range: no lane's source counts), the target's own leaf, first step of
+// its range.
+struct LeafStep {
+  int j, lim;
+  bool self, first;
+};
+
+// Wave-uniform position in the non-empty ranges of the 27 neighbours (lane nb of
+// ra / rb holds range nb; bit nb of `left` is set for the non-empty ranges not
+// yet started).  Past the last range it stays on the last source.
+struct LeafCursor {
+  int ra, rb;
+  unsigned long long left;
+  int nb = 0, a = 0, b = 1, j = 0;
+  bool done = false;
+  __device__ __forceinline__ void start_next() {
+    if (left == 0) {
+      done = true;
+      j = b - 1;
+      return;
+    }
+    nb = __builtin_ctzll(left);
+    left &= left - 1;
+    a = __builtin_amdgcn_readlane(ra, nb);
+    b = __builtin_amdgcn_readlane(rb, nb);
+    j = a;
+  }
+  __device__ __forceinline__ void next() {
+    if (done) return;
+    j += 2;
+    if (j >= b) start_next();
+  }
+  __device__ __forceinline__ LeafStep step() const { return {j, done ? INT_MIN : b, nb == 13, !done && j == a}; }
+};
+
 
 __global__ __launch_bounds__(256) void k_leaf_r32(const float4* __restrict__ pts, const float* __restrict__ qs,
                                                   const int* __restrict__ start, const int4* __restrict__ tasks,
@@ -848,6 +889,11 @@ __global__ __launch_bounds__(256) void k_leaf_r32(const float4* __restrict__ pts
                                                   int n, float alpha, const float* __restrict__ d, int ldd,
                                                   long long drs, int far, const int* __restrict__ order,
                                                   float* __restrict__ pot) {
+  __shared__ float s_surf[3 * kMaxLeafSurface];  // the unit surface (far field)
+  if (far) {
+    for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) s_surf[e] = surf[e];
+    __syncthreads();
+  }
   const int t = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (t >= ntasks) return;
   const int lane = threadIdx.x & 63;
@@ -870,53 +916,76 @@ __global__ __launch_bounds__(256) void k_leaf_r32(const float4* __restrict__ pts
   v16f acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  // The U-list sources as one sequence of 2-source steps over the non-empty
+  // neighbour ranges (wave-uniform cursor), kR32Ahead steps in flight: step u of
+  // a group is computed, then its registers take the step kR32Ahead later.
   const NbRange nr = neighbour_ranges(blk, start, g, o, lane);
-  for (int nb = 0; nb < 27; ++nb) {
-    const int a = __builtin_amdgcn_readlane(nr.a, nb), b = __builtin_amdgcn_readlane(nr.b, nb);
-    if (a >= b) continue;
-    const bool self = nb == 13;
-    // this lane's source of a step (2 sources per step) and its charge of
-    // right-hand side i, loaded kR32Ahead steps before its use
-    // (loads clamped to the leaf's last source; a lane past the end gets k = 0)
-    float4 y[kR32Ahead];
-    float q[kR32Ahead];
-    auto fetch = [&](int u, int jstep) {
-      const int js = min(jstep + h, b - 1);
-      y[u] = pts[js];
-      q[u] = qs[js * 32 + i];
-    };
+  LeafCursor cu{nr.a, nr.b, __builtin_amdgcn_ballot_w64(lane < 27 && nr.a < nr.b)};
+  cu.start_next();
+  float4 y[kR32Ahead];
+  float q[kR32Ahead];
+  LeafStep st[kR32Ahead];
+  auto fetch = [&](int u) {
+    const int js = min(cu.j + h, cu.b - 1);
+    y[u] = pts[js];
+    q[u] = qs[js * 32 + i];
+    st[u] = cu.step();
+    cu.next();
+  };
 #pragma unroll
-    for (int u = 0; u < kR32Ahead; ++u) fetch(u, a + 2 * u);
-    for (int j = a; j < b; j += 2 * kR32Ahead) {
+  for (int u = 0; u < kR32Ahead; ++u) fetch(u);
+  do {
 #pragma unroll
-      for (int u = 0; u < kR32Ahead; ++u) {
-        if (j + 2 * u >= b) break;  // wave-uniform
-        const float ex = x.x - y[u].x, ey = x.y - y[u].y, ez = x.z - y[u].z;
-        const float r2 = ex * ex + ey * ey + ez * ez;
-        float k = __builtin_amdgcn_rsqf(r2);
-        if (self) k = r2 > 0.f ? k : 0.f;  // the target itself
-        k = j + 2 * u + h < b ? k : 0.f;
-        acc = mfma32(k, q[u], acc);
-        fetch(u, j + 2 * u + 2 * kR32Ahead);
-      }
+    for (int u = 0; u < kR32Ahead; ++u) {
+      if (st[u].first) flush(acc);
+      const float ex = x.x - y[u].x, ey = x.y - y[u].y, ez = x.z - y[u].z;
+      const float r2 = ex * ex + ey * ey + ez * ez;
+      float k = __builtin_amdgcn_rsqf(r2);
+      if (st[u].self) k = r2 > 0.f ? k : 0.f;  // the target itself
+      k = st[u].j + h < st[u].lim ? k : 0.f;
+      acc = mfma32(k, q[u], acc);
+      fetch(u);
     }
-    flush(acc);
-  }
+  } while (st[0].lim > INT_MIN);
+  flush(acc);
   if (far) {
     const float4 ch = centers[2 * slot], cl = centers[2 * slot + 1];
     const float xx = (x.x - ch.x) - cl.x, xy = (x.y - ch.y) - cl.y, xz = (x.z - ch.z) - cl.z;
     const float sc = alpha * ch.w;
     const float* dl = d + (size_t)i * drs + (size_t)slot * ldd;  // density of right-hand side i
-    for (int m0 = 0; m0 < n; m0 += 16) {
-      for (int m = m0; m < min(m0 + 16, n); m += 2) {
+    // 16 surface points per FP32 partial: their 8 densities per lane are loaded
+    // one group ahead (two register sets taking turns); the surface points come
+    // from LDS.  Steps past n add zero.
+    const int ngrp = (n + 15) / 16;
+    float dA[8], dB[8];
+    auto load_d = [&](float* dv, int c) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) dv[s] = dl[min(16 * c + 2 * s + h, n - 1)];
+    };
+    auto group = [&](const float* dv, int c) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int m = 16 * c + 2 * s;
         const int mm = min(m + h, n - 1);
-        const float fx = xx - sc * surf[3 * mm], fy = xy - sc * surf[3 * mm + 1], fz = xz - sc * surf[3 * mm + 2];
+        const float fx = xx - sc * s_surf[3 * mm], fy = xy - sc * s_surf[3 * mm + 1], fz = xz - sc * s_surf[3 * mm + 2];
         const float k = __builtin_amdgcn_rsqf(fx * fx + fy * fy + fz * fz);
-        const float dm = m + h < n ? dl[mm] : 0.f;
-        acc = mfma32(k, dm, acc);
+        acc = mfma32(k, m + h < n ? dv[s] : 0.f, acc);
       }
       flush(acc);
+    };
+    load_d(dA, 0);
+    int c = 0;
+    for (; c + 1 < ngrp; c += 2) {
+      load_d(dB, c + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      group(dA, c);
+      __builtin_amdgcn_sched_barrier(0);
+      load_d(dA, c + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      group(dB, c + 1);
+      __builtin_amdgcn_sched_barrier(0);
     }
+    if (c < ngrp) group(dA, c);
   }
 #pragma unroll
   for (int v = 0; v < 16; ++v) {

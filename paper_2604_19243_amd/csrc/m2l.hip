@@ -335,8 +335,9 @@ void launch_m2l_gather(const float* cores, long long core_stride, int ldk, const
 //   in the same order, so that each uhat chunk is fetched once for all of them.
 // * Within a run the chunk steps of successive entries form one sequence; two
 //   register sets take turns, so each step's loads are in flight while the
-//   previous step's products run.  The loads are buffer loads (wave-uniform
-//   base in the resource, the lane's offset in a VGPR).
+//   previous step's products run.  The loads are buffer loads (the base of an
+//   operator's row block or of a source box in the resource, so offsets stay
+//   within a few KiB).
 // Operators are in the lane order of k_m2l; uhat is [box][k / 8][32][8], so
 // that lane (j, h) reads B[8c + 4h .. +3][right-hand side j] as one float4 and
 // a wave's read of one chunk is 1 KiB of contiguous memory.  No partial sums:
@@ -354,16 +355,6 @@ __device__ __forceinline__ void wide_store(const v16f& tot, float* chat, long lo
     if (row < ldk)
       *reinterpret_cast<float4*>(out + row) = make_float4(tot[4 * b4], tot[4 * b4 + 1], tot[4 * b4 + 2], tot[4 * b4 + 3]);
   }
-}
-
-// Buffer-resource loads: a wave-uniform base in the resource (an operator's row
-// block or a source box, so offsets stay within a few KiB), the lane's byte
-// offset in a VGPR; 0x00020000 is the raw 32-bit data format word of gfx9.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t wide_rsrc(const float* base) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, 0x7fffffff, 0x00020000);
-}
-__device__ __forceinline__ float4 bload(__amdgpu_buffer_rsrc_t r, int off) {
-  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 
 // Position (entry e, 8-k chunk c) in a run's sequence of chunk steps, with
@@ -402,9 +393,9 @@ struct WideCtx {
 // P: 0 both targets, 1 target 0 only, 2 target 1 only.
 template <int P>
 __device__ __forceinline__ void wide_load(WideRegs& r, const WideCtx& x, int e0, const WideCursor& cu) {
-  r.a = bload(wide_rsrc(x.ablk + (size_t)cu.en.x * x.core_stride), x.oa + 1024 * cu.c);
-  if (P != 2) r.b0 = bload(wide_rsrc(x.uhat + (size_t)cu.en.y * x.box_stride), x.ob + 1024 * cu.c);
-  if (P != 1) r.b1 = bload(wide_rsrc(x.uhat + (size_t)cu.en.z * x.box_stride), x.ob + 1024 * cu.c);
+  r.a = bload(buf_rsrc(x.ablk + (size_t)cu.en.x * x.core_stride), x.oa + 1024 * cu.c);
+  if (P != 2) r.b0 = bload(buf_rsrc(x.uhat + (size_t)cu.en.y * x.box_stride), x.ob + 1024 * cu.c);
+  if (P != 1) r.b1 = bload(buf_rsrc(x.uhat + (size_t)cu.en.z * x.box_stride), x.ob + 1024 * cu.c);
   r.first = cu.c == 0 && (cu.e - e0) % kM2LFlush == 0;
 }
 

@@ -1,4 +1,4 @@
-// Matrix-core helpers shared by the GEMM and M2L kernels (gfx950, wave64).
+// Matrix-core and buffer-load helpers of the GEMM, M2L and leaf kernels (gfx950, wave64).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,6 +15,16 @@ __device__ __forceinline__ v16f mfma32(float a, float b, v16f c) {
 }
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Buffer loads: a wave-uniform base in the resource (SGPRs), the lane's byte
+// offset (below 2^31) in one VGPR instead of a 64-bit address; 0x00020000 is
+// gfx9's raw 32-bit data-format word.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const float* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, 0x7fffffff, 0x00020000);
+}
+__device__ __forceinline__ float4 bload(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
 
 __device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
