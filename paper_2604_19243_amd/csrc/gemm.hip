@@ -156,8 +156,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const float* __restrict__ W, in
 }
 
 // ------------------------------------------------ GEMM, 32 batch entries ---
-// The same product for a batch of exactly 32 (the 32 right-hand sides) and
-// K <= 256, with
+// The same product for a batch of exactly 32 (the 32 right-hand sides), with
 // the batch entries as the 32 columns of v_mfma_f32_32x32x2_f32: per box, the
 // 32 entries' rows of X form the B operand, so that a chunk of W staged in LDS
 // serves 32 x kR32Boxes columns and every X row is fetched once.  A workgroup
@@ -172,10 +171,14 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const float* __restrict__ W, in
 // loads are in flight while the previous chunk's products run (with one set
 // refilled by a copy, the compiler waits for each load before the products).
 // Past K (the upper half of a last 4-k chunk) a lane reads the row's last four
-// values again, which meet zeros of the staged W.
+// values again, which meet zeros of the staged W.  Every kR32Flush chunks (160 k,
+// about one child's n in U2U) the accumulators are added into running totals and
+// restart, so that long K keeps short FP32 chains.
 constexpr int kR32Boxes = 2;
-constexpr int kR32Slab = 32;  // four 8-k chunks: slab boundaries fall on even chunks
+constexpr int kR32Slab = 32;   // four 8-k chunks: slab boundaries fall on even chunks
+constexpr int kR32Flush = 20;  // even, so that flushes fall between chunk pairs
 
+template <bool LONGK>  // K > 8 kR32Flush: running totals (more registers, fewer waves)
 __global__ __launch_bounds__(512) void k_gemm_r32(const float* __restrict__ W, int ldw, const float* __restrict__ X,
                                                   int ldx, const int* __restrict__ xrow, float* __restrict__ Y,
                                                   int ldy, const int* __restrict__ yrow, int nbox, int nout, int K,
@@ -193,11 +196,21 @@ __global__ __launch_bounds__(512) void k_gemm_r32(const float* __restrict__ W, i
     const int b = min(b0 + bb, nbox - 1);
     xp[bb] = X + j * xbs + (size_t)(xrow ? xrow[b] : b) * ldx;
   }
-  v16f acc[kR32Boxes];
+  v16f acc[kR32Boxes], tot[kR32Boxes];
 #pragma unroll
   for (int bb = 0; bb < kR32Boxes; ++bb)
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[bb][e] = 0.f;
+    for (int e = 0; e < 16; ++e) acc[bb][e] = tot[bb][e] = 0.f;
+  auto flush = [&]() {
+    if (!LONGK) return;
+#pragma unroll
+    for (int bb = 0; bb < kR32Boxes; ++bb)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        tot[bb][e] += acc[bb][e];
+        acc[bb][e] = 0.f;
+      }
+  };
   const int nch_all = (K + 7) >> 3;  // 8-k chunks over the whole K (the last may hold 4)
   auto load_b = [&](float4* b, int g) {
     const int k = min(8 * g + 4 * h, K - 4);  // this lane's first k of chunk g
@@ -234,6 +247,7 @@ __global__ __launch_bounds__(512) void k_gemm_r32(const float* __restrict__ W, i
   int g = 0;
   for (; g + 1 < nch_all; g += 2) {
     if ((g & 3) == 0) stage(g >> 2);
+    if (g && g % kR32Flush == 0) flush();
     load_b(bB, g + 1);
     __builtin_amdgcn_sched_barrier(0);
     compute(bA, g);
@@ -247,6 +261,11 @@ __global__ __launch_bounds__(512) void k_gemm_r32(const float* __restrict__ W, i
     if ((g & 3) == 0) stage(g >> 2);
     compute(bA, g);
   }
+  if (LONGK)
+#pragma unroll
+    for (int bb = 0; bb < kR32Boxes; ++bb)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[bb][e] += tot[bb][e];
   const int ob = o_base + 32 * wave;
 #pragma unroll
   for (int bb = 0; bb < kR32Boxes; ++bb) {
@@ -279,16 +298,18 @@ void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int*
                     const int* yrow, int nbox, int nout, int K, float alpha, int beta, hipStream_t s, int batch,
                     long long xbs, long long ybs, int ywide) {
   if (nbox <= 0 || batch <= 0) return;
-  if (batch == 32 && K <= 256) {
-    // (long K keeps k_gemm_nt, whose accumulators add four k per step: its FP32
-    // chains are half as long)
+  if (batch == 32) {
     // row blocks of 32 outputs, at most 8 per workgroup, spread evenly over the row tiles
     const int rb_all = (nout + 31) / 32;
     const int tiles = (rb_all + 7) / 8;
     const int nrb = (rb_all + tiles - 1) / tiles;
-    hipLaunchKernelGGL(k_gemm_r32, dim3((nbox + kR32Boxes - 1) / kR32Boxes, tiles), dim3(64 * nrb),
-                       gemm_r32_lds_bytes(nrb), s, W, ldw, X, ldx, xrow, Y, ldy, yrow, nbox, nout, K, alpha, beta,
-                       xbs, ybs, ywide);
+    const dim3 grid((nbox + kR32Boxes - 1) / kR32Boxes, tiles), block(64 * nrb);
+    if (K > 8 * kR32Flush)
+      hipLaunchKernelGGL(k_gemm_r32<true>, grid, block, gemm_r32_lds_bytes(nrb), s, W, ldw, X, ldx, xrow, Y, ldy, yrow,
+                         nbox, nout, K, alpha, beta, xbs, ybs, ywide);
+    else
+      hipLaunchKernelGGL(k_gemm_r32<false>, grid, block, gemm_r32_lds_bytes(nrb), s, W, ldw, X, ldx, xrow, Y, ldy,
+                         yrow, nbox, nout, K, alpha, beta, xbs, ybs, ywide);
     return;
   }
   const long long tiles64 = (long long)((nbox + 63) / 64) * ((nout + 63) / 64) * batch;
@@ -306,7 +327,10 @@ void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int*
 // Dynamic LDS limit of the 32-entry GEMM on the current device (see
 // configure_kernels).
 hipError_t configure_gemm_kernels() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_r32), hipFuncAttributeMaxDynamicSharedMemorySize,
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_r32<false>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynamicLds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_r32<true>), hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)kMaxDynamicLds);
 }
 

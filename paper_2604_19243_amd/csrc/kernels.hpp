@@ -27,8 +27,8 @@ struct M2LItem {
 };
 
 // batch > 1: the same product for `batch` right-hand sides, X and Y advanced by
-// xbs and ybs floats per right-hand side (batch = 32 and K <= 256: the right-hand
-// sides are the matrix-core columns, k_gemm_r32).
+// xbs and ybs floats per right-hand side (batch = 32: the right-hand sides are the
+// matrix-core columns, k_gemm_r32).
 // ywide: write Y in the 32-right-hand-side lane order of k_m2l_wide ([row][nout / 8][32][8],
 // batch index = right-hand side; ybs unused), nout a multiple of 8 and batch = 32.
 void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int* xrow, float* Y, int ldy,
