@@ -171,15 +171,14 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const float* __restrict__ W, in
 // loads are in flight while the previous chunk's products run (with one set
 // refilled by a copy, the compiler waits for each load before the products).
 // Past K (the upper half of a last 4-k chunk) a lane reads the row's last four
-// values again, which meet zeros of the staged W.  Every kR32Flush chunks (160 k,
-// about one child's n in U2U) the accumulators are added into running totals and
-// restart, so that long K keeps short FP32 chains.
+// values again, which meet zeros of the staged W.  At each slab the accumulators
+// are added into running totals and restart, so that the FP32 chains are 16
+// products long whatever K (the 16x16x4 kernel adds four k per step over the
+// whole K); the totals' registers hold the kernel to five waves per SIMD.
 constexpr int kR32Boxes = 2;
-constexpr int kR32Slab = 32;   // four 8-k chunks: slab boundaries fall on even chunks
-constexpr int kR32Flush = 20;  // even, so that flushes fall between chunk pairs
+constexpr int kR32Slab = 32;  // four 8-k chunks: slab boundaries fall on even chunks
 
-template <bool LONGK>  // K > 8 kR32Flush: running totals (more registers, fewer waves)
-__global__ __launch_bounds__(512) void k_gemm_r32(const float* __restrict__ W, int ldw, const float* __restrict__ X,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gemm_r32(const float* __restrict__ W, int ldw, const float* __restrict__ X,
                                                   int ldx, const int* __restrict__ xrow, float* __restrict__ Y,
                                                   int ldy, const int* __restrict__ yrow, int nbox, int nout, int K,
                                                   float alpha, int beta, long long xbs, long long ybs, int ywide) {
@@ -202,7 +201,6 @@ __global__ __launch_bounds__(512) void k_gemm_r32(const float* __restrict__ W, i
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[bb][e] = tot[bb][e] = 0.f;
   auto flush = [&]() {
-    if (!LONGK) return;
 #pragma unroll
     for (int bb = 0; bb < kR32Boxes; ++bb)
 #pragma unroll
@@ -246,8 +244,10 @@ __global__ __launch_bounds__(512) void k_gemm_r32(const float* __restrict__ W, i
   load_b(bA, 0);
   int g = 0;
   for (; g + 1 < nch_all; g += 2) {
-    if ((g & 3) == 0) stage(g >> 2);
-    if (g && g % kR32Flush == 0) flush();
+    if ((g & 3) == 0) {
+      if (g) flush();
+      stage(g >> 2);
+    }
     load_b(bB, g + 1);
     __builtin_amdgcn_sched_barrier(0);
     compute(bA, g);
@@ -258,14 +258,16 @@ __global__ __launch_bounds__(512) void k_gemm_r32(const float* __restrict__ W, i
     __builtin_amdgcn_sched_barrier(0);
   }
   if (g < nch_all) {
-    if ((g & 3) == 0) stage(g >> 2);
+    if ((g & 3) == 0) {
+      if (g) flush();
+      stage(g >> 2);
+    }
     compute(bA, g);
   }
-  if (LONGK)
 #pragma unroll
-    for (int bb = 0; bb < kR32Boxes; ++bb)
+  for (int bb = 0; bb < kR32Boxes; ++bb)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) acc[bb][e] += tot[bb][e];
+    for (int e = 0; e < 16; ++e) acc[bb][e] += tot[bb][e];
   const int ob = o_base + 32 * wave;
 #pragma unroll
   for (int bb = 0; bb < kR32Boxes; ++bb) {
@@ -303,13 +305,9 @@ void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int*
     const int rb_all = (nout + 31) / 32;
     const int tiles = (rb_all + 7) / 8;
     const int nrb = (rb_all + tiles - 1) / tiles;
-    const dim3 grid((nbox + kR32Boxes - 1) / kR32Boxes, tiles), block(64 * nrb);
-    if (K > 8 * kR32Flush)
-      hipLaunchKernelGGL(k_gemm_r32<true>, grid, block, gemm_r32_lds_bytes(nrb), s, W, ldw, X, ldx, xrow, Y, ldy, yrow,
-                         nbox, nout, K, alpha, beta, xbs, ybs, ywide);
-    else
-      hipLaunchKernelGGL(k_gemm_r32<false>, grid, block, gemm_r32_lds_bytes(nrb), s, W, ldw, X, ldx, xrow, Y, ldy,
-                         yrow, nbox, nout, K, alpha, beta, xbs, ybs, ywide);
+    hipLaunchKernelGGL(k_gemm_r32, dim3((nbox + kR32Boxes - 1) / kR32Boxes, tiles), dim3(64 * nrb),
+                       gemm_r32_lds_bytes(nrb), s, W, ldw, X, ldx, xrow, Y, ldy, yrow, nbox, nout, K, alpha, beta,
+                       xbs, ybs, ywide);
     return;
   }
   const long long tiles64 = (long long)((nbox + 63) / 64) * ((nout + 63) / 64) * batch;
@@ -327,10 +325,7 @@ void launch_gemm_nt(const float* W, int ldw, const float* X, int ldx, const int*
 // Dynamic LDS limit of the 32-entry GEMM on the current device (see
 // configure_kernels).
 hipError_t configure_gemm_kernels() {
-  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_r32<false>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynamicLds);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_r32<true>), hipFuncAttributeMaxDynamicSharedMemorySize,
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_r32), hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)kMaxDynamicLds);
 }
 

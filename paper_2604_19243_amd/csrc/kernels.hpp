@@ -100,8 +100,9 @@ bool launch_leaf_queue(int mode, const float4* pts, const int* start, const int4
                        float alpha, const float* d, int ldd, int far, const int* order, float* pot, float* grad,
                        float4* near, hipStream_t s);
 
-// Multi-RHS leaf kernels (R = 2, 4, 8, 16, 32; potentials only).  qs: sorted
-// charges [N][R].  q: check fields [R][leaf slots][ldq], qrs = leaf slots * ldq.
+// Multi-RHS leaf kernels (R = 2, 4, 8, 16, 32; potentials only; R = 32 on the
+// matrix cores: k_p2m_r32, k_leaf_r32).  qs: sorted charges [N][R].  q: check
+// fields [R][leaf slots][ldq], qrs = leaf slots * ldq.
 // tasks: (leaf slot, first point offset in the leaf, point count, 0), at most
 // kMultiTile(R) points.
 // d: leaf-level downward densities, slot row `slot` at d + slot * ldd, right-hand

@@ -4,6 +4,7 @@
 // (32 right-hand sides on the matrix cores), and the derivative's combination.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 
 #include "kernels.hpp"
@@ -686,6 +687,109 @@ __global__ __launch_bounds__(256) void k_p2m_multi(const float4* __restrict__ pt
   }
 }
 
+// S2U first half for 32 right-hand sides on the matrix cores: per leaf (one
+// wave) the check field Q[m][r] = sum over sources s of K(p_m, y_s) C[s][r] is a
+// product of the kernel matrix with the leaf's 32-column charge block, two
+// sources per v_mfma_f32_32x32x2_f32 step.  Lane (i, h) = (l % 32, l / 32)
+// computes K(p_{32 b + i}, y_{j+h}) for NB blocks b of 32 check points (the A
+// operands) and loads C[j+h][i] (the B operand); the accumulator of block b
+// holds Q[32 b + 8 (v / 4) + 4 h + v % 4][r = i].  Check points past n repeat
+// the last one and store nothing; a source past the leaf's end (the last one
+// again) has K = 0.  The sources' positions and charges are loaded one step
+// ahead, in two register sets that take turns.  FP32 sums over the leaf's
+// sources, as in k_p2m_multi.
+template <int NB>
+__global__ __launch_bounds__(256) void k_p2m_r32(const float4* __restrict__ pts, const float* __restrict__ qs,
+                                                 const int* __restrict__ start, const int* __restrict__ leaves,
+                                                 const float4* __restrict__ centers, const float* __restrict__ surf,
+                                                 int n, float alpha, float* __restrict__ q, int ldq, long long qrs,
+                                                 int nleaves) {
+  __shared__ float s_tile[4][32][36];  // per wave: one block's 32 right-hand sides x 32 check points
+  const int leaf = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (leaf >= nleaves) return;
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 31, h = lane >> 5;
+  float(*tile)[36] = s_tile[threadIdx.x >> 6];
+  const int slot = leaves[leaf];
+  const float4 ch = centers[2 * slot], cl = centers[2 * slot + 1];
+  const float sc = alpha * ch.w;
+  const int s0 = start[slot], s1 = start[slot + 1];
+  const int nsteps = (s1 - s0 + 1) >> 1;
+  struct Step {
+    float4 y;
+    float c;
+  };
+  auto load = [&](Step& s, int t) {
+    const int js = min(s0 + 2 * t + h, s1 - 1);
+    s.y = pts[js];
+    s.c = qs[(size_t)js * 32 + i];
+  };
+  for (int b0 = 0; b0 < n; b0 += 32 * NB) {
+    float px[NB], py[NB], pz[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int mc = min(b0 + 32 * b + i, n - 1);
+      px[b] = sc * surf[3 * mc];
+      py[b] = sc * surf[3 * mc + 1];
+      pz[b] = sc * surf[3 * mc + 2];
+    }
+    v16f acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
+    auto add = [&](const Step& s, int t) {
+      const float yx = (s.y.x - ch.x) - cl.x, yy = (s.y.y - ch.y) - cl.y, yz = (s.y.z - ch.z) - cl.z;
+      const bool live = s0 + 2 * t + h < s1;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const float dx = px[b] - yx, dy = py[b] - yy, dz = pz[b] - yz;
+        const float k = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+        acc[b] = mfma32(live ? k : 0.f, s.c, acc[b]);
+      }
+    };
+    if (nsteps > 0) {
+      Step sa, sb;
+      load(sa, 0);
+      int t = 0;
+      for (; t + 1 < nsteps; t += 2) {
+        load(sb, t + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        add(sa, t);
+        __builtin_amdgcn_sched_barrier(0);
+        load(sa, t + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        add(sb, t + 1);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (t < nsteps) add(sa, t);
+    }
+    // Each block goes out through the wave's LDS tile, so that 8 lanes write 128
+    // contiguous bytes of one right-hand side's row.
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        *reinterpret_cast<float4*>(&tile[i][8 * g + 4 * h]) =
+            make_float4(acc[b][4 * g], acc[b][4 * g + 1], acc[b][4 * g + 2], acc[b][4 * g + 3]);
+      const int seg = lane & 7, m = b0 + 32 * b + 4 * seg;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int r = 8 * k + (lane >> 3);
+        const float4 v = *reinterpret_cast<const float4*>(&tile[r][4 * seg]);
+        float* out = q + r * qrs + (size_t)slot * ldq + m;
+        if (m + 3 < n) {
+          *reinterpret_cast<float4*>(out) = v;
+        } else {
+          if (m < n) out[0] = v.x;
+          if (m + 1 < n) out[1] = v.y;
+          if (m + 2 < n) out[2] = v.z;
+        }
+      }
+    }
+  }
+}
+
 bool launch_p2m_multi(int R, const float4* pts, const float* qs, const int* start, const int* leaves,
                       const float4* centers, const float* surf, int n, float alpha, float* q, int ldq, long long qrs,
                       int nleaves, hipStream_t s) {
@@ -696,7 +800,22 @@ bool launch_p2m_multi(int R, const float4* pts, const float* qs, const int* star
     case 4: hipLaunchKernelGGL(k_p2m_multi<4>, grid, block, 0, s, pts, qs, start, leaves, centers, surf, n, alpha, q, ldq, qrs, nleaves); return true;
     case 8: hipLaunchKernelGGL(k_p2m_multi<8>, grid, block, 0, s, pts, qs, start, leaves, centers, surf, n, alpha, q, ldq, qrs, nleaves); return true;
     case 16: hipLaunchKernelGGL(k_p2m_multi<16>, grid, block, 0, s, pts, qs, start, leaves, centers, surf, n, alpha, q, ldq, qrs, nleaves); return true;
-    case 32: hipLaunchKernelGGL(k_p2m_multi<32>, grid, block, 0, s, pts, qs, start, leaves, centers, surf, n, alpha, q, ldq, qrs, nleaves); return true;
+    case 32: {
+      // as many 32-point check blocks per pass as the surface needs, at most five
+      const int nb = std::min(5, (n + 31) / 32);
+#define KIFMM_P2M_R32(NB)                                                                                          \
+  hipLaunchKernelGGL(k_p2m_r32<NB>, grid, block, 0, s, pts, qs, start, leaves, centers, surf, n, alpha, q, ldq, qrs, \
+                     nleaves)
+      switch (nb) {
+        case 1: KIFMM_P2M_R32(1); break;
+        case 2: KIFMM_P2M_R32(2); break;
+        case 3: KIFMM_P2M_R32(3); break;
+        case 4: KIFMM_P2M_R32(4); break;
+        default: KIFMM_P2M_R32(5); break;
+      }
+#undef KIFMM_P2M_R32
+      return true;
+    }
     default: return false;
   }
 }

@@ -33,6 +33,8 @@ def _charges(n, R, seed):
     ("sparse_deep_r16", 2_000, 5, 4, "cube", 16, "fp32", 0),
     ("cube20k_r4_bf16x6", 20_000, 3, 6, "cube", 4, "bf16x6", 0),
     ("sphere_r32_rank94", 30_000, 4, 6, "sphere", 32, "fp32", 94),   # wide M2L, three row blocks
+    ("ragged_r32_p5", 7_777, 4, 5, "cube", 32, "fp32", 0),     # n = 98: four check blocks, a partial float4
+    ("sparse_deep_r32_p4", 2_000, 5, 4, "cube", 32, "fp32", 0),  # n = 56: two check blocks, long U2U chains
 ])
 def test_multi_rhs_parity_with_oracle(name, n, depth, p, dist, R, m2l, rank):
     log(f"multi-RHS parity {name} n={n} depth={depth} p={p} R={R} {m2l} rank={rank}")
