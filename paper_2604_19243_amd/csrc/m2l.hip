@@ -259,7 +259,43 @@ bool launch_m2l(int row_blocks, const float* cores, int core_rows, int ldk, int 
 // and the MFMA columns are the group's targets, so sparse trees, whose blocked
 // items are mostly empty columns, keep full columns.  Operators in the lane
 // order of k_m2l; chat written once per target (no partial sums); accumulators
-// restarted every kM2LFlush entries (short FP32 chains).
+// restarted every kM2LFlush entries (short FP32 chains).  The chunk steps of all
+// entries form one sequence with two register sets taking turns, each step's
+// loads in flight while the previous step's products run.
+// Position (entry e, 8-k chunk c) in a unit's sequence of chunk steps: the
+// entry's core (wave-uniform) and this lane's source row, and the next entry's,
+// loaded when the cursor enters an entry.  Past the end it stays on the last chunk.
+struct GatherCursor {
+  int e, c, end, nch;
+  int core, ncore, src, nsrc;
+  const int* ent_core;
+  const int* ent_src;
+  int j;
+  __device__ __forceinline__ void fetch_next() {
+    const int e2 = min(e + 1, end - 1);
+    ncore = ent_core[e2];
+    nsrc = ent_src[(size_t)e2 * 32 + j];
+  }
+  __device__ __forceinline__ void next() {
+    if (++c == nch) {
+      if (e + 1 < end) {
+        c = 0;
+        ++e;
+        core = ncore;
+        src = nsrc;
+        fetch_next();
+      } else {
+        c = nch - 1;
+      }
+    }
+  }
+};
+
+struct GatherRegs {
+  float4 a, b;
+  bool first;
+};
+
 template <int UPPER>  // as in k_m2l
 __global__ __launch_bounds__(64) void k_m2l_gather(const float* __restrict__ cores, long long core_stride, int nch,
                                                    const int4* __restrict__ units, const int* __restrict__ ent_core,
@@ -268,34 +304,52 @@ __global__ __launch_bounds__(64) void k_m2l_gather(const float* __restrict__ cor
   const int4 u = units[blockIdx.x];  // (group, row block, first entry, end entry)
   const int lane = threadIdx.x;
   const int j = lane & 31, h = lane >> 5;
-  const float* alane = cores + (size_t)u.y * nch * 256 + 4 * lane;
+  const float* ablk = cores + (size_t)u.y * nch * 256;
+  const float* blane = uhat + 4 * h;
   v16f acc, tot;
 #pragma unroll
   for (int e = 0; e < 16; ++e) acc[e] = tot[e] = 0.f;
-  for (int e0 = u.z; e0 < u.w; e0 += kM2LFlush) {
-    const int e1 = min(e0 + kM2LFlush, u.w);
-    for (int e = e0; e < e1; ++e) {
-      const float* ap = alane + (size_t)ent_core[e] * core_stride;
-      const float* bp = uhat + (size_t)ent_src[(size_t)e * 32 + j] * ldk + 4 * h;
-      float4 a = *reinterpret_cast<const float4*>(ap);
-      float4 b = *reinterpret_cast<const float4*>(bp);
-      for (int c = 0; c < nch; ++c) {
-        const int cn = min(c + 1, nch - 1);  // next chunk (the last one repeats, unused)
-        const float4 an = *reinterpret_cast<const float4*>(ap + 256 * cn);
-        const float4 bn = *reinterpret_cast<const float4*>(bp + 8 * cn);
-        acc = mfma32(a.x, b.x, acc);
-        acc = mfma32(a.y, b.y, acc);
-        acc = mfma32(a.z, b.z, acc);
-        acc = mfma32(a.w, b.w, acc);
-        a = an;
-        b = bn;
-      }
-    }
+  if (u.z < u.w) {
+    GatherCursor cu{u.z, 0, u.w, nch, ent_core[u.z], 0, ent_src[(size_t)u.z * 32 + j], 0, ent_core, ent_src, j};
+    cu.fetch_next();
+    auto load = [&](GatherRegs& r) {
+      r.a = bload(buf_rsrc(ablk + (size_t)cu.core * core_stride), 16 * lane + 1024 * cu.c);
+      r.b = *reinterpret_cast<const float4*>(blane + (size_t)cu.src * ldk + 8 * cu.c);
+      r.first = cu.c == 0 && (cu.e - u.z) % kM2LFlush == 0;
+    };
+    auto compute = [&](const GatherRegs& r) {
+      if (r.first) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      tot[e] += acc[e];
-      acc[e] = 0.f;
+        for (int e = 0; e < 16; ++e) {
+          tot[e] += acc[e];
+          acc[e] = 0.f;
+        }
+      }
+      acc = mfma32(r.a.x, r.b.x, acc);
+      acc = mfma32(r.a.y, r.b.y, acc);
+      acc = mfma32(r.a.z, r.b.z, acc);
+      acc = mfma32(r.a.w, r.b.w, acc);
+    };
+    const int nv = (u.w - u.z) * nch;
+    GatherRegs r0, r1;
+    load(r0);
+    cu.next();
+    int v = 0;
+    for (; v + 1 < nv; v += 2) {
+      load(r1);
+      cu.next();
+      __builtin_amdgcn_sched_barrier(0);
+      compute(r0);
+      __builtin_amdgcn_sched_barrier(0);
+      load(r0);
+      cu.next();
+      __builtin_amdgcn_sched_barrier(0);
+      compute(r1);
+      __builtin_amdgcn_sched_barrier(0);
     }
+    if (v < nv) compute(r0);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) tot[e] += acc[e];
   }
   const int tgt = grp_tgt[(size_t)u.x * 32 + j];
   if (tgt < 0) return;
