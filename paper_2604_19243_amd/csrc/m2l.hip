@@ -76,12 +76,13 @@ struct M2LCursor {
   }
 };
 
-// Operands of the cursor's chunk.  alane: this lane's float4 of the wave's row
-// block in the slab's first chunk; bq[nb]: the float4 index of its target's
-// staged row plus h.
-__device__ __forceinline__ void m2l_load(M2LRegs& r, const float* __restrict__ alane, const int* bq,
+// Operands of the cursor's chunk.  ablk: the wave's row block of the operators
+// in the slab's first chunk (wave-uniform: a buffer load's base, the lane's
+// float4 at byte 16 lane); bq[nb]: the float4 index of its target's staged row
+// plus h.
+__device__ __forceinline__ void m2l_load(M2LRegs& r, const float* __restrict__ ablk, const int* bq,
                                          const M2LCursor& cu) {
-  r.a = *reinterpret_cast<const float4*>(alane + cu.aoff + 256 * cu.c);
+  r.a = bload(buf_rsrc(ablk + cu.aoff), 16 * (int)(threadIdx.x & 63) + 1024 * cu.c);
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) r.b[nb] = s_m2l[bq[nb] + cu.sh + 2 * cu.c];
   r.first = cu.c == 0 && cu.j % kM2LFlush == 0;
@@ -110,21 +111,21 @@ __device__ __forceinline__ void m2l_compute(const M2LRegs& r, v16f* acc, v16f* t
 }
 
 // All offsets of the item over one slab of nch chunks, with two register sets.
-__device__ __forceinline__ void m2l_slab(v16f* acc, v16f* tot, const float* alane, size_t core_stride, int po_reg,
+__device__ __forceinline__ void m2l_slab(v16f* acc, v16f* tot, const float* ablk, size_t core_stride, int po_reg,
                                          int noffs, const int* bq, int nch, int ld4) {
   const int nv = noffs * nch;
   M2LCursor cu{0, 0, nch, noffs, ld4, po_reg, core_stride, 0, 0};
   cu.set_offset();
   M2LRegs r0, r1;
-  m2l_load(r0, alane, bq, cu);
+  m2l_load(r0, ablk, bq, cu);
   cu.next();
   for (int v = 0; v < nv; v += 2) {
-    m2l_load(r1, alane, bq, cu);
+    m2l_load(r1, ablk, bq, cu);
     cu.next();
     __builtin_amdgcn_sched_barrier(0);
     m2l_compute(r0, acc, tot);
     __builtin_amdgcn_sched_barrier(0);
-    m2l_load(r0, alane, bq, cu);
+    m2l_load(r0, ablk, bq, cu);
     cu.next();
     __builtin_amdgcn_sched_barrier(0);
     if (v + 1 < nv) m2l_compute(r1, acc, tot);
@@ -195,8 +196,8 @@ __global__ __launch_bounds__(512) void k_m2l(const float* __restrict__ cores, in
     for (int e = 0; e < 16; ++e) acc[nb][e] = tot[nb][e] = 0.f;
   // offset table of the item in one VGPR (lane j holds entry j), read with readlane
   const int po_reg = pair_offs[it.pair * 27 + min(lane, 26)];
-  // this lane's float4 in the wave's row block of the lane-ordered operators
-  const float* ablk = cores + (size_t)wave * 32 * ldk + 4 * lane;
+  // the wave's row block of the lane-ordered operators (buffer-load base)
+  const float* ablk = cores + (size_t)__builtin_amdgcn_readfirstlane(wave) * 32 * ldk;
   const size_t core_stride = (size_t)core_rows * ldk;
   __shared__ int s_src[216];
   m2l_load_src(s_src, src_blk + it.src_base);
@@ -592,11 +593,14 @@ extern __shared__ uint4 s_m2lb[];
 constexpr int kM2LSlabB = 32;  // k per LDS slab (two chunks); row stride 8 NP / 2 + 1 units, odd
 
 template <int NP>
-__device__ __forceinline__ void m2lb_load(M2LRegsB<NP>& r, const uint4* __restrict__ alane, const int* bq,
+__device__ __forceinline__ void m2lb_load(M2LRegsB<NP>& r, const uint4* __restrict__ ablk, const int* bq,
                                           const M2LCursor& cu) {
-  const uint4* a = alane + cu.aoff + 64 * NP * cu.c;
+  // ablk: the wave's row block in the slab's first chunk (a buffer load's base)
+  const __amdgpu_buffer_rsrc_t ra = buf_rsrc(reinterpret_cast<const float*>(ablk + cu.aoff));
+  const int oa = 16 * ((int)(threadIdx.x & 63) + 64 * NP * cu.c);
 #pragma unroll
-  for (int p = 0; p < NP; ++p) r.a[p] = a[64 * p];
+  for (int p = 0; p < NP; ++p)
+    r.a[p] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(ra, oa + 1024 * p, 0, 0));
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
@@ -622,21 +626,21 @@ __device__ __forceinline__ void m2lb_compute(const M2LRegsB<NP>& r, v16f* acc, v
 
 // All offsets of the item over one slab of nch chunks, with two register sets.
 template <int NP>
-__device__ __forceinline__ void m2lb_slab(v16f* acc, v16f* tot, const uint4* alane, size_t core_stride, int po_reg,
+__device__ __forceinline__ void m2lb_slab(v16f* acc, v16f* tot, const uint4* ablk, size_t core_stride, int po_reg,
                                           int noffs, const int* bq, int nch, int ld16) {
   const int nv = noffs * nch;
   M2LCursor cu{0, 0, nch, noffs, ld16, po_reg, core_stride, 0, 0};
   cu.set_offset();
   M2LRegsB<NP> r0, r1;
-  m2lb_load<NP>(r0, alane, bq, cu);
+  m2lb_load<NP>(r0, ablk, bq, cu);
   cu.next();
   for (int v = 0; v < nv; v += 2) {
-    m2lb_load<NP>(r1, alane, bq, cu);
+    m2lb_load<NP>(r1, ablk, bq, cu);
     cu.next();
     __builtin_amdgcn_sched_barrier(0);
     m2lb_compute<NP>(r0, acc, tot);
     __builtin_amdgcn_sched_barrier(0);
-    m2lb_load<NP>(r0, alane, bq, cu);
+    m2lb_load<NP>(r0, ablk, bq, cu);
     cu.next();
     __builtin_amdgcn_sched_barrier(0);
     if (v + 1 < nv) m2lb_compute<NP>(r1, acc, tot);
@@ -701,8 +705,8 @@ __global__ __launch_bounds__(512) void k_m2l_bf16(const uint4* __restrict__ core
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[nb][e] = tot[nb][e] = 0.f;
   const int po_reg = pair_offs[it.pair * 27 + min(lane, 26)];
-  // this lane's piece-0 unit in the wave's row block of the lane-ordered operators
-  const uint4* ablk = cores + (size_t)wave * nchunk * 64 * NP + lane;
+  // the wave's row block of the lane-ordered operators (buffer-load base)
+  const uint4* ablk = cores + (size_t)__builtin_amdgcn_readfirstlane(wave) * nchunk * 64 * NP;
   __shared__ int s_src[216];
   m2l_load_src(s_src, src_blk + it.src_base);
 
