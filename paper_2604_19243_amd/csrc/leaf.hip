@@ -292,9 +292,18 @@ __global__ __launch_bounds__(kP2PMaxThreads) void k_p2p(const float4* __restrict
   __syncthreads();
 
   const int t0 = s_cs[0], t1 = s_cs[group_slots];
+  const int lane = tid & 63;
   for (int tb = t0; tb < t1; tb += (int)blockDim.x) {
-    const int ti = tb + tid;
-    if (ti >= t1) break;
+    const int wb = tb + (tid & ~63);  // the wave's first target
+    if (wb >= t1) break;              // the whole wave leaves
+    const int nt = min(64, t1 - wb);  // the wave's targets
+    // A wave with at most 32 targets (the last of a parent) gives each target k
+    // lanes, each summing a share of the nine runs (parts [9q/k, 9(q+1)/k)); the
+    // shares are added in part order below.  Full waves keep k = 1.
+    const int k = (!kNear || !in_lds || nt > 32) ? 1 : nt > 21 ? 2 : nt > 7 ? 3 : 9;
+    const int part = lane / nt;
+    const int ti = wb + (lane - part * nt);  // a target of this wave for every lane
+    const bool act = part < k;
     int o = 0;
     while (o + 1 < group_slots && s_cs[o + 1] <= ti) ++o;
     const float4 x = pts[ti];
@@ -307,17 +316,37 @@ __global__ __launch_bounds__(kP2PMaxThreads) void k_p2p(const float4* __restrict
       // x-fastest block order, so their staged sources form one run: nine runs
       // per target.  The run holding the target's own leaf tests r > 0.
       Sum4 acc;
-      for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy) {
-          const int e0 = (bx - 1) + 4 * (by + dy) + 16 * (bz + dz);
-          const bool own = (dy == 0) & (dz == 0);
-          if (in_lds) {
+      if (in_lds && k == 1) {
+        // (lanes past the wave's targets repeat a target's sums; they are dropped)
+        for (int dz = -1; dz <= 1; ++dz)
+          for (int dy = -1; dy <= 1; ++dy) {
+            const int e0 = (bx - 1) + 4 * (by + dy) + 16 * (bz + dz);
             const int a = s_off[e0], b = s_off[e0 + 3];  // b - a is a multiple of 4
-            if (own)
+            if ((dy == 0) & (dz == 0))
               p2p_run<true>(s_src, a, b, x, acc);
             else
               p2p_run<false>(s_src, a, b, x, acc);
-          } else {
+          }
+      } else if (in_lds) {
+        // runs r = 3 (dz + 1) + (dy + 1) of part q, every pair testing r > 0
+        const int r0 = act ? 9 * part / k : 0, r1 = act ? 9 * (part + 1) / k : 0;
+        for (int r = r0; r < r1; ++r) {
+          const int dz = r / 3 - 1, dy = r - 3 * (r / 3) - 1;
+          const int e0 = (bx - 1) + 4 * (by + dy) + 16 * (bz + dz);
+          p2p_run<true>(s_src, s_off[e0], s_off[e0 + 3], x, acc);
+        }
+        const double p0 = acc.phi, x0 = acc.gx, y0 = acc.gy, z0 = acc.gz;
+        for (int q = 1; q < k; ++q) {
+          const int from = lane + q * nt;  // part q of this lane's target (lanes of part 0)
+          acc.add(__shfl(p0, from), __shfl(x0, from), __shfl(y0, from), __shfl(z0, from));
+        }
+      } else if (act) {
+#pragma unroll 1
+        for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll 1
+          for (int dy = -1; dy <= 1; ++dy) {
+            const int e0 = (bx - 1) + 4 * (by + dy) + 16 * (bz + dz);
+            const bool own = (dy == 0) & (dz == 0);
             for (int dx = 0; dx < 3; ++dx) {
               const int slot = s_slot[e0 + dx];
               if (slot < 0) continue;
@@ -333,18 +362,19 @@ __global__ __launch_bounds__(kP2PMaxThreads) void k_p2p(const float4* __restrict
               }
             }
           }
-        }
+      }
       aphi = acc.phi;
       agx = acc.gx;
       agy = acc.gy;
       agz = acc.gz;
-    } else {
+    } else if (act) {
       const float4 v = near[ti];
       aphi = v.x;
       agx = v.y;
       agy = v.z;
       agz = v.w;
     }
+    if (part != 0) continue;  // the other parts' sums are in part 0's lanes
     if (kFar && far) {
       const float4 ch = centers[2 * (c0 + o)], cl = centers[2 * (c0 + o) + 1];
       const float xx = (x.x - ch.x) - cl.x, xy = (x.y - ch.y) - cl.y, xz = (x.z - ch.z) - cl.z;
