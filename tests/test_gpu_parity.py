@@ -285,6 +285,38 @@ def test_leaf_work_queue_matches_per_parent_kernel(name, n, depth, p, dist, seri
     assert_parity("grad (queue)", out["queue"][1], rg, leaf_groups(t), TOL)
 
 
+@pytest.mark.parametrize("per_parent,serial", [(5, False), (5, True), (15, False), (15, True),
+                                               (28, False), (28, True)])
+def test_short_waves_split_over_lanes(per_parent, serial):
+    # A wave of the per-parent leaf kernel holding nt <= 32 targets gives each target 2, 3 or
+    # 9 lanes (nt <= 32, 21, 7), each summing a share of the target's nine source runs, the
+    # shares added in a fixed order.  Depth 3 (64 parents) with about `per_parent` points per
+    # parent: nearly every parent is one such wave.  Against the oracle, and the same bits at
+    # 256 and 320 threads (near field alone and then the far field, or fused when serial).
+    n = 64 * per_parent
+    log(f"short waves n={n} serial={serial}")
+    x = workloads.points("cube", n, 4600 + n)
+    s = workloads.charges("normal", n, 4700 + n)
+    out = {}
+    for threads, fl in ((320, kifmm.KIFMM_LEAF_THREADS_320), (256, kifmm.KIFMM_LEAF_THREADS_256)):
+        phi, g, f = gpu_evaluate(x, s, 3, 5, UNIT, serial=serial,
+                                 flags=fl | kifmm.KIFMM_LEAF_BLOCKS | kifmm.KIFMM_NO_AUTOTUNE)
+        st = kifmm.kifmm_plan_get_stats(f.plan)
+        f.close()
+        assert st["p2p_threads"] == threads and st["leaf_queue"] == 0
+        out[threads] = (phi, g)
+    np.testing.assert_array_equal(out[256][0], out[320][0])
+    np.testing.assert_array_equal(out[256][1], out[320][1])
+    rphi, rg, t, _ = oracle_evaluate(x, s, 3, 5, UNIT)
+    per_parent_targets = {}
+    for leaf, idx in t.leaf_points.items():
+        key = tuple(int(v) // 2 for v in leaf)
+        per_parent_targets[key] = per_parent_targets.get(key, 0) + len(idx)
+    assert any(0 < c % 64 <= 32 for c in per_parent_targets.values())   # split waves occur
+    assert_parity("phi", out[320][0], rphi, leaf_groups(t), TOL)
+    assert_parity("grad", out[320][1], rg, leaf_groups(t), TOL)
+
+
 def test_device_tree_build_and_plan_on_a_stream():
     # The tree built from device points (copied on a stream), the plan created on that
     # stream and evaluated on it, with non-default surface radii; against the oracle with
